@@ -1,0 +1,208 @@
+/*
+ * tomo.h - C ABI of the MI355X sparse Fubini-Radon tomography library (libtomo.so).
+ *
+ * The operator is the paper's Fourier-slice ("Fubini-Radon") factorisation of
+ * the parallel-beam Radon transform (Sec. 2.2 Eq. (1), Sec. 3 Eq. (2)):
+ *
+ *     A   = F1D^-1 . S^dagger . F2D . diag(k*)        (project,  Radon)
+ *     A^T = diag(k*) . F2D^H . S . F1D^-H             (backproject, exact transpose)
+ *     FBP = (pi / n_theta) . diag(k*) . F2D^H . S . D . F1D^-H      (iRadon)
+ *
+ * where S (M x N) is the sparse polar-to-Cartesian gridding matrix built from a
+ * Kaiser-Bessel window of width k_w (Sec. 3, Fig. 3), stored twice as CSR: once
+ * with polar rows (S^dagger, forward) and once with Cartesian rows (S, adjoint),
+ * so that neither direction needs atomics (Sec. 3.1: the matrix and its
+ * transpose are stored separately).  Pairs of real slices travel as one complex
+ * slice (Sec. 3.1), the real parts carrying even slices and the imaginary parts
+ * odd slices.
+ *
+ * Conventions for every entry point:
+ *   - Return value: TOMO_OK (0) or a negative tomo_status.  Nothing throws across
+ *     the ABI; tomo_last_error() returns a thread-local message for the last error.
+ *   - Device pointers are caller-owned, float32, contiguous, 256-byte aligned is
+ *     not required but 16-byte alignment is (hipMalloc / torch allocations qualify).
+ *     The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All work is
+ *     enqueued on it; no entry point synchronises except tomo_build_operator,
+ *     tomo_destroy_operator and the first call that creates FFT plans or
+ *     solver buffers for a new batch width (these allocate).
+ *   - Precondition failures (NULL pointer, batch < 0 or > max_batch, unsupported
+ *     value type, misaligned pointer) return TOMO_EINVAL before anything is launched.
+ *   - batch == 0 is a no-op returning TOMO_OK.
+ *   - An operator is not thread-safe: calls that share an operator must be ordered
+ *     on one stream (its internal workspace is reused by every call).
+ *
+ * Layouts (row-major, slice index slowest):
+ *   image stack     x[batch][n][n]            pixel (i1, i2) at centred position (i1 - n/2, i2 - n/2)
+ *   sinogram stack  y[batch][n_theta][n_p]    bin b at detector offset b - center
+ *   Cartesian Fourier grid X[G][G][C] complex64, FFT-ordered frequencies, C = ceil(batch/2)
+ *   polar Fourier data     Y[L][n_theta][C] complex64, FFT-ordered radial index k
+ */
+#ifndef TOMO_H
+#define TOMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TOMO_OK = 0,
+  TOMO_EINVAL = -1,       /* bad argument or geometry                                */
+  TOMO_ENOMEM = -2,       /* host or device allocation failed                        */
+  TOMO_EHIP = -3,         /* a HIP runtime call failed                               */
+  TOMO_EFFT = -4,         /* a rocFFT call failed                                    */
+  TOMO_ESTATE = -5,       /* operator built without a device, or value type absent  */
+  TOMO_EUNSUPPORTED = -6  /* valid request this build does not implement             */
+} tomo_status;
+
+/* Storage type of the sparse matrix values; accumulation is always float32. */
+typedef enum { TOMO_VAL_F32 = 0, TOMO_VAL_BF16 = 1, TOMO_VAL_F16 = 2 } tomo_value_type;
+
+/* Bit mask selecting which value arrays tomo_build_operator keeps on the device. */
+#define TOMO_VALUES_F32 (1u << 0)
+#define TOMO_VALUES_BF16 (1u << 1)
+#define TOMO_VALUES_F16 (1u << 2)
+
+/* Diagonal D of Eq. (2) (Sec. 3: Ram-Lak, Shepp-Logan, Hamming), applied per
+ * polar radial index k: D_k = W_k * sum_m h(m) exp(-2 pi i k m / L) with the
+ * band-limited ramp h(0) = 1/4, h(odd m) = -1/(pi m)^2, h(even m) = 0 over the
+ * circle m in [-L/2, L-1-L/2], and window W = 1, sinc(k/L) or
+ * 0.54 + 0.46 cos(2 pi k / L). */
+typedef enum {
+  TOMO_FILTER_NONE = 0,
+  TOMO_FILTER_RAMLAK = 1,
+  TOMO_FILTER_SHEPP = 2,
+  TOMO_FILTER_HAMMING = 3
+} tomo_filter;
+
+/* Experimental parameters of the setup stage (Sec. 3.1: number of pixels, angles,
+ * detector bins, and the choice of filters and kernels). */
+typedef struct {
+  int32_t n;             /* image is n x n pixels (pixel size 1)                          */
+  int32_t n_angles;      /* n_theta                                                        */
+  int32_t n_det;         /* n_p detector bins (bin size 1)                                 */
+  int32_t grid;          /* G = L, Cartesian grid side and polar samples per angle;
+                            0 -> n_det.  Must satisfy grid >= max(n, n_det).               */
+  int32_t kw;            /* kernel width k_w (odd, 1..15); 0 -> 3 (Fig. 3's stencil)       */
+  int32_t max_batch;     /* largest batch (real slices) any call will pass, 1..256         */
+  uint32_t values;       /* TOMO_VALUES_* mask; 0 -> TOMO_VALUES_F32                      */
+  int32_t reserved;      /* must be 0                                                      */
+  double beta;           /* Kaiser-Bessel shape; NaN -> Beatty et al. (2005) rule with
+                            oversampling G / n                                             */
+  double center;         /* rotation-axis bin c; NaN -> floor(n_det / 2) (Sec. 3, c = n_p/2).
+                            Non-integer c returns TOMO_EUNSUPPORTED.                      */
+  const double* angles;  /* host array [n_angles] of radians, or NULL -> a * pi / n_angles */
+} tomo_geometry;
+
+typedef struct tomo_op tomo_op;
+
+typedef struct {
+  int32_t n, n_angles, n_det, grid, kw, max_batch;
+  double beta, center;
+  int64_t n_polar;        /* N = n_angles * grid rows of S^dagger                    */
+  int64_t n_cart;         /* M = grid * grid rows of S                                */
+  int64_t nnz;            /* stored entries (same in both CSR copies)                */
+  int64_t cols_touched;   /* distinct Cartesian points referenced by S^dagger         */
+  int64_t polar_nonempty; /* polar rows with at least one entry                       */
+  int64_t adj_bin_rows[4];/* S rows per bin: <= short, <= medium, long (chunked), 0   */
+  int64_t adj_long_chunks;/* partial-sum chunks used for long S rows                 */
+  int32_t adj_short_max, adj_medium_max, adj_chunk; /* bin thresholds in nnz        */
+  int32_t device;         /* -1 for a host-only operator                             */
+  uint32_t values;        /* value arrays present on the device                      */
+} tomo_op_info;
+
+/* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */
+typedef enum { TOMO_SOLVE_CGLS = 0, TOMO_SOLVE_SIRT_BB = 1 } tomo_solver;
+
+typedef struct {
+  int32_t method;         /* tomo_solver                                                    */
+  int32_t iters;          /* iterations per outer step (>= 0)                               */
+  int32_t refine_outer;   /* R >= 1 outer refinement steps; 1 = plain solve.  With R > 1 each
+                             outer step forms r = b - A_f32 x with float32 values and solves
+                             A_values d = r from zero with `iters` inner iterations.         */
+  int32_t values;         /* tomo_value_type of the (inner) operator                        */
+  int32_t filter;         /* tomo_filter preconditioner D for SIRT_BB (NONE -> HAMMING)     */
+  int32_t use_x0;         /* CGLS only: start from the contents of x instead of zero        */
+  double* out_resnorm;    /* device [batch] float64 or NULL: |b - A x|_2 per slice at exit   */
+} tomo_solve_opts;
+
+/* Build the operator for geometry `g` (Sec. 3.1 setup stage): the CSR matrices S^dagger
+ * and S in float64 on the host (COO -> zero / out-of-band removal -> CSR, Sec. 3.1),
+ * the deapodisation factors, the row bins of S, then the device copies in the
+ * requested value types.  `device` is a HIP device ordinal, or -1 for a host-only
+ * operator (no HIP call is made; only tomo_op_info and tomo_export_* work on it).
+ * The device that is current on entry is current again on return.
+ * On success *out owns all device memory; free it with tomo_destroy_operator.
+ * Errors: TOMO_EINVAL (geometry), TOMO_EUNSUPPORTED (non-integer center),
+ * TOMO_ENOMEM, TOMO_EHIP; *out is left NULL. */
+tomo_status tomo_build_operator(const tomo_geometry* g, int device, tomo_op** out);
+
+/* Forward projection y = A x (Eq. (2), first line) for `batch` slices.
+ * x: device [batch][n][n] f32 (read).  y: device [batch][n_theta][n_det] f32 (written).
+ * `values` picks the matrix value type (must have been built).  x and y must not overlap. */
+tomo_status tomo_project(tomo_op* op, const float* x, float* y, int32_t batch,
+                         int32_t values, void* stream);
+
+/* Back-projection x = A^T y, the exact transpose of tomo_project (D = identity).
+ * y: device [batch][n_theta][n_det] f32 (read).  x: device [batch][n][n] f32 (written). */
+tomo_status tomo_backproject(tomo_op* op, const float* y, float* x, int32_t batch,
+                             int32_t values, void* stream);
+
+/* iRadon / filtered back-projection (Eq. (2), second line), scaled as
+ * x = (pi / n_theta) A^T_D y with D = `filter` (TOMO_FILTER_NONE is rejected). */
+tomo_status tomo_irradon(tomo_op* op, const float* y, float* x, int32_t batch,
+                         int32_t values, int32_t filter, void* stream);
+
+/* The slicing interpolation alone (Sec. 2.2: the key step), as CSR SpMM over
+ * C = ceil(batch/2) complex channels:  Yp = S^dagger Xc.
+ * Xc: device [G*G][C] complex64 (read, FFT-ordered Cartesian Fourier grid).
+ * Yp: device [L*n_theta][C] complex64 (written, row = k_fft * n_theta + angle). */
+tomo_status tomo_slice_fwd(tomo_op* op, const float* Xc, float* Yp, int32_t batch,
+                           int32_t values, void* stream);
+
+/* Adjoint slicing Xc = S diag(D) Yp, row-binned and atomic-free; D per polar
+ * column from `filter` (TOMO_FILTER_NONE -> identity).  Layouts as tomo_slice_fwd. */
+tomo_status tomo_slice_adj(tomo_op* op, const float* Yp, float* Xc, int32_t batch,
+                           int32_t values, int32_t filter, void* stream);
+
+/* Iterative reconstruction of `batch` slices from sinograms b (Sec. 2.1 least
+ * squares; CGLS or SIRT with BB steps, Sec. 3.1).  Per-slice scalars are reduced in
+ * float64 on the device; nothing is copied to the host.
+ * b: device [batch][n_theta][n_det] f32 (read).  x: device [batch][n][n] f32
+ * (written; read first when opts->use_x0).  The first call with a new batch width
+ * allocates the solver's device vectors (kept until tomo_destroy_operator). */
+tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
+                       const tomo_solve_opts* opts, void* stream);
+
+/* Sizes and statistics of a built operator (host only, no synchronisation). */
+tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out);
+
+/* Copy a CSR matrix to host arrays in float64 (test hook; no device access).
+ * which = 0: S^dagger, rows = k_fft * n_theta + angle (N + 1 row pointers),
+ *            columns = j1_fft * G + j2_fft;
+ * which = 1: S, the exact transpose (M + 1 row pointers).
+ * rowptr: int64 [rows + 1]; col: int32 [nnz]; val: float64 [nnz].  Any may be NULL. */
+tomo_status tomo_export_csr(const tomo_op* op, int32_t which, int64_t* rowptr, int32_t* col,
+                            double* val);
+
+/* Copy the separable deapodisation factors kd[n] (k*(i1,i2) = kd[i1] kd[i2]) and,
+ * when filt != NULL, the diagonal D for `filter` per FFT-ordered radial index [L]. */
+tomo_status tomo_export_factors(const tomo_op* op, int32_t filter, double* kd, double* filt);
+
+/* Free everything the operator owns (synchronises its device first).  NULL is a no-op. */
+void tomo_destroy_operator(tomo_op* op);
+
+/* Thread-local message describing the last error in this thread ("" if none). */
+const char* tomo_last_error(void);
+
+/* Library version string, e.g. "1.0.0". */
+const char* tomo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOMO_H */

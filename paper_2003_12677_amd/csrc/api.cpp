@@ -1,0 +1,374 @@
+// C ABI entry points: operator lifecycle, argument checks, and the composed operators of
+// Eq. (2) (Sec. 3): project = F1D^-1 S^dagger F2D k*, backproject = k* F2D^H S F1D^-H.
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+
+namespace tomo {
+const char* last_error_cstr();
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+tomo_status upload(T** dst, const T* src, size_t count) {
+  *dst = nullptr;
+  if (count == 0) return TOMO_OK;
+  if (hipMalloc((void**)dst, count * sizeof(T)) != hipSuccess) {
+    *dst = nullptr;
+    return fail(TOMO_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+  }
+  TOMO_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return TOMO_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+tomo_status upload_csr(const HostCSR& h, uint32_t values, DevCSR* d) {
+  d->rows = h.rows;
+  d->nnz = h.nnz();
+  std::vector<int32_t> rp(h.rowptr.begin(), h.rowptr.end());
+  TOMO_TRY(upload(&d->rowptr, rp.data(), rp.size()));
+  TOMO_TRY(upload(&d->col, h.col.data(), h.col.size()));
+  const size_t nnz = h.val.size();
+  std::vector<float> vf(nnz);
+  for (size_t i = 0; i < nnz; ++i) vf[i] = (float)h.val[i];
+  if (values & TOMO_VALUES_F32) TOMO_TRY(upload((float**)&d->val[TOMO_VAL_F32], vf.data(), nnz));
+  if (values & TOMO_VALUES_BF16) {
+    std::vector<uint16_t> vb(nnz);
+    for (size_t i = 0; i < nnz; ++i) vb[i] = f32_to_bf16_rne(vf[i]);
+    TOMO_TRY(upload((uint16_t**)&d->val[TOMO_VAL_BF16], vb.data(), nnz));
+  }
+  if (values & TOMO_VALUES_F16) {
+    std::vector<_Float16> vh(nnz);
+    for (size_t i = 0; i < nnz; ++i) vh[i] = (_Float16)vf[i];
+    TOMO_TRY(upload((_Float16**)&d->val[TOMO_VAL_F16], vh.data(), nnz));
+  }
+  return TOMO_OK;
+}
+
+void free_csr(DevCSR* d) {
+  dfree(d->rowptr);
+  dfree(d->col);
+  for (auto& v : d->val) dfree(v);
+}
+
+void free_device(tomo_op* op) {
+  destroy_plans(op);
+  free_solver(op);
+  free_csr(&op->fwd);
+  free_csr(&op->adj);
+  dfree(op->bins.short_rows);
+  dfree(op->bins.medium_rows);
+  dfree(op->bins.long_rows);
+  dfree(op->bins.long_chunk_ptr);
+  dfree(op->bins.chunk_beg);
+  dfree(op->bins.chunk_end);
+  dfree(op->kd_dev);
+  for (auto& f : op->filt_dev) dfree(f);
+  dfree(op->X);
+  dfree(op->Y);
+  dfree(op->partials);
+}
+
+tomo_status upload_all(tomo_op* op) {
+  const Geom& g = op->g;
+  TOMO_TRY(upload_csr(op->sdag, g.values, &op->fwd));
+  TOMO_TRY(upload_csr(op->s, g.values, &op->adj));
+  const HostBins& hb = op->hbins;
+  TOMO_TRY(upload(&op->bins.short_rows, hb.short_rows.data(), hb.short_rows.size()));
+  TOMO_TRY(upload(&op->bins.medium_rows, hb.medium_rows.data(), hb.medium_rows.size()));
+  TOMO_TRY(upload(&op->bins.long_rows, hb.long_rows.data(), hb.long_rows.size()));
+  TOMO_TRY(upload(&op->bins.long_chunk_ptr, hb.long_chunk_ptr.data(), hb.long_chunk_ptr.size()));
+  TOMO_TRY(upload(&op->bins.chunk_beg, hb.chunk_beg.data(), hb.chunk_beg.size()));
+  TOMO_TRY(upload(&op->bins.chunk_end, hb.chunk_end.data(), hb.chunk_end.size()));
+  op->bins.n_short = (int64_t)hb.short_rows.size();
+  op->bins.n_medium = (int64_t)hb.medium_rows.size();
+  op->bins.n_long = (int64_t)hb.long_rows.size();
+  op->bins.n_chunks = (int64_t)hb.chunk_beg.size();
+  std::vector<float> kdf(op->kd.begin(), op->kd.end());
+  TOMO_TRY(upload(&op->kd_dev, kdf.data(), kdf.size()));
+  for (int f = TOMO_FILTER_RAMLAK; f <= TOMO_FILTER_HAMMING; ++f) {
+    std::vector<double> d;
+    filter_diagonal(g, f, &d);
+    std::vector<float> df(d.begin(), d.end());
+    TOMO_TRY(upload(&op->filt_dev[f], df.data(), df.size()));
+  }
+  op->cmax = (g.max_batch + 1) / 2;
+  const size_t xb = (size_t)g.G * g.G * op->cmax * sizeof(float2);
+  const size_t yb = (size_t)g.L * g.nt * op->cmax * sizeof(float2);
+  if (hipMalloc((void**)&op->X, xb) != hipSuccess) {
+    op->X = nullptr;
+    return fail(TOMO_ENOMEM, "Cartesian workspace (%zu B)", xb);
+  }
+  if (hipMalloc((void**)&op->Y, yb) != hipSuccess) {
+    op->Y = nullptr;
+    return fail(TOMO_ENOMEM, "polar workspace (%zu B)", yb);
+  }
+  if (op->bins.n_chunks > 0) {
+    const size_t pb = (size_t)op->bins.n_chunks * op->cmax * sizeof(float2);
+    if (hipMalloc((void**)&op->partials, pb) != hipSuccess) {
+      op->partials = nullptr;
+      return fail(TOMO_ENOMEM, "long-row partial sums (%zu B)", pb);
+    }
+  }
+  TOMO_HIP(hipDeviceSynchronize());
+  return TOMO_OK;
+}
+
+bool misaligned(const void* p, size_t a) { return ((uintptr_t)p) % a != 0; }
+
+tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int32_t batch,
+                        int32_t values) {
+  if (!op) return fail(TOMO_EINVAL, "operator is NULL");
+  if (op->device < 0) return fail(TOMO_ESTATE, "operator was built without a device");
+  if (batch < 0 || batch > op->g.max_batch)
+    return fail(TOMO_EINVAL, "batch %d outside [0, max_batch=%d]", batch, op->g.max_batch);
+  if (batch > 0 && (!in || !out)) return fail(TOMO_EINVAL, "NULL data pointer");
+  if (batch > 0 && (misaligned(in, 16) || misaligned(out, 16)))
+    return fail(TOMO_EINVAL, "data pointers must be 16-byte aligned");
+  const int C = (batch + 1) / 2;
+  if (C % 2 == 1 && C > 64)
+    return fail(TOMO_EUNSUPPORTED, "odd channel counts above 64 (batch %d) are not supported", batch);
+  if (values < 0 || values > 2) return fail(TOMO_EINVAL, "unknown value type %d", values);
+  if (!(op->values & (1u << values)))
+    return fail(TOMO_ESTATE, "value type %d was not built for this operator", values);
+  return TOMO_OK;
+}
+
+}  // namespace
+
+tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st) {
+  const int C = (B + 1) / 2;
+  FFTPlans* p = nullptr;
+  TOMO_TRY(get_plans(op, C, &p));
+  TOMO_TRY(launch_embed(op, x, op->X, B, st));
+  TOMO_TRY(fft_exec(p->fwd2, p, op->X, st));
+  TOMO_TRY(launch_spmm_fwd(op, op->X, op->Y, C, vt, st));
+  TOMO_TRY(fft_exec(p->inv1, p, op->Y, st));
+  TOMO_TRY(launch_crop_sino(op, op->Y, y, B, 1.0f / (float)op->g.L, st));
+  return TOMO_OK;
+}
+
+tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
+                              float extra_scale, hipStream_t st) {
+  const int C = (B + 1) / 2;
+  FFTPlans* p = nullptr;
+  TOMO_TRY(get_plans(op, C, &p));
+  TOMO_TRY(launch_pad_sino(op, y, op->Y, B, st));
+  TOMO_TRY(fft_exec(p->fwd1, p, op->Y, st));
+  const float* ds = (filter == TOMO_FILTER_NONE) ? nullptr : op->filt_dev[filter];
+  TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
+  TOMO_TRY(fft_exec(p->inv2, p, op->X, st));
+  TOMO_TRY(launch_crop_image(op, op->X, x, B, extra_scale / (float)op->g.L, st));
+  return TOMO_OK;
+}
+
+}  // namespace tomo
+
+using namespace tomo;
+
+extern "C" {
+
+tomo_status tomo_build_operator(const tomo_geometry* gin, int device, tomo_op** out) {
+  clear_error();
+  if (!out) return fail(TOMO_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<tomo_op> op(new (std::nothrow) tomo_op());
+  if (!op) return fail(TOMO_ENOMEM, "host allocation failed");
+  TOMO_TRY(resolve_geometry(gin, &op->g));
+  try {
+    build_sdag(op->g, &op->sdag);
+    transpose_csr(op->sdag, &op->s);
+    build_bins(op->s, op->binp, &op->hbins);
+    deapod_factors(op->g, &op->kd);
+  } catch (const std::bad_alloc&) {
+    return fail(TOMO_ENOMEM, "host allocation failed while building the matrices");
+  }
+  for (double v : op->kd)
+    if (!(v > 0) || !std::isfinite(v))
+      return fail(TOMO_EINVAL, "deapodisation undefined (kernel transform not positive)");
+  for (int64_t r = 0; r < op->s.rows; ++r) op->cols_touched += (op->s.rowptr[r + 1] > op->s.rowptr[r]);
+  for (int64_t r = 0; r < op->sdag.rows; ++r)
+    op->polar_nonempty += (op->sdag.rowptr[r + 1] > op->sdag.rowptr[r]);
+  op->device = device;
+  if (device >= 0) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev)
+      return fail(TOMO_EINVAL, "device %d not available", device);
+    DeviceGuard guard(device);
+    if (guard.err != hipSuccess) return fail(TOMO_EHIP, "hipSetDevice(%d) failed", device);
+    const tomo_status st = upload_all(op.get());
+    if (st != TOMO_OK) {
+      free_device(op.get());
+      return st;
+    }
+    op->values = op->g.values;
+  } else if (device != -1) {
+    return fail(TOMO_EINVAL, "device must be >= 0, or -1 for a host-only operator");
+  }
+  *out = op.release();
+  return TOMO_OK;
+}
+
+tomo_status tomo_project(tomo_op* op, const float* x, float* y, int32_t batch, int32_t values,
+                         void* stream) {
+  clear_error();
+  TOMO_TRY(check_apply(op, x, y, batch, values));
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return apply_project(op, x, y, batch, values, (hipStream_t)stream);
+}
+
+tomo_status tomo_backproject(tomo_op* op, const float* y, float* x, int32_t batch, int32_t values,
+                             void* stream) {
+  clear_error();
+  TOMO_TRY(check_apply(op, y, x, batch, values));
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return apply_backproject(op, y, x, batch, values, TOMO_FILTER_NONE, 1.0f, (hipStream_t)stream);
+}
+
+tomo_status tomo_irradon(tomo_op* op, const float* y, float* x, int32_t batch, int32_t values,
+                         int32_t filter, void* stream) {
+  clear_error();
+  TOMO_TRY(check_apply(op, y, x, batch, values));
+  if (filter < TOMO_FILTER_RAMLAK || filter > TOMO_FILTER_HAMMING)
+    return fail(TOMO_EINVAL, "irradon needs a filter (got %d)", filter);
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return apply_backproject(op, y, x, batch, values, filter, (float)(M_PI / op->g.nt),
+                           (hipStream_t)stream);
+}
+
+tomo_status tomo_slice_fwd(tomo_op* op, const float* Xc, float* Yp, int32_t batch, int32_t values,
+                           void* stream) {
+  clear_error();
+  TOMO_TRY(check_apply(op, Xc, Yp, batch, values));
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return launch_spmm_fwd(op, (const float2*)Xc, (float2*)Yp, (batch + 1) / 2, values,
+                         (hipStream_t)stream);
+}
+
+tomo_status tomo_slice_adj(tomo_op* op, const float* Yp, float* Xc, int32_t batch, int32_t values,
+                           int32_t filter, void* stream) {
+  clear_error();
+  TOMO_TRY(check_apply(op, Yp, Xc, batch, values));
+  if (filter < TOMO_FILTER_NONE || filter > TOMO_FILTER_HAMMING)
+    return fail(TOMO_EINVAL, "unknown filter %d", filter);
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  const float* ds = (filter == TOMO_FILTER_NONE) ? nullptr : op->filt_dev[filter];
+  return launch_spmm_adj(op, (const float2*)Yp, (float2*)Xc, (batch + 1) / 2, values, ds,
+                         (hipStream_t)stream);
+}
+
+tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
+                       const tomo_solve_opts* opts, void* stream) {
+  clear_error();
+  if (!opts) return fail(TOMO_EINVAL, "opts is NULL");
+  TOMO_TRY(check_apply(op, b, x, batch, opts->values));
+  if (opts->method != TOMO_SOLVE_CGLS && opts->method != TOMO_SOLVE_SIRT_BB)
+    return fail(TOMO_EINVAL, "unknown solver %d", opts->method);
+  if (opts->iters < 0 || opts->refine_outer < 1)
+    return fail(TOMO_EINVAL, "iters must be >= 0 and refine_outer >= 1");
+  if (opts->filter < TOMO_FILTER_NONE || opts->filter > TOMO_FILTER_HAMMING)
+    return fail(TOMO_EINVAL, "unknown filter %d", opts->filter);
+  if (opts->method == TOMO_SOLVE_SIRT_BB && (opts->refine_outer != 1 || opts->use_x0))
+    return fail(TOMO_EUNSUPPORTED, "SIRT-BB runs from zero without refinement");
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return run_solve(op, b, x, batch, opts, (hipStream_t)stream);
+}
+
+tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out) {
+  clear_error();
+  if (!op || !out) return fail(TOMO_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  const Geom& g = op->g;
+  out->n = g.n;
+  out->n_angles = g.nt;
+  out->n_det = g.np;
+  out->grid = g.G;
+  out->kw = g.kw;
+  out->max_batch = g.max_batch;
+  out->beta = g.beta;
+  out->center = g.center;
+  out->n_polar = op->sdag.rows;
+  out->n_cart = op->s.rows;
+  out->nnz = op->sdag.nnz();
+  out->cols_touched = op->cols_touched;
+  out->polar_nonempty = op->polar_nonempty;
+  out->adj_bin_rows[0] = (int64_t)op->hbins.short_rows.size();
+  out->adj_bin_rows[1] = (int64_t)op->hbins.medium_rows.size();
+  out->adj_bin_rows[2] = (int64_t)op->hbins.long_rows.size();
+  out->adj_long_chunks = (int64_t)op->hbins.chunk_beg.size();
+  out->adj_short_max = op->binp.short_max;
+  out->adj_medium_max = op->binp.medium_max;
+  out->adj_chunk = op->binp.chunk;
+  out->device = op->device;
+  out->values = op->values;
+  return TOMO_OK;
+}
+
+tomo_status tomo_export_csr(const tomo_op* op, int32_t which, int64_t* rowptr, int32_t* col,
+                            double* val) {
+  clear_error();
+  if (!op) return fail(TOMO_EINVAL, "operator is NULL");
+  if (which != 0 && which != 1) return fail(TOMO_EINVAL, "which must be 0 or 1");
+  const HostCSR& m = which == 0 ? op->sdag : op->s;
+  if (rowptr) std::memcpy(rowptr, m.rowptr.data(), m.rowptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, m.col.data(), m.col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, m.val.data(), m.val.size() * sizeof(double));
+  return TOMO_OK;
+}
+
+tomo_status tomo_export_factors(const tomo_op* op, int32_t filter, double* kd, double* filt) {
+  clear_error();
+  if (!op) return fail(TOMO_EINVAL, "operator is NULL");
+  if (filter < TOMO_FILTER_NONE || filter > TOMO_FILTER_HAMMING)
+    return fail(TOMO_EINVAL, "unknown filter %d", filter);
+  if (kd) std::memcpy(kd, op->kd.data(), op->kd.size() * sizeof(double));
+  if (filt) {
+    std::vector<double> d;
+    filter_diagonal(op->g, filter, &d);
+    std::memcpy(filt, d.data(), d.size() * sizeof(double));
+  }
+  return TOMO_OK;
+}
+
+void tomo_destroy_operator(tomo_op* op) {
+  if (!op) return;
+  if (op->device >= 0) {
+    DeviceGuard guard(op->device);
+    (void)hipDeviceSynchronize();
+    free_device(op);
+  }
+  delete op;
+}
+
+const char* tomo_last_error(void) { return last_error_cstr(); }
+
+const char* tomo_version(void) { return "1.0.0"; }
+
+}  // extern "C"

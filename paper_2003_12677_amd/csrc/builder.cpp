@@ -1,0 +1,286 @@
+// Host-side setup stage (Sec. 3.1): geometry -> gridding matrix S^dagger (polar rows) and its
+// stored transpose S (Cartesian rows) in float64, adjoint row bins, deapodisation and the
+// filter diagonal.  Plain C++17, no HIP calls.
+//
+// Matrix layout chosen for the device path (differs from the paper's ordering, same matrix):
+//   * polar row r = kf * nt + a, where kf = k mod L is the FFT-ordered radial index of the
+//     sample at radius k (in Fourier grid units) on angle theta_a; radial-major rows make the
+//     1D transform along k a plain strided batch and keep an angle's neighbours adjacent;
+//   * Cartesian column / row m = (j1 mod G) * G + (j2 mod G), the FFT-ordered frequency,
+//     so the 2D transform needs no shift.
+//
+// Entries (Sec. 3, Fig. 3): polar point q = k (G/L) (cos theta_a, sin theta_a); window
+// j = rint(q) + s, s in [-h, h]^2, h = (k_w - 1)/2; value K(j1 - q1) K(j2 - q2) with the
+// Kaiser-Bessel kernel K zero at |t| >= k_w / 2.  Zero entries, entries with |j1| or |j2|
+// above ceil(G/2) - 1, and the unpaired radial sample k = -L/2 (even L) are removed, which
+// keeps the composed operator exactly real-to-real so that two real slices can share one
+// complex channel (Sec. 3.1).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace tomo {
+
+namespace {
+thread_local std::string g_last_error;
+
+// I0(x) - 1 from the power series sum_{k>=1} (x^2/4)^k / (k!)^2 (Abramowitz & Stegun 9.6.10);
+// every term is positive, so the sum has no cancellation.
+double bessel_i0_minus_1(double x) {
+  const double y = 0.25 * x * x;
+  double term = 1.0, sum = 0.0;
+  for (int k = 1; k < 1000; ++k) {
+    term *= y / ((double)k * (double)k);
+    sum += term;
+    if (term <= sum * 1e-18) break;
+  }
+  return sum;
+}
+
+inline int64_t mod_pos(int64_t a, int64_t m) {
+  int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+}  // namespace
+
+tomo_status fail(tomo_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+tomo_status resolve_geometry(const tomo_geometry* in, Geom* g) {
+  if (!in) return fail(TOMO_EINVAL, "geometry is NULL");
+  Geom r;
+  r.n = in->n;
+  r.nt = in->n_angles;
+  r.np = in->n_det;
+  if (r.n < 1 || r.nt < 1 || r.np < 1)
+    return fail(TOMO_EINVAL, "n, n_angles and n_det must be positive (got %d, %d, %d)", r.n, r.nt,
+                r.np);
+  r.G = in->grid ? in->grid : r.np;
+  r.L = r.G;
+  if (r.G < r.n || r.G < r.np)
+    return fail(TOMO_EINVAL, "grid %d must be >= max(n=%d, n_det=%d)", r.G, r.n, r.np);
+  if (r.G < 3) return fail(TOMO_EINVAL, "grid must be at least 3");
+  r.kw = in->kw ? in->kw : 3;
+  if (r.kw < 1 || r.kw > 15 || r.kw % 2 == 0)
+    return fail(TOMO_EINVAL, "kernel width kw=%d must be odd and in [1, 15]", r.kw);
+  r.h = (r.kw - 1) / 2;
+  r.max_batch = in->max_batch;
+  if (r.max_batch < 1 || r.max_batch > 256)
+    return fail(TOMO_EINVAL, "max_batch=%d must be in [1, 256]", r.max_batch);
+  if (in->reserved != 0) return fail(TOMO_EINVAL, "reserved field must be 0");
+  r.values = in->values ? in->values : TOMO_VALUES_F32;
+  if (r.values & ~(uint32_t)(TOMO_VALUES_F32 | TOMO_VALUES_BF16 | TOMO_VALUES_F16))
+    return fail(TOMO_EINVAL, "unknown bits in values mask 0x%x", r.values);
+  r.values |= TOMO_VALUES_F32;   // the float32 copy is always kept (refinement residuals)
+  const double sigma = (double)r.G / (double)r.n;
+  if (std::isnan(in->beta)) {
+    // Beatty, Nishimura, Pauly (IEEE TMI 2005), Eq. 5
+    const double w = (double)r.kw;
+    const double arg = (w / sigma) * (w / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8;
+    if (arg <= 0) return fail(TOMO_EINVAL, "default beta undefined for kw=%d, G/n=%g", r.kw, sigma);
+    r.beta = M_PI * std::sqrt(arg);
+  } else {
+    r.beta = in->beta;
+  }
+  if (!(r.beta > 0) || !std::isfinite(r.beta)) return fail(TOMO_EINVAL, "beta must be positive");
+  r.center = std::isnan(in->center) ? (double)(r.np / 2) : in->center;
+  if (!std::isfinite(r.center)) return fail(TOMO_EINVAL, "center must be finite");
+  if (r.center != std::floor(r.center))
+    return fail(TOMO_EUNSUPPORTED, "non-integer rotation-axis bin %g is not supported", r.center);
+  r.cdet = (int)mod_pos((int64_t)r.center, r.L);
+  r.jmax = (r.G + 1) / 2 - 1;
+  r.on = r.n / 2;
+  r.theta.resize(r.nt);
+  for (int a = 0; a < r.nt; ++a) {
+    r.theta[a] = in->angles ? in->angles[a] : (double)a * M_PI / (double)r.nt;
+    if (!std::isfinite(r.theta[a])) return fail(TOMO_EINVAL, "angle %d is not finite", a);
+  }
+  // index ranges must fit the int32 device arrays
+  const double nnz_bound = (double)r.nt * r.L * r.kw * r.kw;
+  if (nnz_bound >= 2147483647.0 || (double)r.G * r.G >= 2147483647.0)
+    return fail(TOMO_EINVAL, "operator too large for 32-bit indices");
+  *g = std::move(r);
+  return TOMO_OK;
+}
+
+double kernel_value(double t, int W, double beta) {
+  const double half = 0.5 * W;
+  if (!(std::fabs(t) < half)) return 0.0;
+  const double u = 2.0 * t / W;
+  const double arg = beta * std::sqrt(std::max(0.0, 1.0 - u * u));
+  return bessel_i0_minus_1(arg) / bessel_i0_minus_1(beta);
+}
+
+void build_sdag(const Geom& g, HostCSR* out) {
+  const int64_t N = (int64_t)g.nt * g.L;
+  const int64_t M = (int64_t)g.G * g.G;
+  const int W = g.kw, h = g.h;
+  const double scale = (double)g.G / (double)g.L;
+  std::vector<double> ct(g.nt), st(g.nt);
+  for (int a = 0; a < g.nt; ++a) {
+    ct[a] = std::cos(g.theta[a]);
+    st[a] = std::sin(g.theta[a]);
+  }
+  out->rows = N;
+  out->cols = M;
+  out->rowptr.assign(N + 1, 0);
+  out->col.clear();
+  out->val.clear();
+  out->col.reserve((size_t)N * W * W);
+  out->val.reserve((size_t)N * W * W);
+  std::vector<std::pair<int32_t, double>> ent;
+  std::vector<double> w1(W), w2(W);
+  std::vector<int64_t> j1s(W), j2s(W);
+  for (int kf = 0; kf < g.L; ++kf) {
+    const bool nyquist = (2 * kf == g.L);
+    const int64_t k = (2 * kf < g.L) ? kf : (int64_t)kf - g.L;
+    for (int a = 0; a < g.nt; ++a) {
+      const int64_t r = (int64_t)kf * g.nt + a;
+      if (!nyquist) {
+        const double q1 = ((double)k * scale) * ct[a];
+        const double q2 = ((double)k * scale) * st[a];
+        const double c1 = std::nearbyint(q1);   // round half to even
+        const double c2 = std::nearbyint(q2);
+        for (int s = -h; s <= h; ++s) {
+          j1s[s + h] = (int64_t)c1 + s;
+          j2s[s + h] = (int64_t)c2 + s;
+          w1[s + h] = kernel_value((double)j1s[s + h] - q1, W, g.beta);
+          w2[s + h] = kernel_value((double)j2s[s + h] - q2, W, g.beta);
+        }
+        ent.clear();
+        for (int s1 = 0; s1 < W; ++s1) {
+          if (std::llabs(j1s[s1]) > g.jmax || w1[s1] == 0.0) continue;
+          for (int s2 = 0; s2 < W; ++s2) {
+            if (std::llabs(j2s[s2]) > g.jmax) continue;
+            const double w = w1[s1] * w2[s2];
+            if (w == 0.0) continue;
+            const int64_t m = mod_pos(j1s[s1], g.G) * g.G + mod_pos(j2s[s2], g.G);
+            ent.emplace_back((int32_t)m, w);
+          }
+        }
+        std::sort(ent.begin(), ent.end(),
+                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                    return x.first < y.first;
+                  });
+        for (auto& e : ent) {
+          out->col.push_back(e.first);
+          out->val.push_back(e.second);
+        }
+      }
+      out->rowptr[r + 1] = (int64_t)out->col.size();
+    }
+  }
+}
+
+void transpose_csr(const HostCSR& a, HostCSR* at) {
+  at->rows = a.cols;
+  at->cols = a.rows;
+  at->rowptr.assign(a.cols + 1, 0);
+  const int64_t nnz = a.nnz();
+  for (int64_t e = 0; e < nnz; ++e) at->rowptr[a.col[e] + 1]++;
+  for (int64_t i = 0; i < a.cols; ++i) at->rowptr[i + 1] += at->rowptr[i];
+  at->col.assign(nnz, 0);
+  at->val.assign(nnz, 0.0);
+  std::vector<int64_t> next(at->rowptr.begin(), at->rowptr.end() - 1);
+  for (int64_t r = 0; r < a.rows; ++r) {
+    for (int64_t e = a.rowptr[r]; e < a.rowptr[r + 1]; ++e) {
+      const int64_t dst = next[a.col[e]]++;
+      at->col[dst] = (int32_t)r;   // rows visited in order: columns come out sorted
+      at->val[dst] = a.val[e];
+    }
+  }
+}
+
+void build_bins(const HostCSR& s, const BinParams& p, HostBins* b) {
+  b->short_rows.clear();
+  b->medium_rows.clear();
+  b->long_rows.clear();
+  b->long_chunk_ptr.assign(1, 0);
+  b->chunk_beg.clear();
+  b->chunk_end.clear();
+  for (int64_t r = 0; r < s.rows; ++r) {
+    const int64_t len = s.rowptr[r + 1] - s.rowptr[r];
+    if (len <= p.short_max) {
+      b->short_rows.push_back((int32_t)r);
+    } else if (len <= p.medium_max) {
+      b->medium_rows.push_back((int32_t)r);
+    } else {
+      b->long_rows.push_back((int32_t)r);
+      for (int64_t e = s.rowptr[r]; e < s.rowptr[r + 1]; e += p.chunk) {
+        b->chunk_beg.push_back((int32_t)e);
+        b->chunk_end.push_back((int32_t)std::min<int64_t>(e + p.chunk, s.rowptr[r + 1]));
+      }
+      b->long_chunk_ptr.push_back((int32_t)b->chunk_beg.size());
+    }
+  }
+}
+
+void deapod_factors(const Geom& g, std::vector<double>* kd) {
+  // kappa(x) = sum_{s=-h..h} K(s) cos(2 pi s x / G), the discrete transform of the kernel taps;
+  // k*(i1, i2) = 1 / (kappa(i1 - n/2) kappa(i2 - n/2)) on the image support (Sec. 3).
+  std::vector<double> taps(g.h + 1);
+  for (int s = 0; s <= g.h; ++s) taps[s] = kernel_value((double)s, g.kw, g.beta);
+  kd->resize(g.n);
+  for (int i = 0; i < g.n; ++i) {
+    const double x = (double)(i - g.on);
+    double kap = taps[0];
+    for (int s = 1; s <= g.h; ++s) kap += 2.0 * taps[s] * std::cos(2.0 * M_PI * s * x / g.G);
+    (*kd)[i] = 1.0 / kap;
+  }
+}
+
+void filter_diagonal(const Geom& g, int filter, std::vector<double>* d) {
+  const int L = g.L;
+  d->assign(L, 1.0);
+  if (filter == TOMO_FILTER_NONE) return;
+  // band-limited ramp h(m) on the circle m in [-L/2, L-1-L/2] (Kak & Slaney 1988)
+  std::vector<double> hm(L, 0.0);
+  const int m0 = -(L / 2);
+  for (int i = 0; i < L; ++i) {
+    const int m = m0 + i;
+    if (m == 0)
+      hm[i] = 0.25;
+    else if (m % 2 != 0)
+      hm[i] = -1.0 / ((M_PI * m) * (M_PI * m));
+  }
+  for (int kf = 0; kf < L; ++kf) {
+    const int k = (2 * kf < L) ? kf : kf - L;
+    double R = 0.0;
+    for (int i = 0; i < L; ++i)
+      if (hm[i] != 0.0) R += hm[i] * std::cos(2.0 * M_PI * (double)k * (double)(m0 + i) / L);
+    double win = 1.0;
+    if (filter == TOMO_FILTER_SHEPP) {
+      const double x = M_PI * (double)k / L;
+      win = (k == 0) ? 1.0 : std::sin(x) / x;
+    } else if (filter == TOMO_FILTER_HAMMING) {
+      win = 0.54 + 0.46 * std::cos(2.0 * M_PI * (double)k / L);
+    }
+    (*d)[kf] = R * win;
+  }
+}
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+}  // namespace tomo

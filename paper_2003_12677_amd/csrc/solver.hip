@@ -1,0 +1,286 @@
+// Iterative reconstruction on the device (Sec. 2.1 least squares; Sec. 3.1 lists CGLS and SIRT
+// with Hamming preconditioning and Barzilai-Borwein steps).  Slices are independent, so every
+// scalar (step lengths, inner products) is per slice: float64 reductions over each slice with a
+// fixed two-level order (bitwise reproducible), stored in device arrays and read by the update
+// kernels, so nothing returns to the host inside the loop.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace tomo {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double w[4];
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) w[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (w[0] + w[1]) + (w[2] + w[3]);
+  return r;
+}
+
+// partial[s][j] = sum over the j-th strided share of slice s of a*b, in float64
+__global__ __launch_bounds__(256) void k_dot_partial(const float* __restrict__ a,
+                                                     const float* __restrict__ b, int64_t len,
+                                                     double* __restrict__ partial) {
+  const int s = blockIdx.y;
+  const float* pa = a + (int64_t)s * len;
+  const float* pb = b + (int64_t)s * len;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
+    acc += (double)pa[i] * (double)pb[i];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[(int64_t)s * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ partial, int nblk,
+                                                   double* __restrict__ out) {
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += partial[(int64_t)s * nblk + i];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) out[s] = t;
+}
+
+// out = sa*ca[s]*a + sb*cb[s]*b per slice (null ca / cb mean 1; null b means no second term);
+// out may be a or b (element-wise in place)
+__global__ __launch_bounds__(256) void k_lincomb(float* out, const float* a,
+                                                 const float* b, const double* __restrict__ ca,
+                                                 const double* __restrict__ cb, double sa, double sb,
+                                                 int64_t len) {
+  const int s = blockIdx.y;
+  const float fa = (float)(sa * (ca ? ca[s] : 1.0));
+  const float fb = (float)(sb * (cb ? cb[s] : 1.0));
+  const int64_t base = (int64_t)s * len;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    float v = fa * a[base + i];
+    if (b) v += fb * b[base + i];
+    out[base + i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill(float* __restrict__ out, float v, int64_t len) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
+    out[i] = v;
+}
+
+// out[s] = den[s] > 0 ? num[s] / den[s] : 0
+__global__ void k_ratio(const double* num, const double* den, double* out, int B) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < B) out[s] = den[s] > 0.0 ? num[s] / den[s] : 0.0;
+}
+
+// Barzilai-Borwein step (BB1) for the gradient recurrence g_{k+1} = g_k - alpha_k h_k with
+// h_k = A^T_D A g_k:  s = -alpha_{k-1} g_{k-1}, y = -alpha_{k-1} h_{k-1} give
+// alpha_k = <s,s>/<s,y> = <g_{k-1},g_{k-1}> / <g_{k-1},h_{k-1}>; alpha_0 is the exact line search
+// <g_0,g_0>/<g_0,h_0>.  A non-positive <s,y> keeps the previous step.
+// state layout per slice: [0] num_k, [1] den_k, [2] num_{k-1}, [3] den_{k-1}, [4] alpha
+__global__ void k_sirt_step(double* num, double* den, double* pnum, double* pden, double* alpha,
+                            int B, int first) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= B) return;
+  if (first) {
+    alpha[s] = den[s] > 0.0 ? num[s] / den[s] : 0.0;
+  } else if (pden[s] > 0.0 && alpha[s] != 0.0) {
+    alpha[s] = pnum[s] / pden[s];
+  }
+  pnum[s] = num[s];
+  pden[s] = den[s];
+}
+
+__global__ void k_sqrt(const double* in, double* out, int B) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < B) out[s] = sqrt(in[s] > 0.0 ? in[s] : 0.0);
+}
+
+inline unsigned grid_for(int64_t len) {
+  int64_t b = (len + 255) / 256;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// scalar slots in SolverBuffers::scal ([16][B] doubles)
+enum { kGamma0 = 0, kGamma1, kDelta, kAlpha, kBeta, kNum, kDen, kPNum, kPDen, kTmp, kSlots };
+
+}  // namespace
+
+tomo_status launch_dot(const float* a, const float* b, int64_t len, int B, double* partial,
+                       double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, B), dim3(256), 0, st, a, b, len, partial);
+  TOMO_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, partial, kDotBlocks, out);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+tomo_status launch_lincomb(float* out, const float* a, const float* b, const double* ca,
+                           const double* cb, double sa, double sb, int64_t len, int B,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for(len), B), dim3(256), 0, st, out, a, b, ca, cb, sa, sb,
+                     len);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+tomo_status launch_fill(float* out, float v, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(len)), dim3(256), 0, st, out, v, len);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+void free_solver(tomo_op* op) {
+  SolverBuffers& b = op->sb;
+  for (float** p : {&b.p, &b.s, &b.d, &b.r, &b.q, &b.rb}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (b.scal) (void)hipFree(b.scal);
+  if (b.partial) (void)hipFree(b.partial);
+  b.scal = b.partial = nullptr;
+  b.B = 0;
+}
+
+namespace {
+
+tomo_status ensure_solver(tomo_op* op) {
+  SolverBuffers& b = op->sb;
+  if (b.B) return TOMO_OK;
+  const Geom& g = op->g;
+  const size_t B = (size_t)g.max_batch;
+  const size_t img = B * g.n * g.n * sizeof(float);
+  const size_t sino = B * g.nt * g.np * sizeof(float);
+  struct Req { void** p; size_t bytes; } req[] = {
+      {(void**)&b.p, img},  {(void**)&b.s, img},  {(void**)&b.d, img},
+      {(void**)&b.r, sino}, {(void**)&b.q, sino}, {(void**)&b.rb, sino},
+      {(void**)&b.scal, kSlots * B * sizeof(double)},
+      {(void**)&b.partial, B * kDotBlocks * sizeof(double)}};
+  for (auto& r : req) {
+    if (hipMalloc(r.p, r.bytes) != hipSuccess) {
+      *r.p = nullptr;
+      free_solver(op);
+      return fail(TOMO_ENOMEM, "solver buffer of %zu bytes", r.bytes);
+    }
+  }
+  b.B = (int)B;
+  return TOMO_OK;
+}
+
+struct Ctx {
+  tomo_op* op;
+  int B;
+  hipStream_t st;
+  int64_t img, sino;
+  double* sc(int slot) const { return op->sb.scal + (int64_t)slot * op->g.max_batch; }
+  tomo_status dot(const float* a, const float* b, int64_t len, int slot) const {
+    return launch_dot(a, b, len, B, op->sb.partial, sc(slot), st);
+  }
+  tomo_status lin(float* out, const float* a, const float* b, const double* ca, const double* cb,
+                  double sa, double sb, int64_t len) const {
+    return launch_lincomb(out, a, b, ca, cb, sa, sb, len, B, st);
+  }
+};
+
+// CGLS on A_vt from x (zero, or x's contents when use_x0) with rhs b; x is updated in place.
+tomo_status cgls(const Ctx& c, const float* b, float* x, int vt, int iters, bool use_x0) {
+  SolverBuffers& w = c.op->sb;
+  if (use_x0) {
+    TOMO_TRY(apply_project(c.op, x, w.q, c.B, vt, c.st));
+    TOMO_TRY(c.lin(w.r, b, w.q, nullptr, nullptr, 1.0, -1.0, c.sino));       // r = b - A x
+  } else {
+    TOMO_TRY(launch_fill(x, 0.f, c.img * c.B, c.st));
+    TOMO_TRY(c.lin(w.r, b, nullptr, nullptr, nullptr, 1.0, 0.0, c.sino));    // r = b
+  }
+  TOMO_TRY(apply_backproject(c.op, w.r, w.s, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));   // s = A^T r
+  TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));     // p = s
+  int cur = kGamma0, nxt = kGamma1;
+  TOMO_TRY(c.dot(w.s, w.s, c.img, cur));                                      // gamma = |s|^2
+  for (int it = 0; it < iters; ++it) {
+    TOMO_TRY(apply_project(c.op, w.p, w.q, c.B, vt, c.st));                  // q = A p
+    TOMO_TRY(c.dot(w.q, w.q, c.sino, kDelta));                                // delta = |q|^2
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
+    TOMO_HIP(hipGetLastError());
+    TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));      // x += alpha p
+    TOMO_TRY(c.lin(w.r, w.r, w.q, nullptr, c.sc(kAlpha), 1.0, -1.0, c.sino));// r -= alpha q
+    TOMO_TRY(apply_backproject(c.op, w.r, w.s, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
+    TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));                                    // gamma' = |s|^2
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
+    TOMO_HIP(hipGetLastError());
+    TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));   // p = s + beta p
+    std::swap(cur, nxt);
+  }
+  return TOMO_OK;
+}
+
+// SIRT with the ramp/Hamming preconditioner D in the polar Fourier domain and BB steps:
+// g = A^T_D (A x - b), x0 = 0, gradients carried by the recurrence g -= alpha A^T_D A g.
+tomo_status sirt_bb(const Ctx& c, const float* b, float* x, int vt, int iters, int filter) {
+  SolverBuffers& w = c.op->sb;
+  TOMO_TRY(launch_fill(x, 0.f, c.img * c.B, c.st));
+  TOMO_TRY(apply_backproject(c.op, b, w.s, c.B, vt, filter, 1.0f, c.st));   // s = A^T_D b
+  TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, -1.0, 0.0, c.img));  // g = -A^T_D b
+  for (int it = 0; it < iters; ++it) {
+    TOMO_TRY(apply_project(c.op, w.p, w.q, c.B, vt, c.st));                // q = A g
+    TOMO_TRY(apply_backproject(c.op, w.q, w.s, c.B, vt, filter, 1.0f, c.st));   // h = A^T_D A g
+    TOMO_TRY(c.dot(w.p, w.p, c.img, kNum));
+    TOMO_TRY(c.dot(w.p, w.s, c.img, kDen));
+    hipLaunchKernelGGL(k_sirt_step, dim3(1), dim3(256), 0, c.st, c.sc(kNum), c.sc(kDen), c.sc(kPNum),
+                       c.sc(kPDen), c.sc(kAlpha), c.B, it == 0 ? 1 : 0);
+    TOMO_HIP(hipGetLastError());
+    TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img));    // x -= alpha g
+    TOMO_TRY(c.lin(w.p, w.p, w.s, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img));// g -= alpha h
+  }
+  return TOMO_OK;
+}
+
+}  // namespace
+
+tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_solve_opts* o,
+                      hipStream_t st) {
+  if (B > 256) return fail(TOMO_EINVAL, "batch too large for the scalar kernels");
+  TOMO_TRY(ensure_solver(op));
+  Ctx c{op, B, st, (int64_t)op->g.n * op->g.n, (int64_t)op->g.nt * op->g.np};
+  SolverBuffers& w = op->sb;
+  if (o->method == TOMO_SOLVE_SIRT_BB) {
+    const int filter = o->filter == TOMO_FILTER_NONE ? TOMO_FILTER_HAMMING : o->filter;
+    TOMO_TRY(sirt_bb(c, b, x, o->values, o->iters, filter));
+  } else if (o->refine_outer == 1) {
+    TOMO_TRY(cgls(c, b, x, o->values, o->iters, o->use_x0 != 0));
+  } else {
+    // iterative refinement: residual with float32 values, correction with `values`
+    for (int outer = 0; outer < o->refine_outer; ++outer) {
+      const bool have_x = outer > 0 || o->use_x0;
+      if (have_x) {
+        TOMO_TRY(apply_project(op, x, w.q, B, TOMO_VAL_F32, st));
+        TOMO_TRY(c.lin(w.rb, b, w.q, nullptr, nullptr, 1.0, -1.0, c.sino));   // rb = b - A_f32 x
+      } else {
+        TOMO_TRY(c.lin(w.rb, b, nullptr, nullptr, nullptr, 1.0, 0.0, c.sino));
+      }
+      TOMO_TRY(cgls(c, w.rb, w.d, o->values, o->iters, false));
+      if (have_x)
+        TOMO_TRY(c.lin(x, x, w.d, nullptr, nullptr, 1.0, 1.0, c.img));       // x += d
+      else
+        TOMO_TRY(c.lin(x, w.d, nullptr, nullptr, nullptr, 1.0, 0.0, c.img)); // x = d
+    }
+  }
+  if (o->out_resnorm) {
+    TOMO_TRY(apply_project(op, x, w.q, B, TOMO_VAL_F32, st));
+    TOMO_TRY(c.lin(w.r, b, w.q, nullptr, nullptr, 1.0, -1.0, c.sino));
+    TOMO_TRY(c.dot(w.r, w.r, c.sino, kTmp));
+    hipLaunchKernelGGL(k_sqrt, dim3(1), dim3(256), 0, st, c.sc(kTmp), o->out_resnorm, B);
+    TOMO_HIP(hipGetLastError());
+  }
+  return TOMO_OK;
+}
+
+}  // namespace tomo

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Float32 operators must agree to 1e-5 relative L2 per slice; integer structure and
+run-to-run results must agree bitwise."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import round_values, Operator as OracleOperator
+from synth import phantom_stack, slice_rng
+from tests.gpu_util import cart_map, complex_channels, oracle_op, polar_row_map, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5           # float32 operators vs float64 oracle, relative L2 per slice
+
+# (n, n_angles, n_det, extra) — tiny ragged shapes, the 64^2 configuration, padding, off-centre axis
+SHAPES = [
+    (15, 7, 21, {}),
+    (16, 12, 16, {}),
+    (12, 10, 16, {"grid": 20}),
+    (16, 9, 23, {"center": 10.0}),
+    (64, 90, 91, {}),
+    (9, 7, 13, {"kw": 5}),
+]
+
+
+def _ids(s):
+    return f"n{s[0]}_t{s[1]}_p{s[2]}" + "".join(f"_{k}{v}" for k, v in s[3].items())
+
+
+def _gpu_op(tomo, n, nt, npb, extra, max_batch=8, values=("f32",)):
+    return tomo.Operator(n, nt, npb, max_batch=max_batch, values=values, device=0, **extra)
+
+
+def _oracle(n, nt, npb, extra):
+    return oracle_op(n, nt, npb, extra.get("grid", 0), extra.get("kw", 3), extra.get("center", float("nan")))
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+# ------------------------------------------------------------------------------------------
+# the SpMM kernels alone
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", SHAPES, ids=_ids)
+@pytest.mark.parametrize("batch", [1, 2, 5, 8])
+def test_slice_spmm_matches_oracle_csr(tomo, shape, batch):
+    n, nt, npb, extra = shape
+    op = _gpu_op(tomo, n, nt, npb, extra)
+    ref = _oracle(n, nt, npb, extra)
+    g = ref.geom
+    C = (batch + 1) // 2
+    Xc = _rand((g.G * g.G, C, 2), 100 + batch)
+    Xg = _dev(Xc)
+    Yg = op.slice_fwd(Xg, batch)
+    Y = complex_channels(Yg)
+    cm, pm = cart_map(g), polar_row_map(g)
+    Xo = np.empty((g.G * g.G, C), dtype=np.complex128)
+    Xo[cm] = Xc[..., 0] + 1j * Xc[..., 1]
+    Yref = (ref.S_dag @ Xo)[pm]
+    assert rel_l2(Y, Yref) < 1e-6
+    # adjoint, with and without the filter diagonal
+    Yc = _rand((g.L * nt, C, 2), 200 + batch)
+    Yo = np.empty((g.L * nt, C), dtype=np.complex128)
+    Yo[pm] = Yc[..., 0] + 1j * Yc[..., 1]
+    Xg2 = op.slice_adj(_dev(Yc), batch)
+    Xref = (ref.S @ Yo)[cm]
+    assert rel_l2(complex_channels(Xg2), Xref) < 1e-6
+    from oracle import ramp_filter
+    D = ramp_filter(g, "hamming")                              # per centred k
+    Dpolar = np.tile(D, nt)                                     # oracle column a*L + kk
+    Xg3 = op.slice_adj(_dev(Yc), batch, filter="hamming")
+    Xref3 = (ref.S @ (Dpolar[:, None] * Yo))[cm]
+    assert rel_l2(complex_channels(Xg3), Xref3) < 1e-6
+    # bitwise reproducible (no atomics)
+    assert torch.equal(op.slice_adj(_dev(Yc), batch), Xg2)
+    assert torch.equal(op.slice_fwd(Xg, batch), Yg)
+    op.close()
+
+
+# ------------------------------------------------------------------------------------------
+# composed operators
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", SHAPES, ids=_ids)
+@pytest.mark.parametrize("batch", [1, 3, 8])
+def test_project_backproject_irradon(tomo, shape, batch):
+    n, nt, npb, extra = shape
+    op = _gpu_op(tomo, n, nt, npb, extra)
+    ref = _oracle(n, nt, npb, extra)
+    x = _rand((batch, n, n), 300 + batch)
+    y = _rand((batch, nt, npb), 400 + batch)
+    yg = _host(op.project(_dev(x)))
+    xg = _host(op.backproject(_dev(y)))
+    xf = _host(op.irradon(_dev(y), filter="hamming"))
+    for s in range(batch):
+        xs = x[s].astype(np.float32).astype(np.float64)
+        ys = y[s].astype(np.float32).astype(np.float64)
+        assert rel_l2(yg[s], ref.project(xs)) < TOL, s
+        assert rel_l2(xg[s], ref.backproject(ys)) < TOL, s
+        assert rel_l2(xf[s], ref.irradon(ys, "hamming")) < TOL, s
+    op.close()
+
+
+def test_phantom_stack_configuration_1_shape(tomo):
+    """Random-ellipse phantoms at 64^2, 90 angles, 91 bins, through the paired path."""
+    x = phantom_stack(64, 5, seed_base=1000)
+    op = tomo.Operator(64, 90, 91, max_batch=5, device=0)
+    ref = oracle_op(64, 90, 91)
+    yg = _host(op.project(_dev(x)))
+    for s in range(5):
+        assert rel_l2(yg[s], ref.project(x[s].astype(np.float32).astype(np.float64))) < TOL
+    op.close()
+
+
+@pytest.mark.parametrize("vt", ["bf16", "f16"])
+def test_low_precision_values_match_rounded_oracle(tomo, vt):
+    """16-bit matrix values with float32 accumulation equal the oracle run with the same
+    rounded values; the error against the float64 operator is stated, not bounded tightly."""
+    n, nt, npb = 64, 90, 91
+    op = tomo.Operator(n, nt, npb, max_batch=4, values=("f32", vt), device=0)
+    ref = oracle_op(n, nt, npb)
+    lo = OracleOperator(ref.geom, S=round_values(ref.S, vt))
+    x = phantom_stack(n, 4, seed_base=1100)
+    y = _rand((4, nt, npb), 12)
+    yg = _host(op.project(_dev(x), values=vt))
+    xg = _host(op.backproject(_dev(y), values=vt))
+    errs = []
+    for s in range(4):
+        xs = x[s].astype(np.float32).astype(np.float64)
+        assert rel_l2(yg[s], lo.project(xs)) < TOL
+        assert rel_l2(xg[s], lo.backproject(y[s].astype(np.float32).astype(np.float64))) < TOL
+        errs.append(rel_l2(yg[s], ref.project(xs)))
+    # bf16 keeps 8 significant bits (relative rounding <= 2^-9), f16 11 bits
+    assert max(errs) < (4e-3 if vt == "bf16" else 5e-4)
+    op.close()
+
+
+# ------------------------------------------------------------------------------------------
+# invariants on the GPU (float32)
+# ------------------------------------------------------------------------------------------
+def test_gpu_adjoint_mass_conservation_and_ones(tomo):
+    n, nt, npb = 64, 90, 91
+    op = tomo.Operator(n, nt, npb, max_batch=8, device=0)
+    x = np.random.default_rng(31).uniform(0, 1, (8, n, n))
+    y = np.random.default_rng(32).standard_normal((8, nt, npb))
+    Ax = _host(op.project(_dev(x)))
+    ATy = _host(op.backproject(_dev(y)))
+    xf = x.astype(np.float32).astype(np.float64)
+    yf = y.astype(np.float32).astype(np.float64)
+    for s in range(8):
+        lhs, rhs = np.vdot(Ax[s], yf[s]), np.vdot(xf[s], ATy[s])
+        assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Ax[s]) * np.linalg.norm(yf[s])
+        np.testing.assert_allclose(Ax[s].sum(axis=1), xf[s].sum(), rtol=1e-5)
+    ones = _host(op.backproject(_dev(np.ones((2, nt, npb)))))
+    np.testing.assert_allclose(ones, nt, rtol=1e-5)
+    op.close()
+
+
+def test_gpu_determinism_and_batch_edges(tomo):
+    op = tomo.Operator(16, 12, 23, max_batch=4, device=0)
+    x = _dev(_rand((4, 16, 16), 41))
+    a = op.project(x)
+    b = op.project(x)
+    assert torch.equal(a, b)
+    # batch 0 is a no-op; batch above max_batch is rejected before any launch
+    lib = tomo.load()
+    assert lib.tomo_project(op._handle, x.data_ptr(), a.data_ptr(), 0, 0, None) == 0
+    assert lib.tomo_project(op._handle, x.data_ptr(), a.data_ptr(), 5, 0, None) == -1
+    assert lib.tomo_project(op._handle, None, a.data_ptr(), 1, 0, None) == -1
+    assert lib.tomo_project(op._handle, x.data_ptr(), a.data_ptr(), 1, 1, None) == -5  # bf16 absent
+    # slices are independent: a batch of 3 equals three batches of 1
+    x3 = _dev(_rand((3, 16, 16), 42))
+    y3 = _host(op.project(x3))
+    for s in range(3):
+        ys = _host(op.project(x3[s:s + 1].contiguous()))
+        assert rel_l2(ys[0], y3[s]) < 1e-6
+    op.close()
