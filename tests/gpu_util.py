@@ -51,16 +51,31 @@ def complex_channels(t) -> np.ndarray:
     return a[..., 0] + 1j * a[..., 1]
 
 
-def fp32_emulated(op: Operator):
-    """The oracle operator with every input and output rounded to float32: a model of what
-    float32 vector storage does to a Krylov solver (used to derive solver tolerances)."""
-    def r32(v):
-        return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
-
-    return (lambda x: r32(op.project(r32(x)))), (lambda y: r32(op.backproject(r32(y))))
+def r32(v):
+    """Round to float32 and back (models float32 storage)."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
-def solver_tolerance(x64, x32_emulated, floor: float = 1e-5, factor: float = 4.0) -> float:
-    """Allowed float32-vs-float64 iterate difference: ``factor`` times the difference the
-    float32-rounded oracle itself shows, plus a floor for the kernels' own rounding."""
-    return factor * rel_l2(x32_emulated, x64) + floor
+OP_EPS = 5e-7
+"""Relative error of one float32 operator application against float64 (the operator parity
+tests bound it by 1e-5 and measure about 1.5e-7 per application)."""
+
+
+def noisy_fp32(fn, rng, eps: float = OP_EPS):
+    """float32 model of one operator: ``fn`` on a float32-rounded input, output perturbed by
+    relative noise of size ``eps`` and rounded to float32."""
+    def apply(v):
+        out = fn(r32(v))
+        return r32(out * (1.0 + eps * rng.standard_normal(np.shape(out))))
+    return apply
+
+
+def krylov_tolerance(run, x64, realizations: int = 6, factor: float = 2.0, floor: float = 1e-5) -> float:
+    """Tolerance for a float32 Krylov solve against its float64 oracle.  These operators are
+    numerically rank-deficient, so after a few iterations float32 iterates separate from
+    float64 ones in the near-null space by an amount that depends on the rounding sequence.
+    ``run(rng)`` repeats the oracle solve with float32 storage and float32-level operator
+    noise (:func:`noisy_fp32`); the tolerance is ``factor`` times the largest deviation over
+    ``realizations`` such runs, plus ``floor``."""
+    devs = [rel_l2(run(np.random.default_rng(i)), x64) for i in range(realizations)]
+    return factor * max(devs) + floor
