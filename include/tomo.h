@@ -107,12 +107,28 @@ typedef struct {
   int64_t nnz;            /* stored entries (same in both CSR copies)                */
   int64_t cols_touched;   /* distinct Cartesian points referenced by S^dagger         */
   int64_t polar_nonempty; /* polar rows with at least one entry                       */
-  int64_t adj_bin_rows[4];/* S rows per bin: <= short, <= medium, long (chunked), 0   */
-  int64_t adj_long_chunks;/* partial-sum chunks used for long S rows                 */
-  int32_t adj_short_max, adj_medium_max, adj_chunk; /* bin thresholds in nnz        */
+  int64_t adj_sell_rows;   /* S rows held in the sliced-ELL layout                   */
+  int64_t adj_sell_padding;/* padding entries of that layout                          */
+  int64_t adj_medium_rows; /* S rows processed one wavefront per row                  */
+  int64_t adj_long_rows;   /* S rows split into chunks                                */
+  int64_t adj_long_chunks; /* chunks (partial sums) used for the long rows            */
   int32_t device;         /* -1 for a host-only operator                             */
   uint32_t values;        /* value arrays present on the device                      */
 } tomo_op_info;
+
+/* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
+ * Defaults: 2, 2, 16, 4096, 256, 256. */
+typedef struct {
+  int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
+                                     (reduced automatically when it does not divide C)        */
+  int32_t adj_channels_per_lane;  /* same for the adjoint SpMM                                */
+  int32_t adj_sell_max;           /* S rows with <= this many entries use the sliced-ELL
+                                     layout (8 rows per slice); 0..1024                        */
+  int32_t adj_sell_sigma;         /* those rows are sorted by length within windows of this
+                                     many rows (>= 1; 1 = natural order)                       */
+  int32_t adj_medium_max;         /* longer rows up to this many entries: one wavefront each  */
+  int32_t adj_chunk;              /* rows above that: chunks of this many entries (8..8192)   */
+} tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */
 typedef enum { TOMO_SOLVE_CGLS = 0, TOMO_SOLVE_SIRT_BB = 1 } tomo_solver;
@@ -191,6 +207,15 @@ tomo_status tomo_export_csr(const tomo_op* op, int32_t which, int64_t* rowptr, i
 /* Copy the separable deapodisation factors kd[n] (k*(i1,i2) = kd[i1] kd[i2]) and,
  * when filt != NULL, the diagonal D for `filter` per FFT-ordered radial index [L]. */
 tomo_status tomo_export_factors(const tomo_op* op, int32_t filter, double* kd, double* filt);
+
+/* Read the current kernel layout parameters. */
+tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out);
+
+/* Change the kernel layout parameters.  Changing the adjoint bin parameters rebuilds that
+ * layout on the host and re-uploads it, synchronising the device; results do not depend on
+ * the parameters except through float32 summation order.  Errors: TOMO_EINVAL (out of range;
+ * the operator is unchanged), TOMO_ENOMEM. */
+tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* t);
 
 /* Free everything the operator owns (synchronises its device first).  NULL is a no-op. */
 void tomo_destroy_operator(tomo_op* op);

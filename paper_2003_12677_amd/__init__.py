@@ -45,10 +45,16 @@ class tomo_op_info(ctypes.Structure):
                 ("beta", ctypes.c_double), ("center", ctypes.c_double),
                 ("n_polar", ctypes.c_int64), ("n_cart", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("cols_touched", ctypes.c_int64), ("polar_nonempty", ctypes.c_int64),
-                ("adj_bin_rows", ctypes.c_int64 * 4), ("adj_long_chunks", ctypes.c_int64),
-                ("adj_short_max", ctypes.c_int32), ("adj_medium_max", ctypes.c_int32),
-                ("adj_chunk", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("adj_sell_rows", ctypes.c_int64), ("adj_sell_padding", ctypes.c_int64),
+                ("adj_medium_rows", ctypes.c_int64), ("adj_long_rows", ctypes.c_int64),
+                ("adj_long_chunks", ctypes.c_int64), ("device", ctypes.c_int32),
                 ("values", ctypes.c_uint32)]
+
+
+class tomo_tuning(ctypes.Structure):
+    _fields_ = [("fwd_channels_per_lane", ctypes.c_int32), ("adj_channels_per_lane", ctypes.c_int32),
+                ("adj_sell_max", ctypes.c_int32), ("adj_sell_sigma", ctypes.c_int32),
+                ("adj_medium_max", ctypes.c_int32), ("adj_chunk", ctypes.c_int32)]
 
 
 class tomo_solve_opts(ctypes.Structure):
@@ -72,6 +78,8 @@ SIGNATURES = {
     "tomo_op_info_get": (ctypes.c_int, [_P, ctypes.POINTER(tomo_op_info)]),
     "tomo_export_csr": (ctypes.c_int, [_P, _I, _P, _P, _P]),
     "tomo_export_factors": (ctypes.c_int, [_P, _I, _P, _P]),
+    "tomo_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(tomo_tuning)]),
+    "tomo_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(tomo_tuning)]),
     "tomo_destroy_operator": (None, [_P]),
     "tomo_last_error": (ctypes.c_char_p, []),
     "tomo_version": (ctypes.c_char_p, []),
@@ -183,6 +191,23 @@ class Operator:
         val = np.empty(info.nnz, dtype=np.float64)
         _check(_lib.tomo_export_csr(self._handle, which, rp.ctypes.data, col.ctypes.data, val.ctypes.data))
         return rp, col, val
+
+    def get_tuning(self) -> dict:
+        t = tomo_tuning()
+        _check(_lib.tomo_get_tuning(self._handle, ctypes.byref(t)))
+        return {name: getattr(t, name) for name, _ in tomo_tuning._fields_}
+
+    def set_tuning(self, **changes) -> dict:
+        """``tomo_set_tuning`` with the given fields changed; returns the new tuning."""
+        cur = self.get_tuning()
+        unknown = set(changes) - set(cur)
+        if unknown:
+            raise KeyError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update(changes)
+        t = tomo_tuning(**cur)
+        _check(_lib.tomo_set_tuning(self._handle, ctypes.byref(t)))
+        self.info = self.op_info()
+        return self.get_tuning()
 
     def export_factors(self, filter: str = "none"):
         import numpy as np

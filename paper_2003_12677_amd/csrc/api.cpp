@@ -43,68 +43,103 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-tomo_status upload_csr(const HostCSR& h, uint32_t values, DevCSR* d) {
-  d->rows = h.rows;
-  d->nnz = h.nnz();
-  std::vector<int32_t> rp(h.rowptr.begin(), h.rowptr.end());
-  TOMO_TRY(upload(&d->rowptr, rp.data(), rp.size()));
-  TOMO_TRY(upload(&d->col, h.col.data(), h.col.size()));
-  const size_t nnz = h.val.size();
+// Upload float64 values as every requested storage type (float32, bfloat16, float16).
+tomo_status upload_values(const std::vector<double>& v, uint32_t values, void* dst[3]) {
+  const size_t nnz = v.size();
   std::vector<float> vf(nnz);
-  for (size_t i = 0; i < nnz; ++i) vf[i] = (float)h.val[i];
-  if (values & TOMO_VALUES_F32) TOMO_TRY(upload((float**)&d->val[TOMO_VAL_F32], vf.data(), nnz));
+  for (size_t i = 0; i < nnz; ++i) vf[i] = (float)v[i];
+  if (values & TOMO_VALUES_F32) TOMO_TRY(upload((float**)&dst[TOMO_VAL_F32], vf.data(), nnz));
   if (values & TOMO_VALUES_BF16) {
     std::vector<uint16_t> vb(nnz);
     for (size_t i = 0; i < nnz; ++i) vb[i] = f32_to_bf16_rne(vf[i]);
-    TOMO_TRY(upload((uint16_t**)&d->val[TOMO_VAL_BF16], vb.data(), nnz));
+    TOMO_TRY(upload((uint16_t**)&dst[TOMO_VAL_BF16], vb.data(), nnz));
   }
   if (values & TOMO_VALUES_F16) {
     std::vector<_Float16> vh(nnz);
     for (size_t i = 0; i < nnz; ++i) vh[i] = (_Float16)vf[i];
-    TOMO_TRY(upload((_Float16**)&d->val[TOMO_VAL_F16], vh.data(), nnz));
+    TOMO_TRY(upload((_Float16**)&dst[TOMO_VAL_F16], vh.data(), nnz));
   }
   return TOMO_OK;
 }
 
-void free_csr(DevCSR* d) {
-  dfree(d->rowptr);
-  dfree(d->col);
-  for (auto& v : d->val) dfree(v);
+void free_adj(tomo_op* op) {
+  DevAdj& d = op->adj;
+  dfree(d.slice_ptr);
+  dfree(d.slice_rows);
+  dfree(d.col);
+  for (auto& v : d.val) dfree(v);
+  dfree(d.tail_rows);
+  dfree(d.tail_ptr);
+  dfree(d.tail_col);
+  for (auto& v : d.tail_val) dfree(v);
+  dfree(d.chunk_beg);
+  dfree(d.chunk_end);
+  dfree(d.long_chunk_ptr);
+  d = DevAdj();
+  dfree(op->partials);
+  op->partials_cap = 0;
+}
+
+// (Re)build the adjoint layout for op->tune on the host and upload it.
+tomo_status upload_adj(tomo_op* op) {
+  op->adj_ready = false;
+  free_adj(op);
+  build_adj_layout(op->s, op->tune, &op->hadj);
+  const HostAdj& h = op->hadj;
+  if (h.col.size() >= (size_t)INT32_MAX)
+    return fail(TOMO_EINVAL, "sliced-ELL layout exceeds 32-bit entry indices; lower adj_sell_max");
+  DevAdj& d = op->adj;
+  d.n_slices = (int64_t)h.slice_ptr.size() - 1;
+  d.n_medium = h.n_medium;
+  d.n_long = h.n_long;
+  d.n_chunks = (int64_t)h.chunk_beg.size();
+  TOMO_TRY(upload(&d.slice_ptr, h.slice_ptr.data(), h.slice_ptr.size()));
+  TOMO_TRY(upload(&d.slice_rows, h.slice_rows.data(), h.slice_rows.size()));
+  TOMO_TRY(upload(&d.col, h.col.data(), h.col.size()));
+  TOMO_TRY(upload_values(h.val, op->g.values, d.val));
+  TOMO_TRY(upload(&d.tail_rows, h.tail_rows.data(), h.tail_rows.size()));
+  TOMO_TRY(upload(&d.tail_ptr, h.tail_ptr.data(), h.tail_ptr.size()));
+  TOMO_TRY(upload(&d.tail_col, h.tail_col.data(), h.tail_col.size()));
+  TOMO_TRY(upload_values(h.tail_val, op->g.values, d.tail_val));
+  TOMO_TRY(upload(&d.chunk_beg, h.chunk_beg.data(), h.chunk_beg.size()));
+  TOMO_TRY(upload(&d.chunk_end, h.chunk_end.data(), h.chunk_end.size()));
+  TOMO_TRY(upload(&d.long_chunk_ptr, h.long_chunk_ptr.data(), h.long_chunk_ptr.size()));
+  if (d.n_chunks > 0) {
+    const size_t pb = (size_t)d.n_chunks * op->cmax * sizeof(float2);
+    if (hipMalloc((void**)&op->partials, pb) != hipSuccess) {
+      op->partials = nullptr;
+      return fail(TOMO_ENOMEM, "long-row partial sums (%zu B)", pb);
+    }
+    op->partials_cap = (size_t)d.n_chunks;
+  }
+  op->adj_ready = true;
+  return TOMO_OK;
 }
 
 void free_device(tomo_op* op) {
   destroy_plans(op);
   free_solver(op);
-  free_csr(&op->fwd);
-  free_csr(&op->adj);
-  dfree(op->bins.short_rows);
-  dfree(op->bins.medium_rows);
-  dfree(op->bins.long_rows);
-  dfree(op->bins.long_chunk_ptr);
-  dfree(op->bins.chunk_beg);
-  dfree(op->bins.chunk_end);
+  dfree(op->fwd.col);
+  for (auto& v : op->fwd.val) dfree(v);
+  free_adj(op);
   dfree(op->kd_dev);
   for (auto& f : op->filt_dev) dfree(f);
   dfree(op->X);
   dfree(op->Y);
-  dfree(op->partials);
 }
 
 tomo_status upload_all(tomo_op* op) {
   const Geom& g = op->g;
-  TOMO_TRY(upload_csr(op->sdag, g.values, &op->fwd));
-  TOMO_TRY(upload_csr(op->s, g.values, &op->adj));
-  const HostBins& hb = op->hbins;
-  TOMO_TRY(upload(&op->bins.short_rows, hb.short_rows.data(), hb.short_rows.size()));
-  TOMO_TRY(upload(&op->bins.medium_rows, hb.medium_rows.data(), hb.medium_rows.size()));
-  TOMO_TRY(upload(&op->bins.long_rows, hb.long_rows.data(), hb.long_rows.size()));
-  TOMO_TRY(upload(&op->bins.long_chunk_ptr, hb.long_chunk_ptr.data(), hb.long_chunk_ptr.size()));
-  TOMO_TRY(upload(&op->bins.chunk_beg, hb.chunk_beg.data(), hb.chunk_beg.size()));
-  TOMO_TRY(upload(&op->bins.chunk_end, hb.chunk_end.data(), hb.chunk_end.size()));
-  op->bins.n_short = (int64_t)hb.short_rows.size();
-  op->bins.n_medium = (int64_t)hb.medium_rows.size();
-  op->bins.n_long = (int64_t)hb.long_rows.size();
-  op->bins.n_chunks = (int64_t)hb.chunk_beg.size();
+  op->cmax = (g.max_batch + 1) / 2;
+  {
+    HostEll ell;
+    build_ell(op->sdag, g.kw * g.kw, &ell);
+    op->fwd.rows = op->sdag.rows;
+    op->fwd.W2 = ell.W2;
+    TOMO_TRY(upload(&op->fwd.col, ell.col.data(), ell.col.size()));
+    TOMO_TRY(upload_values(ell.val, g.values, op->fwd.val));
+  }
+  TOMO_TRY(upload_adj(op));
   std::vector<float> kdf(op->kd.begin(), op->kd.end());
   TOMO_TRY(upload(&op->kd_dev, kdf.data(), kdf.size()));
   for (int f = TOMO_FILTER_RAMLAK; f <= TOMO_FILTER_HAMMING; ++f) {
@@ -113,7 +148,6 @@ tomo_status upload_all(tomo_op* op) {
     std::vector<float> df(d.begin(), d.end());
     TOMO_TRY(upload(&op->filt_dev[f], df.data(), df.size()));
   }
-  op->cmax = (g.max_batch + 1) / 2;
   const size_t xb = (size_t)g.G * g.G * op->cmax * sizeof(float2);
   const size_t yb = (size_t)g.L * g.nt * op->cmax * sizeof(float2);
   if (hipMalloc((void**)&op->X, xb) != hipSuccess) {
@@ -123,13 +157,6 @@ tomo_status upload_all(tomo_op* op) {
   if (hipMalloc((void**)&op->Y, yb) != hipSuccess) {
     op->Y = nullptr;
     return fail(TOMO_ENOMEM, "polar workspace (%zu B)", yb);
-  }
-  if (op->bins.n_chunks > 0) {
-    const size_t pb = (size_t)op->bins.n_chunks * op->cmax * sizeof(float2);
-    if (hipMalloc((void**)&op->partials, pb) != hipSuccess) {
-      op->partials = nullptr;
-      return fail(TOMO_ENOMEM, "long-row partial sums (%zu B)", pb);
-    }
   }
   TOMO_HIP(hipDeviceSynchronize());
   return TOMO_OK;
@@ -199,8 +226,8 @@ tomo_status tomo_build_operator(const tomo_geometry* gin, int device, tomo_op** 
   try {
     build_sdag(op->g, &op->sdag);
     transpose_csr(op->sdag, &op->s);
-    build_bins(op->s, op->binp, &op->hbins);
     deapod_factors(op->g, &op->kd);
+    if (device < 0) build_adj_layout(op->s, op->tune, &op->hadj);
   } catch (const std::bad_alloc&) {
     return fail(TOMO_ENOMEM, "host allocation failed while building the matrices");
   }
@@ -319,13 +346,11 @@ tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out) {
   out->nnz = op->sdag.nnz();
   out->cols_touched = op->cols_touched;
   out->polar_nonempty = op->polar_nonempty;
-  out->adj_bin_rows[0] = (int64_t)op->hbins.short_rows.size();
-  out->adj_bin_rows[1] = (int64_t)op->hbins.medium_rows.size();
-  out->adj_bin_rows[2] = (int64_t)op->hbins.long_rows.size();
-  out->adj_long_chunks = (int64_t)op->hbins.chunk_beg.size();
-  out->adj_short_max = op->binp.short_max;
-  out->adj_medium_max = op->binp.medium_max;
-  out->adj_chunk = op->binp.chunk;
+  out->adj_sell_rows = op->hadj.sell_rows;
+  out->adj_sell_padding = op->hadj.sell_padding;
+  out->adj_medium_rows = op->hadj.n_medium;
+  out->adj_long_rows = op->hadj.n_long;
+  out->adj_long_chunks = (int64_t)op->hadj.chunk_beg.size();
   out->device = op->device;
   out->values = op->values;
   return TOMO_OK;
@@ -354,6 +379,45 @@ tomo_status tomo_export_factors(const tomo_op* op, int32_t filter, double* kd, d
     filter_diagonal(op->g, filter, &d);
     std::memcpy(filt, d.data(), d.size() * sizeof(double));
   }
+  return TOMO_OK;
+}
+
+tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
+  clear_error();
+  if (!op || !out) return fail(TOMO_EINVAL, "NULL argument");
+  out->fwd_channels_per_lane = op->tune.fwd_cpl;
+  out->adj_channels_per_lane = op->tune.adj_cpl;
+  out->adj_sell_max = op->tune.sell_max;
+  out->adj_sell_sigma = op->tune.sell_sigma;
+  out->adj_medium_max = op->tune.medium_max;
+  out->adj_chunk = op->tune.chunk;
+  return TOMO_OK;
+}
+
+tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
+  clear_error();
+  if (!op || !in) return fail(TOMO_EINVAL, "NULL argument");
+  Tuning t;
+  t.fwd_cpl = in->fwd_channels_per_lane;
+  t.adj_cpl = in->adj_channels_per_lane;
+  t.sell_max = in->adj_sell_max;
+  t.sell_sigma = in->adj_sell_sigma;
+  t.medium_max = in->adj_medium_max;
+  t.chunk = in->adj_chunk;
+  TOMO_TRY(check_tuning(t));
+  const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
+                        t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
+  op->tune = t;
+  if (!relayout) return TOMO_OK;
+  if (op->device < 0) {
+    build_adj_layout(op->s, op->tune, &op->hadj);
+    return TOMO_OK;
+  }
+  DeviceGuard guard(op->device);
+  TOMO_HIP(hipDeviceSynchronize());
+  const tomo_status st = upload_adj(op);
+  if (st != TOMO_OK) return st;
+  TOMO_HIP(hipDeviceSynchronize());
   return TOMO_OK;
 }
 

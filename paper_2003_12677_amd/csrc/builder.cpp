@@ -207,27 +207,97 @@ void transpose_csr(const HostCSR& a, HostCSR* at) {
   }
 }
 
-void build_bins(const HostCSR& s, const BinParams& p, HostBins* b) {
-  b->short_rows.clear();
-  b->medium_rows.clear();
-  b->long_rows.clear();
-  b->long_chunk_ptr.assign(1, 0);
-  b->chunk_beg.clear();
-  b->chunk_end.clear();
-  for (int64_t r = 0; r < s.rows; ++r) {
-    const int64_t len = s.rowptr[r + 1] - s.rowptr[r];
-    if (len <= p.short_max) {
-      b->short_rows.push_back((int32_t)r);
-    } else if (len <= p.medium_max) {
-      b->medium_rows.push_back((int32_t)r);
-    } else {
-      b->long_rows.push_back((int32_t)r);
-      for (int64_t e = s.rowptr[r]; e < s.rowptr[r + 1]; e += p.chunk) {
-        b->chunk_beg.push_back((int32_t)e);
-        b->chunk_end.push_back((int32_t)std::min<int64_t>(e + p.chunk, s.rowptr[r + 1]));
-      }
-      b->long_chunk_ptr.push_back((int32_t)b->chunk_beg.size());
+void build_ell(const HostCSR& a, int W2, HostEll* out) {
+  out->W2 = W2;
+  out->col.assign((size_t)a.rows * W2, -1);
+  out->val.assign((size_t)a.rows * W2, 0.0);
+  for (int64_t r = 0; r < a.rows; ++r) {
+    int s = 0;
+    for (int64_t e = a.rowptr[r]; e < a.rowptr[r + 1]; ++e, ++s) {
+      out->col[(size_t)r * W2 + s] = a.col[e];
+      out->val[(size_t)r * W2 + s] = a.val[e];
     }
+  }
+}
+
+tomo_status check_tuning(const Tuning& t) {
+  auto cpl_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
+  if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
+    return fail(TOMO_EINVAL, "channels per lane must be 1, 2 or 4 (got %d, %d)", t.fwd_cpl, t.adj_cpl);
+  if (t.sell_max < 0 || t.sell_max > 1024) return fail(TOMO_EINVAL, "sell_max %d not in [0, 1024]", t.sell_max);
+  if (t.medium_max < t.sell_max || t.medium_max > (1 << 20))
+    return fail(TOMO_EINVAL, "medium_max %d must be in [sell_max, 2^20]", t.medium_max);
+  if (t.chunk < 8 || t.chunk > 8192) return fail(TOMO_EINVAL, "chunk %d not in [8, 8192]", t.chunk);
+  if (t.sell_sigma < 1) return fail(TOMO_EINVAL, "sell_sigma must be >= 1");
+  return TOMO_OK;
+}
+
+void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* o) {
+  *o = HostAdj();
+  std::vector<int32_t> sell, medium, lng;
+  auto len = [&](int64_t r) { return s.rowptr[r + 1] - s.rowptr[r]; };
+  for (int64_t r = 0; r < s.rows; ++r) {
+    const int64_t l = len(r);
+    if (l <= t.sell_max) sell.push_back((int32_t)r);
+    else if (l <= t.medium_max) medium.push_back((int32_t)r);
+    else lng.push_back((int32_t)r);
+  }
+  // sort by decreasing length inside windows of sigma rows (keeps neighbouring rows together)
+  for (size_t w = 0; w < sell.size(); w += (size_t)t.sell_sigma) {
+    auto b = sell.begin() + w;
+    auto e = sell.begin() + std::min(sell.size(), w + (size_t)t.sell_sigma);
+    std::stable_sort(b, e, [&](int32_t x, int32_t y) { return len(x) > len(y); });
+  }
+  o->sell_rows = (int64_t)sell.size();
+  const int64_t ns = (o->sell_rows + kSliceRows - 1) / kSliceRows;
+  o->slice_rows.assign((size_t)ns * kSliceRows, -1);
+  std::copy(sell.begin(), sell.end(), o->slice_rows.begin());
+  o->slice_ptr.assign((size_t)ns + 1, 0);
+  for (int64_t i = 0; i < ns; ++i) {
+    int64_t lmax = 0;
+    for (int j = 0; j < kSliceRows; ++j) {
+      const int32_t r = o->slice_rows[i * kSliceRows + j];
+      if (r >= 0) lmax = std::max(lmax, len(r));
+    }
+    o->slice_ptr[i + 1] = o->slice_ptr[i] + (int32_t)(lmax * kSliceRows);
+  }
+  o->col.assign((size_t)o->slice_ptr[ns], -1);
+  o->val.assign((size_t)o->slice_ptr[ns], 0.0);
+  int64_t used = 0;
+  for (int64_t i = 0; i < ns; ++i) {
+    for (int j = 0; j < kSliceRows; ++j) {
+      const int32_t r = o->slice_rows[i * kSliceRows + j];
+      if (r < 0) continue;
+      for (int64_t e = 0; e < len(r); ++e) {
+        const size_t dst = (size_t)o->slice_ptr[i] + (size_t)e * kSliceRows + j;
+        o->col[dst] = s.col[s.rowptr[r] + e];
+        o->val[dst] = s.val[s.rowptr[r] + e];
+        ++used;
+      }
+    }
+  }
+  o->sell_padding = (int64_t)o->col.size() - used;
+  // tail CSR: medium rows, then long rows
+  o->n_medium = (int64_t)medium.size();
+  o->n_long = (int64_t)lng.size();
+  o->tail_rows = medium;
+  o->tail_rows.insert(o->tail_rows.end(), lng.begin(), lng.end());
+  o->tail_ptr.assign(o->tail_rows.size() + 1, 0);
+  for (size_t i = 0; i < o->tail_rows.size(); ++i) {
+    const int32_t r = o->tail_rows[i];
+    o->tail_ptr[i + 1] = o->tail_ptr[i] + (int32_t)len(r);
+    for (int64_t e = s.rowptr[r]; e < s.rowptr[r + 1]; ++e) {
+      o->tail_col.push_back(s.col[e]);
+      o->tail_val.push_back(s.val[e]);
+    }
+  }
+  o->long_chunk_ptr.assign(1, 0);
+  for (int64_t i = o->n_medium; i < (int64_t)o->tail_rows.size(); ++i) {
+    for (int32_t e = o->tail_ptr[i]; e < o->tail_ptr[i + 1]; e += t.chunk) {
+      o->chunk_beg.push_back(e);
+      o->chunk_end.push_back(std::min(e + t.chunk, o->tail_ptr[i + 1]));
+    }
+    o->long_chunk_ptr.push_back((int32_t)o->chunk_beg.size());
   }
 }
 

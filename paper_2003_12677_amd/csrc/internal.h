@@ -54,25 +54,45 @@ struct HostCSR {
   int64_t nnz() const { return (int64_t)col.size(); }
 };
 
-// Bin thresholds (nnz per row) for the adjoint SpMM over S's Cartesian rows.
-struct BinParams {
-  int short_max = 16;   // rows with <= short_max entries: one lane group per row
-  int medium_max = 128; // rows with <= medium_max entries: one wavefront per row
-  int chunk = 256;      // longer rows: split into chunks of <= chunk entries per block
+// Layout parameters of the two SpMMs (the autotuner's search space; tomo_set_tuning).
+struct Tuning {
+  int fwd_cpl = 2;        // complex channels per lane in the forward kernel (1, 2 or 4)
+  int adj_cpl = 2;        // complex channels per lane in the adjoint kernel (1, 2 or 4)
+  int sell_max = 16;      // S rows with <= sell_max entries: sliced ELL, 8 rows per slice
+  int sell_sigma = 4096;  // rows are sorted by length within windows of sell_sigma rows
+  int medium_max = 256;   // longer rows up to medium_max entries: one wavefront per row
+  int chunk = 256;        // rows above medium_max: chunks of <= chunk entries, one block each
 };
 
-struct HostBins {
-  std::vector<int32_t> short_rows, medium_rows;
-  std::vector<int32_t> long_rows;          // [n_long]
-  std::vector<int32_t> long_chunk_ptr;     // [n_long + 1] into the chunk list
-  std::vector<int32_t> chunk_beg, chunk_end;  // [n_chunks] entry ranges
+constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
+
+// S^dagger with a constant row stride W2 = k_w^2 (its rows never hold more): entry s of row r
+// at r * W2 + s, padded with column -1 (skipped) and value 0.
+struct HostEll {
+  int W2 = 0;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+// S split by row length: short rows in sliced ELL (slice i holds rows slice_rows[8i .. 8i+8),
+// entry e of slot j at slice_ptr[i] + 8 e + j, padded with column -1), the remaining rows as a
+// compact CSR ("tail"): medium rows first, then long rows, whose entries are cut into chunks.
+struct HostAdj {
+  std::vector<int32_t> slice_ptr, slice_rows, col;
+  std::vector<double> val;
+  std::vector<int32_t> tail_rows, tail_ptr, tail_col;
+  std::vector<double> tail_val;
+  int64_t n_medium = 0, n_long = 0, sell_rows = 0, sell_padding = 0;
+  std::vector<int32_t> chunk_beg, chunk_end, long_chunk_ptr;   // into the tail entries
 };
 
 tomo_status resolve_geometry(const tomo_geometry* in, Geom* g);
 double kernel_value(double t, int W, double beta);
 void build_sdag(const Geom& g, HostCSR* sdag);
 void transpose_csr(const HostCSR& a, HostCSR* at);
-void build_bins(const HostCSR& s, const BinParams& p, HostBins* bins);
+void build_ell(const HostCSR& a, int W2, HostEll* out);
+tomo_status check_tuning(const Tuning& t);
+void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* out);
 void deapod_factors(const Geom& g, std::vector<double>* kd);
 void filter_diagonal(const Geom& g, int filter, std::vector<double>* d);   // FFT-ordered k
 uint16_t f32_to_bf16_rne(float f);
@@ -80,19 +100,20 @@ uint16_t f32_to_bf16_rne(float f);
 // ---------------------------------------------------------------------------------
 // device state
 // ---------------------------------------------------------------------------------
-struct DevCSR {
-  int64_t rows = 0, nnz = 0;
-  int32_t* rowptr = nullptr;    // int32 row pointers (nnz < 2^31 is checked)
+struct DevEll {
+  int64_t rows = 0;
+  int W2 = 0;
   int32_t* col = nullptr;
   void* val[3] = {nullptr, nullptr, nullptr};   // indexed by tomo_value_type
 };
 
-struct DevBins {
-  int32_t* short_rows = nullptr;  int64_t n_short = 0;
-  int32_t* medium_rows = nullptr; int64_t n_medium = 0;
-  int32_t* long_rows = nullptr;   int64_t n_long = 0;
-  int32_t* long_chunk_ptr = nullptr;
-  int32_t* chunk_beg = nullptr;   int32_t* chunk_end = nullptr; int64_t n_chunks = 0;
+struct DevAdj {
+  int64_t n_slices = 0, n_medium = 0, n_long = 0, n_chunks = 0;
+  int32_t *slice_ptr = nullptr, *slice_rows = nullptr, *col = nullptr;
+  void* val[3] = {nullptr, nullptr, nullptr};
+  int32_t *tail_rows = nullptr, *tail_ptr = nullptr, *tail_col = nullptr;
+  void* tail_val[3] = {nullptr, nullptr, nullptr};
+  int32_t *chunk_beg = nullptr, *chunk_end = nullptr, *long_chunk_ptr = nullptr;
 };
 
 struct FFTPlans {
@@ -114,22 +135,24 @@ struct SolverBuffers {
 
 struct tomo_op {
   tomo::Geom g;
-  tomo::BinParams binp;
+  tomo::Tuning tune;
   tomo::HostCSR sdag, s;          // float64 host copies (test export)
-  tomo::HostBins hbins;
+  tomo::HostAdj hadj;             // adjoint layout for the current tuning
   std::vector<double> kd;         // separable deapodisation factors [n]
   int device = -1;
   uint32_t values = 0;
   int64_t cols_touched = 0, polar_nonempty = 0;
   // device
-  tomo::DevCSR fwd, adj;
-  tomo::DevBins bins;
+  tomo::DevEll fwd;
+  tomo::DevAdj adj;
   float* kd_dev = nullptr;        // [n]
   float* filt_dev[4] = {nullptr, nullptr, nullptr, nullptr};   // D per tomo_filter, [L]
   int cmax = 0;                   // complex channels the workspace holds
   float2* X = nullptr;            // [G*G][cmax]
   float2* Y = nullptr;            // [L*nt][cmax]
   float2* partials = nullptr;     // [n_chunks][cmax] long-row partial sums
+  size_t partials_cap = 0;        // chunks the partials buffer holds
+  bool adj_ready = false;         // false while (or after a failed) adjoint layout upload
   std::map<int, tomo::FFTPlans> plans;   // keyed by channel count C
   tomo::SolverBuffers sb;
 };

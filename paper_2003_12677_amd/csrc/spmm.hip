@@ -1,18 +1,25 @@
-// CSR SpMM kernels for the slicing interpolation (Sec. 2.2: the key step; Sec. 3 Eq. (2)).
+// SpMM kernels for the slicing interpolation (Sec. 2.2: the key step; Sec. 3 Eq. (2)).
 //
-// Vectors hold C complex channels per grid point, channel-fastest ([point][C] complex64), so
-// gathering one column fetches 8*C contiguous bytes (128 B, one cache line, at C = 16).
-// A "lane group" of T lanes owns one output row; lane t holds CPL consecutive complex channels
-// (CPL = 2 -> one 16-byte load per lane per gathered column).  Accumulation is float32 in a
-// fixed order, so results are bitwise reproducible.
+// Vectors hold C complex channels per grid point, channel-fastest ([point][C] complex64), so a
+// gathered column is 8*C contiguous bytes (128 B, one cache line, at C = 16).  A lane group of T
+// lanes owns one output row; lane t holds CPL consecutive complex channels (CPL = 2: one 16-byte
+// load per lane per gathered column).  Accumulation is float32 in a fixed order, so results are
+// bitwise reproducible.
 //
-// Forward (S^dagger, polar rows, <= k_w^2 entries per row): one lane group per row.
-// Adjoint (S, Cartesian rows, 0 .. thousands of entries per row): row-binned, no atomics
-// (the transpose is stored, Sec. 3.1), in one launch whose block range selects the bin:
-//   short rows  -> one lane group per row,
-//   medium rows -> one wavefront per row (lane groups stride the entries, shuffle reduction),
-//   long rows   -> chunks of entries, one block per chunk, partial sums to a scratch buffer,
-//                  followed by a small launch that adds each long row's chunks in order.
+// These kernels are latency-bound: measured HBM traffic equals the algorithmic bytes, so speed
+// comes from keeping the number of dependent memory round trips per row small.  Every row is
+// processed in "rounds": first all column indices and values of up to U entries are loaded, then
+// all U gathers are issued, then accumulated.
+//
+// Forward (S^dagger): rows hold at most k_w^2 entries, stored with a constant stride (ELL), so a
+// row is one round: indices/values, then k_w^2 gathers.
+// Adjoint (S): atomic-free through the stored transpose (Sec. 3.1), one kernel per row layout
+// (separate launches, so each gets its own register allocation and full occupancy):
+//   sliced ELL  rows with few entries (99% of rows), 8 rows per slice, entries of a slice stored
+//               entry-major so the 8 rows' indices of one entry are contiguous;
+//   medium      one wavefront per row, lane groups stride the row's entries, shuffle reduction;
+//   long        chunks of entries, one block per chunk, partial sums to a scratch buffer,
+//               then a small launch adds each long row's chunk sums in order.
 
 #include <hip/hip_runtime.h>
 
@@ -22,6 +29,7 @@ namespace tomo {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kRound = 8;   // entries per round in the adjoint paths
 
 struct bf16_t { uint16_t bits; };
 
@@ -39,287 +47,350 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
+// CPL consecutive complex channels of one lane
 template <int CPL>
-struct Acc {
+struct Vec {
   float v[2 * CPL];
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int i = 0; i < 2 * CPL; ++i) v[i] = 0.f;
-  }
-  __device__ __forceinline__ void fma(float w, const float2* p) {
-    if constexpr (CPL == 2) {
-      const float4 x = *reinterpret_cast<const float4*>(p);
-      v[0] += w * x.x; v[1] += w * x.y; v[2] += w * x.z; v[3] += w * x.w;
-    } else {
-      const float2 x = *p;
-      v[0] += w * x.x; v[1] += w * x.y;
-    }
-  }
-  __device__ __forceinline__ void store(float2* p) const {
-    if constexpr (CPL == 2) {
-      *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-    } else {
-      *p = make_float2(v[0], v[1]);
-    }
-  }
-  __device__ __forceinline__ void add(const Acc& o) {
-#pragma unroll
-    for (int i = 0; i < 2 * CPL; ++i) v[i] += o.v[i];
-  }
 };
 
-// Sum of entries [e0, e1) with stride `step` of one CSR row into acc (lane's channels at p0).
-template <int CPL, typename V, bool FILT>
-__device__ __forceinline__ void row_dot(const int32_t* __restrict__ col, const V* __restrict__ val,
-                                        const float2* __restrict__ src, int C, int cb,
-                                        int64_t e0, int64_t e1, int step, const float* dscale,
-                                        double inv_nt, Acc<CPL>& acc) {
-  int64_t e = e0;
-  // four entries per round: the index and value loads of all four are issued before the
-  // gathers, so each lane keeps four independent 16-byte loads in flight
-  for (; e + 3 * step < e1; e += 4 * step) {
-    int c[4];
-    float w[4];
+template <int CPL>
+__device__ __forceinline__ Vec<CPL> load_vec(const float2* p) {
+  Vec<CPL> r;
+  if constexpr (CPL == 1) {
+    const float2 a = *p;
+    r.v[0] = a.x; r.v[1] = a.y;
+  } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      c[u] = col[e + u * step];
-      w[u] = ldv(val, e + u * step);
+    for (int h = 0; h < CPL / 2; ++h) {
+      const float4 a = reinterpret_cast<const float4*>(p)[h];
+      r.v[4 * h] = a.x; r.v[4 * h + 1] = a.y; r.v[4 * h + 2] = a.z; r.v[4 * h + 3] = a.w;
     }
-    if constexpr (FILT) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) w[u] *= dscale[(int)(((double)c[u] + 0.5) * inv_nt)];
-    }
-    const float2* p[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) p[u] = src + (int64_t)c[u] * C + cb;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc.fma(w[u], p[u]);
   }
-  for (; e < e1; e += step) {
-    const int c = col[e];
-    float w = ldv(val, e);
-    if constexpr (FILT) w *= dscale[(int)(((double)c + 0.5) * inv_nt)];
-    acc.fma(w, src + (int64_t)c * C + cb);
+  return r;
+}
+
+template <int CPL>
+__device__ __forceinline__ void store_vec(float2* p, const Vec<CPL>& r) {
+  if constexpr (CPL == 1) {
+    *p = make_float2(r.v[0], r.v[1]);
+  } else {
+#pragma unroll
+    for (int h = 0; h < CPL / 2; ++h)
+      reinterpret_cast<float4*>(p)[h] =
+          make_float4(r.v[4 * h], r.v[4 * h + 1], r.v[4 * h + 2], r.v[4 * h + 3]);
   }
 }
 
+template <int CPL>
+__device__ __forceinline__ void vzero(Vec<CPL>& a) {
+#pragma unroll
+  for (int i = 0; i < 2 * CPL; ++i) a.v[i] = 0.f;
+}
+
+// One round: entries base + u*stride for u < count (count <= U).  Entries with a negative column
+// are padding and contribute nothing.
+template <int CPL, int U, typename V, bool FILT>
+__device__ __forceinline__ void gather_round(const int32_t* __restrict__ col,
+                                             const V* __restrict__ val, int base,
+                                             int stride, int count,
+                                             const float2* __restrict__ src, int C, int cb,
+                                             const float* __restrict__ dscale, double inv_nt,
+                                             Vec<CPL>& acc) {
+  int c[U];
+  float w[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    c[u] = -1;
+    w[u] = 0.f;
+    if (u < count) {
+      const int e = base + u * stride;   // entry indices fit in 32 bits (checked at build)
+      c[u] = col[e];
+      w[u] = ldv(val, e);
+    }
+  }
+  if constexpr (FILT) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c[u] >= 0) w[u] *= dscale[(int)(((double)c[u] + 0.5) * inv_nt)];
+  }
+  Vec<CPL> x[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (c[u] >= 0)
+      x[u] = load_vec<CPL>(src + (int64_t)c[u] * C + cb);
+    else
+      vzero(x[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int i = 0; i < 2 * CPL; ++i) acc.v[i] += w[u] * x[u].v[i];
+}
+
 // ------------------------------------------------------------------------------------------
-// forward: Y = S^dagger X
+// forward: Y = S^dagger X with a constant row stride W2
 // ------------------------------------------------------------------------------------------
-template <int T, int CPL, typename V>
-__global__ __launch_bounds__(kBlock) void k_spmm_fwd(const int32_t* __restrict__ rowptr,
-                                                     const int32_t* __restrict__ col,
-                                                     const V* __restrict__ val,
-                                                     const float2* __restrict__ X,
-                                                     float2* __restrict__ Y, int64_t nrows, int C) {
-  constexpr int RPB = kBlock / T;
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int64_t row = xcd_remap(blockIdx.x, gridDim.x) * RPB + g;
+template <int CPL, typename V, int W2>
+__global__ __launch_bounds__(kBlock) void k_fwd_ell(const int32_t* __restrict__ col,
+                                                    const V* __restrict__ val,
+                                                    const float2* __restrict__ X,
+                                                    float2* __restrict__ Y, int64_t nrows, int C,
+                                                    int logT, int w2_runtime) {
+  const int g = threadIdx.x >> logT, t = threadIdx.x & ((1 << logT) - 1);
+  const int64_t row = xcd_remap(blockIdx.x, gridDim.x) * (kBlock >> logT) + g;
   const int cb = t * CPL;
   if (row >= nrows || cb >= C) return;
-  Acc<CPL> acc;
-  acc.zero();
-  row_dot<CPL, V, false>(col, val, X, C, cb, rowptr[row], rowptr[row + 1], 1, nullptr, 0.0, acc);
-  acc.store(Y + row * C + cb);
+  Vec<CPL> acc;
+  vzero(acc);
+  if constexpr (W2 > 0) {
+    gather_round<CPL, W2, V, false>(col, val, (int)row * W2, 1, W2, X, C, cb, nullptr, 0.0, acc);
+  } else {
+    for (int e = 0; e < w2_runtime; e += kRound)
+      gather_round<CPL, kRound, V, false>(col, val, (int)row * w2_runtime + e, 1,
+                                          min(kRound, w2_runtime - e), X, C, cb, nullptr, 0.0, acc);
+  }
+  store_vec(Y + row * C + cb, acc);
 }
 
 // ------------------------------------------------------------------------------------------
-// adjoint: X = S diag(d) Y, row-binned
+// adjoint: X = S diag(d) Y
 // ------------------------------------------------------------------------------------------
 struct AdjArgs {
-  const int32_t* rowptr;
+  const int32_t* slice_ptr;
+  const int32_t* slice_rows;
   const int32_t* col;
+  int64_t n_slices, nb_sell;
+  const int32_t* tail_rows;
+  const int32_t* tail_ptr;
+  const int32_t* tail_col;
+  int64_t n_medium, nb_medium;
+  const int32_t* chunk_beg;
+  const int32_t* chunk_end;
+  int64_t n_chunks;
+  float2* partials;
   const float2* Y;
   float2* X;
-  int C;
-  const int32_t* short_rows;  int64_t n_short;  int64_t nb_short;
-  const int32_t* medium_rows; int64_t n_medium; int64_t nb_medium;
-  const int32_t* chunk_beg;   const int32_t* chunk_end; int64_t n_chunks;
-  float2* partials;
+  int C, logT;
   const float* dscale;        // per FFT-ordered radial index, or null
   double inv_nt;              // 1 / n_theta: radial index of polar column c is floor(c / nt)
 };
 
-template <int T, int CPL, typename V, bool FILT>
-__global__ __launch_bounds__(kBlock) void k_spmm_adj(AdjArgs a, const V* __restrict__ val) {
-  constexpr int RPB = kBlock / T;     // lane groups per block
-  constexpr int GPW = 64 / T;         // lane groups per wavefront
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int cb = t * CPL;
-  const bool active = cb < a.C;
-  int64_t bid = blockIdx.x;
-  if (bid < a.nb_short) {
-    bid = xcd_remap(bid, a.nb_short);
-    const int64_t i = bid * RPB + g;
-    if (i >= a.n_short || !active) return;
-    const int64_t row = a.short_rows[i];
-    Acc<CPL> acc;
-    acc.zero();
-    row_dot<CPL, V, FILT>(a.col, val, a.Y, a.C, cb, a.rowptr[row], a.rowptr[row + 1], 1, a.dscale,
-                          a.inv_nt, acc);
-    acc.store(a.X + row * a.C + cb);
-    return;
-  }
-  bid -= a.nb_short;
-  if (bid < a.nb_medium) {
-    const int wave = threadIdx.x >> 6;
-    const int gw = (threadIdx.x & 63) / T;           // lane group within the wavefront
-    const int64_t i = bid * (kBlock / 64) + wave;
-    if (i >= a.n_medium) return;                      // whole wavefront leaves together
-    const int64_t row = a.medium_rows[i];
-    Acc<CPL> acc;
-    acc.zero();
-    if (active)
-      row_dot<CPL, V, FILT>(a.col, val, a.Y, a.C, cb, a.rowptr[row] + gw, a.rowptr[row + 1], GPW,
-                            a.dscale, a.inv_nt, acc);
-#pragma unroll
-    for (int off = T; off < 64; off <<= 1) {
-#pragma unroll
-      for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += __shfl_xor(acc.v[k], off, 64);
-    }
-    if (gw == 0 && active) acc.store(a.X + row * a.C + cb);
-    return;
-  }
-  bid -= a.nb_medium;
-  if (bid >= a.n_chunks) return;
-  // one chunk of a long row: all lane groups of the block share the chunk's entries
-  __shared__ float red[kBlock * 2 * CPL];
-  Acc<CPL> acc;
-  acc.zero();
-  if (active)
-    row_dot<CPL, V, FILT>(a.col, val, a.Y, a.C, cb, (int64_t)a.chunk_beg[bid] + g,
-                          a.chunk_end[bid], RPB, a.dscale, a.inv_nt, acc);
-#pragma unroll
+template <int CPL>
+__device__ __forceinline__ void wave_reduce_groups(Vec<CPL>& acc, int T) {
   for (int off = T; off < 64; off <<= 1) {
 #pragma unroll
     for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += __shfl_xor(acc.v[k], off, 64);
   }
+}
+
+// sliced ELL: one lane group per row slot of a slice
+template <int CPL, typename V, bool FILT>
+__global__ __launch_bounds__(kBlock) void k_adj_sell(AdjArgs a, const V* __restrict__ val) {
+  const int g = threadIdx.x >> a.logT, t = threadIdx.x & ((1 << a.logT) - 1);
+  const int cb = t * CPL;
+  const int64_t gid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock >> a.logT) + g;
+  const int64_t slice = gid / kSliceRows;
+  const int j = (int)(gid % kSliceRows);
+  if (slice >= a.n_slices || cb >= a.C) return;
+  const int32_t e0 = a.slice_ptr[slice];
+  const int len = (a.slice_ptr[slice + 1] - e0) / kSliceRows;
+  const int32_t row = a.slice_rows[gid];
+  Vec<CPL> acc;
+  vzero(acc);
+  for (int e = 0; e < len; e += kRound)
+    gather_round<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j,
+                                       kSliceRows, min(kRound, len - e), a.Y, a.C, cb, a.dscale,
+                                       a.inv_nt, acc);
+  if (row >= 0) store_vec(a.X + (int64_t)row * a.C + cb, acc);
+}
+
+// one wavefront per medium row; lane groups stride the row's entries
+template <int CPL, typename V, bool FILT>
+__global__ __launch_bounds__(kBlock) void k_adj_medium(AdjArgs a, const V* __restrict__ tail_val) {
+  const int T = 1 << a.logT;
+  const int GPW = 64 >> a.logT;
+  const int t = threadIdx.x & (T - 1);
+  const int cb = t * CPL;
+  const bool active = cb < a.C;
+  const int wave = threadIdx.x >> 6;
+  const int gw = (threadIdx.x & 63) >> a.logT;
+  const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+  if (i >= a.n_medium) return;                       // the whole wavefront leaves together
+  const int e1 = a.tail_ptr[i + 1];
+  Vec<CPL> acc;
+  vzero(acc);
+  if (active) {
+    for (int e = a.tail_ptr[i] + gw; e < e1; e += kRound * GPW)
+      gather_round<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, GPW,
+                                         min(kRound, (e1 - e + GPW - 1) / GPW), a.Y,
+                                         a.C, cb, a.dscale, a.inv_nt, acc);
+  }
+  wave_reduce_groups(acc, T);
+  if (gw == 0 && active) store_vec(a.X + (int64_t)a.tail_rows[i] * a.C + cb, acc);
+}
+
+// one block per chunk of a long row: partial sums to the scratch buffer
+template <int CPL, typename V, bool FILT>
+__global__ __launch_bounds__(kBlock) void k_adj_chunk(AdjArgs a, const V* __restrict__ tail_val) {
+  const int T = 1 << a.logT;
+  const int RPB = kBlock >> a.logT;
+  const int g = threadIdx.x >> a.logT, t = threadIdx.x & (T - 1);
+  const int cb = t * CPL;
+  const bool active = cb < a.C;
+  const int64_t bid = blockIdx.x;
+  __shared__ float red[(kBlock / 64) * 256];
+  const int e1 = a.chunk_end[bid];
+  Vec<CPL> acc;
+  vzero(acc);
+  if (active) {
+    for (int e = a.chunk_beg[bid] + g; e < e1; e += kRound * RPB)
+      gather_round<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, RPB,
+                                         min(kRound, (e1 - e + RPB - 1) / RPB), a.Y,
+                                         a.C, cb, a.dscale, a.inv_nt, acc);
+  }
+  wave_reduce_groups(acc, T);
   const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) < T) {
 #pragma unroll
-    for (int k = 0; k < 2 * CPL; ++k) red[(wave * T + t) * 2 * CPL + k] = acc.v[k];
+    for (int k = 0; k < 2 * CPL; ++k) red[wave * 256 + t * 2 * CPL + k] = acc.v[k];
   }
   __syncthreads();
   if (threadIdx.x < T && active) {
-    Acc<CPL> s;
-    s.zero();
+    Vec<CPL> s;
+    vzero(s);
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w)
 #pragma unroll
-      for (int k = 0; k < 2 * CPL; ++k) s.v[k] += red[(w * T + t) * 2 * CPL + k];
-    s.store(a.partials + bid * a.C + cb);
+      for (int k = 0; k < 2 * CPL; ++k) s.v[k] += red[w * 256 + t * 2 * CPL + k];
+    store_vec(a.partials + bid * a.C + cb, s);
   }
 }
 
-template <int T, int CPL>
-__global__ __launch_bounds__(kBlock) void k_adj_long_reduce(const int32_t* __restrict__ long_rows,
+// X[row] = sum of the row's chunk partials, in chunk order
+template <int CPL>
+__global__ __launch_bounds__(kBlock) void k_adj_long_reduce(const int32_t* __restrict__ tail_rows,
                                                             const int32_t* __restrict__ chunk_ptr,
                                                             const float2* __restrict__ partials,
-                                                            float2* __restrict__ X, int64_t n_long,
-                                                            int C) {
-  constexpr int RPB = kBlock / T;
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int64_t i = (int64_t)blockIdx.x * RPB + g;
+                                                            float2* __restrict__ X, int64_t n_medium,
+                                                            int64_t n_long, int C, int logT) {
+  const int g = threadIdx.x >> logT, t = threadIdx.x & ((1 << logT) - 1);
+  const int64_t li = (int64_t)blockIdx.x * (kBlock >> logT) + g;
   const int cb = t * CPL;
-  if (i >= n_long || cb >= C) return;
-  Acc<CPL> acc;
-  acc.zero();
-  for (int c = chunk_ptr[i]; c < chunk_ptr[i + 1]; ++c) acc.fma(1.0f, partials + (int64_t)c * C + cb);
-  acc.store(X + (int64_t)long_rows[i] * C + cb);
+  if (li >= n_long || cb >= C) return;
+  Vec<CPL> acc;
+  vzero(acc);
+  for (int c = chunk_ptr[li]; c < chunk_ptr[li + 1]; ++c) {
+    const Vec<CPL> p = load_vec<CPL>(partials + (int64_t)c * C + cb);
+#pragma unroll
+    for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += p.v[k];
+  }
+  store_vec(X + (int64_t)tail_rows[n_medium + li] * C + cb, acc);
 }
 
 // ------------------------------------------------------------------------------------------
-// dispatch over (T, CPL, value type)
+// dispatch
 // ------------------------------------------------------------------------------------------
-inline int next_pow2(int v) {
-  int p = 1;
-  while (p < v) p <<= 1;
-  return p;
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
 }
 
-template <int T, int CPL, typename V>
+// Largest valid channels-per-lane not above the preference: CPL must divide C (so that every
+// lane's vector is whole and 16-byte aligned when CPL >= 2), and lane groups are <= 64 wide.
+inline int pick_cpl(int pref, int C) {
+  for (int cpl = pref; cpl >= 1; cpl >>= 1)
+    if (C % cpl == 0 && (C + cpl - 1) / cpl <= 64) return cpl;
+  return 0;
+}
+
+template <int CPL, typename V>
 tomo_status fwd_impl(const tomo_op* op, const void* val, const float2* X, float2* Y, int C,
                      hipStream_t st) {
+  const int logT = ilog2((C + CPL - 1) / CPL);
   const int64_t rows = op->fwd.rows;
-  constexpr int RPB = kBlock / T;
-  const int64_t nb = (rows + RPB - 1) / RPB;
-  hipLaunchKernelGGL((k_spmm_fwd<T, CPL, V>), dim3((unsigned)nb), dim3(kBlock), 0, st,
-                     op->fwd.rowptr, op->fwd.col, (const V*)val, X, Y, rows, C);
+  const int64_t rpb = kBlock >> logT;
+  const int64_t nb = (rows + rpb - 1) / rpb;
+  const int W2 = op->fwd.W2;
+  if (W2 == 9)
+    hipLaunchKernelGGL((k_fwd_ell<CPL, V, 9>), dim3((unsigned)nb), dim3(kBlock), 0, st,
+                       op->fwd.col, (const V*)val, X, Y, rows, C, logT, W2);
+  else
+    hipLaunchKernelGGL((k_fwd_ell<CPL, V, 0>), dim3((unsigned)nb), dim3(kBlock), 0, st,
+                       op->fwd.col, (const V*)val, X, Y, rows, C, logT, W2);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
 
-template <int T, int CPL, typename V>
-tomo_status adj_impl(const tomo_op* op, const void* val, const float2* Y, float2* X, int C,
+template <int CPL, typename V>
+tomo_status adj_impl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
                      const float* dscale, hipStream_t st) {
-  constexpr int RPB = kBlock / T;
+  const DevAdj& d = op->adj;
   AdjArgs a;
-  a.rowptr = op->adj.rowptr;
-  a.col = op->adj.col;
+  a.logT = ilog2((C + CPL - 1) / CPL);
+  const int64_t rpb = kBlock >> a.logT;
+  a.slice_ptr = d.slice_ptr;
+  a.slice_rows = d.slice_rows;
+  a.col = d.col;
+  a.n_slices = d.n_slices;
+  a.nb_sell = (d.n_slices * kSliceRows + rpb - 1) / rpb;
+  a.tail_rows = d.tail_rows;
+  a.tail_ptr = d.tail_ptr;
+  a.tail_col = d.tail_col;
+  a.n_medium = d.n_medium;
+  a.nb_medium = (d.n_medium + (kBlock / 64) - 1) / (kBlock / 64);
+  a.chunk_beg = d.chunk_beg;
+  a.chunk_end = d.chunk_end;
+  a.n_chunks = d.n_chunks;
+  a.partials = op->partials;
   a.Y = Y;
   a.X = X;
   a.C = C;
-  a.short_rows = op->bins.short_rows;
-  a.n_short = op->bins.n_short;
-  a.nb_short = (a.n_short + RPB - 1) / RPB;
-  a.medium_rows = op->bins.medium_rows;
-  a.n_medium = op->bins.n_medium;
-  a.nb_medium = (a.n_medium + (kBlock / 64) - 1) / (kBlock / 64);
-  a.chunk_beg = op->bins.chunk_beg;
-  a.chunk_end = op->bins.chunk_end;
-  a.n_chunks = op->bins.n_chunks;
-  a.partials = op->partials;
   a.dscale = dscale;
   a.inv_nt = 1.0 / (double)op->g.nt;
-  const int64_t nb = a.nb_short + a.nb_medium + a.n_chunks;
-  if (nb > 0) {
-    if (dscale)
-      hipLaunchKernelGGL((k_spmm_adj<T, CPL, V, true>), dim3((unsigned)nb), dim3(kBlock), 0, st, a,
-                         (const V*)val);
-    else
-      hipLaunchKernelGGL((k_spmm_adj<T, CPL, V, false>), dim3((unsigned)nb), dim3(kBlock), 0, st,
-                         a, (const V*)val);
-    TOMO_HIP(hipGetLastError());
+  const V* v = (const V*)d.val[vt];
+  const V* tv = (const V*)d.tail_val[vt];
+#define TOMO_ADJ_LAUNCH(KERNEL, NB, VALS)                                                     \
+  if ((NB) > 0) {                                                                          \
+    if (dscale)                                                                            \
+      hipLaunchKernelGGL((KERNEL<CPL, V, true>), dim3((unsigned)(NB)), dim3(kBlock), 0, st, a, VALS); \
+    else                                                                                   \
+      hipLaunchKernelGGL((KERNEL<CPL, V, false>), dim3((unsigned)(NB)), dim3(kBlock), 0, st, a, VALS); \
+    TOMO_HIP(hipGetLastError());                                                           \
   }
-  if (op->bins.n_long > 0) {
-    const int64_t nbl = (op->bins.n_long + RPB - 1) / RPB;
-    hipLaunchKernelGGL((k_adj_long_reduce<T, CPL>), dim3((unsigned)nbl), dim3(kBlock), 0, st,
-                       op->bins.long_rows, op->bins.long_chunk_ptr, op->partials, X,
-                       op->bins.n_long, C);
+  TOMO_ADJ_LAUNCH(k_adj_sell, a.nb_sell, v)
+  TOMO_ADJ_LAUNCH(k_adj_medium, a.nb_medium, tv)
+  TOMO_ADJ_LAUNCH(k_adj_chunk, a.n_chunks, tv)
+#undef TOMO_ADJ_LAUNCH
+  if (d.n_long > 0) {
+    const int64_t nbl = (d.n_long + rpb - 1) / rpb;
+    hipLaunchKernelGGL((k_adj_long_reduce<CPL>), dim3((unsigned)nbl), dim3(kBlock), 0, st,
+                       d.tail_rows, d.long_chunk_ptr, op->partials, X, d.n_medium, d.n_long, C,
+                       a.logT);
     TOMO_HIP(hipGetLastError());
   }
   return TOMO_OK;
 }
 
-template <bool FWD, typename V>
-tomo_status dispatch_T(const tomo_op* op, const void* val, const float2* in, float2* out, int C,
-                       const float* dscale, hipStream_t st) {
-  const int CPL = (C % 2 == 0) ? 2 : 1;
-  const int T = next_pow2((C + CPL - 1) / CPL);
-#define TOMO_CASE(TT, CC)                                                              \
-  if (T == TT && CPL == CC) {                                                          \
-    if (FWD) return fwd_impl<TT, CC, V>(op, val, in, out, C, st);                       \
-    return adj_impl<TT, CC, V>(op, val, in, out, C, dscale, st);                        \
+template <typename V>
+tomo_status fwd_cpl(const tomo_op* op, const void* val, const float2* X, float2* Y, int C,
+                    hipStream_t st) {
+  switch (pick_cpl(op->tune.fwd_cpl, C)) {
+    case 1: return fwd_impl<1, V>(op, val, X, Y, C, st);
+    case 2: return fwd_impl<2, V>(op, val, X, Y, C, st);
+    case 4: return fwd_impl<4, V>(op, val, X, Y, C, st);
+    default: return fail(TOMO_EINVAL, "channel count %d not supported", C);
   }
-  TOMO_CASE(1, 1) TOMO_CASE(2, 1) TOMO_CASE(4, 1) TOMO_CASE(8, 1) TOMO_CASE(16, 1)
-  TOMO_CASE(32, 1) TOMO_CASE(64, 1)
-  TOMO_CASE(1, 2) TOMO_CASE(2, 2) TOMO_CASE(4, 2) TOMO_CASE(8, 2) TOMO_CASE(16, 2)
-  TOMO_CASE(32, 2) TOMO_CASE(64, 2)
-#undef TOMO_CASE
-  return fail(TOMO_EINVAL, "channel count %d not supported", C);
 }
 
-template <bool FWD>
-tomo_status dispatch(const tomo_op* op, int vt, const float2* in, float2* out, int C,
-                     const float* dscale, hipStream_t st) {
-  const DevCSR& m = FWD ? op->fwd : op->adj;
-  if (vt < 0 || vt > 2 || !m.val[vt])
-    return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
-  if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
-  switch (vt) {
-    case TOMO_VAL_F32: return dispatch_T<FWD, float>(op, m.val[vt], in, out, C, dscale, st);
-    case TOMO_VAL_BF16: return dispatch_T<FWD, bf16_t>(op, m.val[vt], in, out, C, dscale, st);
-    default: return dispatch_T<FWD, _Float16>(op, m.val[vt], in, out, C, dscale, st);
+template <typename V>
+tomo_status adj_cpl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
+                    const float* dscale, hipStream_t st) {
+  switch (pick_cpl(op->tune.adj_cpl, C)) {
+    case 1: return adj_impl<1, V>(op, vt, Y, X, C, dscale, st);
+    case 2: return adj_impl<2, V>(op, vt, Y, X, C, dscale, st);
+    case 4: return adj_impl<4, V>(op, vt, Y, X, C, dscale, st);
+    default: return fail(TOMO_EINVAL, "channel count %d not supported", C);
   }
 }
 
@@ -327,12 +398,27 @@ tomo_status dispatch(const tomo_op* op, int vt, const float2* in, float2* out, i
 
 tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
                             hipStream_t st) {
-  return dispatch<true>(op, vt, X, Y, C, nullptr, st);
+  if (vt < 0 || vt > 2 || !op->fwd.val[vt])
+    return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
+  if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
+  switch (vt) {
+    case TOMO_VAL_F32: return fwd_cpl<float>(op, op->fwd.val[vt], X, Y, C, st);
+    case TOMO_VAL_BF16: return fwd_cpl<bf16_t>(op, op->fwd.val[vt], X, Y, C, st);
+    default: return fwd_cpl<_Float16>(op, op->fwd.val[vt], X, Y, C, st);
+  }
 }
 
 tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
                             const float* dscale, hipStream_t st) {
-  return dispatch<false>(op, vt, Y, X, C, dscale, st);
+  if (vt < 0 || vt > 2 || !(op->values & (1u << vt)))
+    return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
+  if (!op->adj_ready) return fail(TOMO_ESTATE, "adjoint layout unavailable (failed re-tuning)");
+  if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
+  switch (vt) {
+    case TOMO_VAL_F32: return adj_cpl<float>(op, vt, Y, X, C, dscale, st);
+    case TOMO_VAL_BF16: return adj_cpl<bf16_t>(op, vt, Y, X, C, dscale, st);
+    default: return adj_cpl<_Float16>(op, vt, Y, X, C, dscale, st);
+  }
 }
 
 }  // namespace tomo

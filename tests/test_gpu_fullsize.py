@@ -61,7 +61,7 @@ def test_fullsize_spmm_sampled_rows(big, ref):
     Xg2 = big.slice_adj(torch.from_numpy(Yc).cuda(), B)
     torch.cuda.synchronize()
     lens = np.diff(ref.S.indptr)[cm]                               # library row order
-    long_rows = np.nonzero(lens > big.info.adj_medium_max)[0]
+    long_rows = np.nonzero(lens > big.get_tuning()["adj_medium_max"])[0]
     rows2 = np.unique(np.concatenate([rng.choice(g.G * g.G, 4000, replace=False), long_rows]))
     Xref = _sampled_rows_ref(ref.S, cm[rows2], pm_inv, Ylib)
     X = Xg2.cpu().numpy()[rows2]

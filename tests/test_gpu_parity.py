@@ -188,3 +188,38 @@ def test_gpu_determinism_and_batch_edges(tomo):
         ys = _host(op.project(x3[s:s + 1].contiguous()))
         assert rel_l2(ys[0], y3[s]) < 1e-6
     op.close()
+
+
+TUNINGS = [
+    dict(fwd_channels_per_lane=1, adj_channels_per_lane=1),
+    dict(fwd_channels_per_lane=4, adj_channels_per_lane=4),
+    dict(adj_sell_max=0, adj_medium_max=0, adj_chunk=8),          # every row chunked
+    dict(adj_sell_max=1024, adj_medium_max=1024),                 # every row in sliced ELL
+    dict(adj_sell_max=4, adj_medium_max=16, adj_chunk=24, adj_sell_sigma=1),
+]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: "_".join(f"{k}{v}" for k, v in t.items()))
+@pytest.mark.parametrize("batch", [7, 16, 32])
+def test_slice_spmm_tunings(tomo, tuning, batch):
+    """Every kernel layout the tuning space allows gives the oracle's CSR products."""
+    n, nt, npb = 64, 90, 91
+    op = tomo.Operator(n, nt, npb, max_batch=32, values=("f32", "bf16"), device=0)
+    op.set_tuning(**tuning)
+    ref = oracle_op(n, nt, npb)
+    g = ref.geom
+    C = (batch + 1) // 2
+    cm, pm = cart_map(g), polar_row_map(g)
+    Xc = _rand((g.G * g.G, C, 2), 500 + batch)
+    Xo = np.empty((g.G * g.G, C), dtype=np.complex128)
+    Xo[cm] = Xc[..., 0] + 1j * Xc[..., 1]
+    assert rel_l2(complex_channels(op.slice_fwd(_dev(Xc), batch)), (ref.S_dag @ Xo)[pm]) < 1e-6
+    Yc = _rand((g.L * nt, C, 2), 600 + batch)
+    Yo = np.empty((g.L * nt, C), dtype=np.complex128)
+    Yo[pm] = Yc[..., 0] + 1j * Yc[..., 1]
+    Xa = op.slice_adj(_dev(Yc), batch)
+    assert rel_l2(complex_channels(Xa), (ref.S @ Yo)[cm]) < 1e-6
+    assert torch.equal(op.slice_adj(_dev(Yc), batch), Xa)
+    lo = round_values(ref.S, "bf16")
+    assert rel_l2(complex_channels(op.slice_adj(_dev(Yc), batch, values="bf16")), (lo @ Yo)[cm]) < 1e-6
+    op.close()

@@ -82,17 +82,34 @@ def test_factors_match_oracle(d):
     op.close()
 
 
-def test_row_bins_partition_rows():
+@pytest.mark.parametrize("tuning", [{}, dict(adj_sell_max=8, adj_medium_max=40, adj_chunk=16),
+                                    dict(adj_sell_max=0, adj_medium_max=0, adj_chunk=64),
+                                    dict(adj_sell_sigma=1)])
+def test_row_bins_partition_rows(tuning):
     op = tomo.Operator(device=-1, max_batch=2, n=64, n_angles=90, n_det=91)
+    t = op.set_tuning(**tuning)
     info = op.info
     rpt, _, _ = op.export_csr(1)
     lens = np.diff(rpt)
-    assert info.adj_bin_rows[0] == np.sum(lens <= info.adj_short_max)
-    assert info.adj_bin_rows[1] == np.sum((lens > info.adj_short_max) & (lens <= info.adj_medium_max))
-    assert info.adj_bin_rows[2] == np.sum(lens > info.adj_medium_max)
-    long = lens[lens > info.adj_medium_max]
-    assert info.adj_long_chunks == int(np.sum(np.ceil(long / info.adj_chunk)))
+    sm, mm, ch = t["adj_sell_max"], t["adj_medium_max"], t["adj_chunk"]
+    assert info.adj_sell_rows == np.sum(lens <= sm)
+    assert info.adj_medium_rows == np.sum((lens > sm) & (lens <= mm))
+    assert info.adj_long_rows == np.sum(lens > mm)
+    long = lens[lens > mm]
+    assert info.adj_long_chunks == int(np.sum(np.ceil(long / ch)))
     assert info.cols_touched == np.sum(lens > 0)
+    assert info.adj_sell_padding >= 0
+    op.close()
+
+
+def test_tuning_rejects_out_of_range():
+    op = tomo.Operator(device=-1, max_batch=2, n=16, n_angles=12, n_det=23)
+    before = op.get_tuning()
+    for bad in (dict(fwd_channels_per_lane=3), dict(adj_sell_max=-1), dict(adj_chunk=4),
+                dict(adj_medium_max=10, adj_sell_max=20), dict(adj_sell_sigma=0)):
+        with pytest.raises(tomo.TomoError):
+            op.set_tuning(**bad)
+        assert op.get_tuning() == before
     op.close()
 
 
