@@ -117,7 +117,8 @@ typedef struct {
 } tomo_op_info;
 
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
- * Defaults: 2, 2, 16, 4096, 256, 256. */
+ * Staged kernels are used when their LDS footprint fits 64 KiB, else the row kernels.
+ * Defaults: 2, 2, 16, 4096, 256, 256, 0, 0, 16, 256, 4. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -128,6 +129,15 @@ typedef struct {
                                      many rows (>= 1; 1 = natural order)                       */
   int32_t adj_medium_max;         /* longer rows up to this many entries: one wavefront each  */
   int32_t adj_chunk;              /* rows above that: chunks of this many entries (8..8192)   */
+  int32_t fwd_tiled;              /* 1: forward SpMM stages Cartesian tiles (+ halo) in LDS;
+                                     0: one lane group per row with every tap gathered from L2 */
+  int32_t adj_tiled;              /* 1: adjoint SpMM stages each output tile's polar rows in LDS
+                                     in chunks; 0: the row-binned layouts above                */
+  int32_t tile;                   /* Cartesian tile side of the staged kernels: 8, 16 or 32   */
+  int32_t tile_points;            /* forward: samples per block; adjoint: polar rows staged per
+                                     chunk (multiple of 32, 32..1024)                          */
+  int32_t tile_chunks;            /* adjoint: chunks one block accumulates before a tile is
+                                     split into partial sums (1..64)                           */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */
@@ -216,6 +226,12 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out);
  * the parameters except through float32 summation order.  Errors: TOMO_EINVAL (out of range;
  * the operator is unchanged), TOMO_ENOMEM. */
 tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* t);
+
+/* Host self-check (no device access): rebuild every kernel layout for the current tuning on
+ * the host, apply each one in float64 following the kernels' traversal, and report the largest
+ * relative difference from the CSR products in *max_rel_err (about 1e-16 when correct; NaN if
+ * some output row would not be written). */
+tomo_status tomo_check_layouts(const tomo_op* op, double* max_rel_err);
 
 /* Free everything the operator owns (synchronises its device first).  NULL is a no-op. */
 void tomo_destroy_operator(tomo_op* op);

@@ -54,7 +54,9 @@ class tomo_op_info(ctypes.Structure):
 class tomo_tuning(ctypes.Structure):
     _fields_ = [("fwd_channels_per_lane", ctypes.c_int32), ("adj_channels_per_lane", ctypes.c_int32),
                 ("adj_sell_max", ctypes.c_int32), ("adj_sell_sigma", ctypes.c_int32),
-                ("adj_medium_max", ctypes.c_int32), ("adj_chunk", ctypes.c_int32)]
+                ("adj_medium_max", ctypes.c_int32), ("adj_chunk", ctypes.c_int32),
+                ("fwd_tiled", ctypes.c_int32), ("adj_tiled", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("tile_points", ctypes.c_int32), ("tile_chunks", ctypes.c_int32)]
 
 
 class tomo_solve_opts(ctypes.Structure):
@@ -78,6 +80,7 @@ SIGNATURES = {
     "tomo_op_info_get": (ctypes.c_int, [_P, ctypes.POINTER(tomo_op_info)]),
     "tomo_export_csr": (ctypes.c_int, [_P, _I, _P, _P, _P]),
     "tomo_export_factors": (ctypes.c_int, [_P, _I, _P, _P]),
+    "tomo_check_layouts": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "tomo_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(tomo_tuning)]),
     "tomo_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(tomo_tuning)]),
     "tomo_destroy_operator": (None, [_P]),
@@ -208,6 +211,12 @@ class Operator:
         _check(_lib.tomo_set_tuning(self._handle, ctypes.byref(t)))
         self.info = self.op_info()
         return self.get_tuning()
+
+    def check_layouts(self) -> float:
+        """``tomo_check_layouts``: host replay of every kernel layout against the CSR products."""
+        err = ctypes.c_double()
+        _check(_lib.tomo_check_layouts(self._handle, ctypes.byref(err)))
+        return err.value
 
     def export_factors(self, filter: str = "none"):
         import numpy as np

@@ -116,7 +116,70 @@ tomo_status upload_adj(tomo_op* op) {
   return TOMO_OK;
 }
 
+void free_tiles(tomo_op* op) {
+  DevFwdTiles& f = op->ftile;
+  dfree(f.wi_tile); dfree(f.wi_beg); dfree(f.pt_row); dfree(f.pt_slot);
+  for (auto& v : f.val) dfree(v);
+  f = DevFwdTiles();
+  DevAdjTiles& a = op->atile;
+  dfree(a.wi_tile); dfree(a.wi_cb); dfree(a.wi_ce); dfree(a.wi_out);
+  dfree(a.ch_pt_beg); dfree(a.ch_pts); dfree(a.ch_row_off); dfree(a.en_slot);
+  for (auto& v : a.en_val) dfree(v);
+  dfree(a.red_tile); dfree(a.red_beg); dfree(a.red_cnt);
+  a = DevAdjTiles();
+  dfree(op->tile_partials);
+}
+
+// (Re)build the LDS-staged layouts for op->tune on the host and upload them.
+tomo_status upload_tiles(tomo_op* op) {
+  op->tiles_ready = false;
+  free_tiles(op);
+  {
+    HostFwdTiles h;
+    TOMO_TRY(build_fwd_tiles(op->g, op->sdag, op->centres, op->tune, &h));
+    DevFwdTiles& d = op->ftile;
+    d.n_wi = (int64_t)h.wi_tile.size();
+    d.TS = h.TS; d.PS = h.PS; d.NT = h.NT; d.WS = h.WS;
+    TOMO_TRY(upload(&d.wi_tile, h.wi_tile.data(), h.wi_tile.size()));
+    TOMO_TRY(upload(&d.wi_beg, h.wi_beg.data(), h.wi_beg.size()));
+    TOMO_TRY(upload(&d.pt_row, h.pt_row.data(), h.pt_row.size()));
+    TOMO_TRY(upload(&d.pt_slot, h.pt_slot.data(), h.pt_slot.size()));
+    TOMO_TRY(upload_values(h.pt_val, op->g.values, d.val));
+  }
+  {
+    HostAdjTiles h;
+    TOMO_TRY(build_adj_tiles(op->g, op->s, op->tune, &h));
+    DevAdjTiles& d = op->atile;
+    d.n_wi = (int64_t)h.wi_tile.size();
+    d.n_red = (int64_t)h.red_tile.size();
+    d.n_pslots = h.n_pslots;
+    d.TS = h.TS; d.NT = h.NT; d.qmax = op->tune.tile_points; d.emax = std::max(1, h.emax);
+    TOMO_TRY(upload(&d.wi_tile, h.wi_tile.data(), h.wi_tile.size()));
+    TOMO_TRY(upload(&d.wi_cb, h.wi_chunk_beg.data(), h.wi_chunk_beg.size()));
+    TOMO_TRY(upload(&d.wi_ce, h.wi_chunk_end.data(), h.wi_chunk_end.size()));
+    TOMO_TRY(upload(&d.wi_out, h.wi_out.data(), h.wi_out.size()));
+    TOMO_TRY(upload(&d.ch_pt_beg, h.ch_pt_beg.data(), h.ch_pt_beg.size()));
+    TOMO_TRY(upload(&d.ch_pts, h.ch_pts.data(), h.ch_pts.size()));
+    TOMO_TRY(upload(&d.ch_row_off, h.ch_row_off.data(), h.ch_row_off.size()));
+    TOMO_TRY(upload(&d.en_slot, h.en_slot.data(), h.en_slot.size()));
+    TOMO_TRY(upload_values(h.en_val, op->g.values, d.en_val));
+    TOMO_TRY(upload(&d.red_tile, h.red_tile.data(), h.red_tile.size()));
+    TOMO_TRY(upload(&d.red_beg, h.red_beg.data(), h.red_beg.size()));
+    TOMO_TRY(upload(&d.red_cnt, h.red_cnt.data(), h.red_cnt.size()));
+    if (d.n_pslots > 0) {
+      const size_t pb = (size_t)d.n_pslots * d.TS * d.TS * op->cmax * sizeof(float2);
+      if (hipMalloc((void**)&op->tile_partials, pb) != hipSuccess) {
+        op->tile_partials = nullptr;
+        return fail(TOMO_ENOMEM, "tile partial sums (%zu B)", pb);
+      }
+    }
+  }
+  op->tiles_ready = true;
+  return TOMO_OK;
+}
+
 void free_device(tomo_op* op) {
+  free_tiles(op);
   destroy_plans(op);
   free_solver(op);
   dfree(op->fwd.col);
@@ -126,6 +189,8 @@ void free_device(tomo_op* op) {
   for (auto& f : op->filt_dev) dfree(f);
   dfree(op->X);
   dfree(op->Y);
+  dfree(op->Xs);
+  dfree(op->Ys);
 }
 
 tomo_status upload_all(tomo_op* op) {
@@ -140,6 +205,7 @@ tomo_status upload_all(tomo_op* op) {
     TOMO_TRY(upload_values(ell.val, g.values, op->fwd.val));
   }
   TOMO_TRY(upload_adj(op));
+  TOMO_TRY(upload_tiles(op));
   std::vector<float> kdf(op->kd.begin(), op->kd.end());
   TOMO_TRY(upload(&op->kd_dev, kdf.data(), kdf.size()));
   for (int f = TOMO_FILTER_RAMLAK; f <= TOMO_FILTER_HAMMING; ++f) {
@@ -157,6 +223,14 @@ tomo_status upload_all(tomo_op* op) {
   if (hipMalloc((void**)&op->Y, yb) != hipSuccess) {
     op->Y = nullptr;
     return fail(TOMO_ENOMEM, "polar workspace (%zu B)", yb);
+  }
+  if (hipMalloc((void**)&op->Xs, xb) != hipSuccess) {
+    op->Xs = nullptr;
+    return fail(TOMO_ENOMEM, "Cartesian FFT workspace (%zu B)", xb);
+  }
+  if (hipMalloc((void**)&op->Ys, yb) != hipSuccess) {
+    op->Ys = nullptr;
+    return fail(TOMO_ENOMEM, "polar FFT workspace (%zu B)", yb);
   }
   TOMO_HIP(hipDeviceSynchronize());
   return TOMO_OK;
@@ -184,29 +258,37 @@ tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int3
 
 }  // namespace
 
+// project: embed + deapodise -> F2D -> S^dagger -> F1D^-1 -> crop (Eq. (2), first line)
 tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st) {
+  const Geom& g = op->g;
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
-  TOMO_TRY(launch_embed(op, x, op->X, B, st));
-  TOMO_TRY(fft_exec(p->fwd2, p, op->X, st));
+  TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
+  TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  TOMO_TRY(launch_to_channel_fastest(op->Xs, op->X, (int64_t)g.G * g.G, C, st));
   TOMO_TRY(launch_spmm_fwd(op, op->X, op->Y, C, vt, st));
-  TOMO_TRY(fft_exec(p->inv1, p, op->Y, st));
-  TOMO_TRY(launch_crop_sino(op, op->Y, y, B, 1.0f / (float)op->g.L, st));
+  TOMO_TRY(launch_polar_to_slowest(op->Y, op->Ys, g.L, g.nt, C, st));
+  TOMO_TRY(fft_exec(p->inv1, p, op->Ys, st));
+  TOMO_TRY(launch_crop_sino(op, op->Ys, y, B, 1.0f / (float)g.L, st));
   return TOMO_OK;
 }
 
+// backproject: pad -> F1D -> S diag(D) -> F2D^H -> crop + deapodise (Eq. (2), second line)
 tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
                               float extra_scale, hipStream_t st) {
+  const Geom& g = op->g;
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
-  TOMO_TRY(launch_pad_sino(op, y, op->Y, B, st));
-  TOMO_TRY(fft_exec(p->fwd1, p, op->Y, st));
+  TOMO_TRY(launch_pad_sino(op, y, op->Ys, B, st));
+  TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
+  TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
   const float* ds = (filter == TOMO_FILTER_NONE) ? nullptr : op->filt_dev[filter];
   TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
-  TOMO_TRY(fft_exec(p->inv2, p, op->X, st));
-  TOMO_TRY(launch_crop_image(op, op->X, x, B, extra_scale / (float)op->g.L, st));
+  TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
+  TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
+  TOMO_TRY(launch_crop_image(op, op->Xs, x, B, extra_scale / (float)g.L, st));
   return TOMO_OK;
 }
 
@@ -224,7 +306,7 @@ tomo_status tomo_build_operator(const tomo_geometry* gin, int device, tomo_op** 
   if (!op) return fail(TOMO_ENOMEM, "host allocation failed");
   TOMO_TRY(resolve_geometry(gin, &op->g));
   try {
-    build_sdag(op->g, &op->sdag);
+    build_sdag(op->g, &op->sdag, &op->centres);
     transpose_csr(op->sdag, &op->s);
     deapod_factors(op->g, &op->kd);
     if (device < 0) build_adj_layout(op->s, op->tune, &op->hadj);
@@ -382,6 +464,12 @@ tomo_status tomo_export_factors(const tomo_op* op, int32_t filter, double* kd, d
   return TOMO_OK;
 }
 
+tomo_status tomo_check_layouts(const tomo_op* op, double* max_rel_err) {
+  clear_error();
+  if (!op || !max_rel_err) return fail(TOMO_EINVAL, "NULL argument");
+  return check_layouts(op->g, op->sdag, op->s, op->centres, op->tune, max_rel_err);
+}
+
 tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   clear_error();
   if (!op || !out) return fail(TOMO_EINVAL, "NULL argument");
@@ -391,6 +479,11 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->adj_sell_sigma = op->tune.sell_sigma;
   out->adj_medium_max = op->tune.medium_max;
   out->adj_chunk = op->tune.chunk;
+  out->fwd_tiled = op->tune.fwd_tiled;
+  out->adj_tiled = op->tune.adj_tiled;
+  out->tile = op->tune.tile;
+  out->tile_points = op->tune.tile_points;
+  out->tile_chunks = op->tune.tile_chunks;
   return TOMO_OK;
 }
 
@@ -404,19 +497,26 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.sell_sigma = in->adj_sell_sigma;
   t.medium_max = in->adj_medium_max;
   t.chunk = in->adj_chunk;
+  t.fwd_tiled = in->fwd_tiled;
+  t.adj_tiled = in->adj_tiled;
+  t.tile = in->tile;
+  t.tile_points = in->tile_points;
+  t.tile_chunks = in->tile_chunks;
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
+  const bool retile = t.tile != op->tune.tile || t.tile_points != op->tune.tile_points ||
+                      t.tile_chunks != op->tune.tile_chunks;
   op->tune = t;
-  if (!relayout) return TOMO_OK;
   if (op->device < 0) {
-    build_adj_layout(op->s, op->tune, &op->hadj);
+    if (relayout) build_adj_layout(op->s, op->tune, &op->hadj);
     return TOMO_OK;
   }
+  if (!relayout && !retile) return TOMO_OK;
   DeviceGuard guard(op->device);
   TOMO_HIP(hipDeviceSynchronize());
-  const tomo_status st = upload_adj(op);
-  if (st != TOMO_OK) return st;
+  if (relayout) TOMO_TRY(upload_adj(op));
+  if (retile) TOMO_TRY(upload_tiles(op));
   TOMO_HIP(hipDeviceSynchronize());
   return TOMO_OK;
 }

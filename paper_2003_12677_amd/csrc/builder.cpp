@@ -127,7 +127,7 @@ double kernel_value(double t, int W, double beta) {
   return bessel_i0_minus_1(arg) / bessel_i0_minus_1(beta);
 }
 
-void build_sdag(const Geom& g, HostCSR* out) {
+void build_sdag(const Geom& g, HostCSR* out, std::vector<int32_t>* centres) {
   const int64_t N = (int64_t)g.nt * g.L;
   const int64_t M = (int64_t)g.G * g.G;
   const int W = g.kw, h = g.h;
@@ -144,6 +144,7 @@ void build_sdag(const Geom& g, HostCSR* out) {
   out->val.clear();
   out->col.reserve((size_t)N * W * W);
   out->val.reserve((size_t)N * W * W);
+  if (centres) centres->assign((size_t)N * 2, INT32_MIN);
   std::vector<std::pair<int32_t, double>> ent;
   std::vector<double> w1(W), w2(W);
   std::vector<int64_t> j1s(W), j2s(W);
@@ -157,6 +158,10 @@ void build_sdag(const Geom& g, HostCSR* out) {
         const double q2 = ((double)k * scale) * st[a];
         const double c1 = std::nearbyint(q1);   // round half to even
         const double c2 = std::nearbyint(q2);
+        if (centres) {
+          (*centres)[(size_t)r * 2] = (int32_t)c1;
+          (*centres)[(size_t)r * 2 + 1] = (int32_t)c2;
+        }
         for (int s = -h; s <= h; ++s) {
           j1s[s + h] = (int64_t)c1 + s;
           j2s[s + h] = (int64_t)c2 + s;
@@ -222,6 +227,12 @@ void build_ell(const HostCSR& a, int W2, HostEll* out) {
 
 tomo_status check_tuning(const Tuning& t) {
   auto cpl_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
+  if ((t.fwd_tiled != 0 && t.fwd_tiled != 1) || (t.adj_tiled != 0 && t.adj_tiled != 1))
+    return fail(TOMO_EINVAL, "fwd_tiled / adj_tiled must be 0 or 1");
+  if (t.tile != 8 && t.tile != 16 && t.tile != 32) return fail(TOMO_EINVAL, "tile must be 8, 16 or 32");
+  if (t.tile_points < 32 || t.tile_points > 1024 || t.tile_points % 32 != 0)
+    return fail(TOMO_EINVAL, "tile_points must be a multiple of 32 in [32, 1024]");
+  if (t.tile_chunks < 1 || t.tile_chunks > 64) return fail(TOMO_EINVAL, "tile_chunks must be in [1, 64]");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
     return fail(TOMO_EINVAL, "channels per lane must be 1, 2 or 4 (got %d, %d)", t.fwd_cpl, t.adj_cpl);
   if (t.sell_max < 0 || t.sell_max > 1024) return fail(TOMO_EINVAL, "sell_max %d not in [0, 1024]", t.sell_max);
@@ -299,6 +310,259 @@ void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* o) {
     }
     o->long_chunk_ptr.push_back((int32_t)o->chunk_beg.size());
   }
+}
+
+namespace {
+// centred frequency of an FFT-ordered index
+inline int centred(int64_t f, int G, int oG) { return (f <= G - 1 - oG) ? (int)f : (int)(f - G); }
+// tile index along one axis of the centred coordinate j
+inline int tile_of(int j, int oG, int TS) { return (j + oG) / TS; }
+}  // namespace
+
+tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
+                            const Tuning& t, HostFwdTiles* o) {
+  *o = HostFwdTiles();
+  const int G = g.G, oG = G / 2, TS = t.tile, h = g.h;
+  o->TS = TS;
+  o->PS = TS + 2 * h;
+  o->NT = (G + TS - 1) / TS;
+  o->W2 = g.kw * g.kw;
+  o->WS = (o->W2 + 3) / 4 * 4;
+  if ((int64_t)o->PS * o->PS > 0xFFFF) return fail(TOMO_EINVAL, "tile patch too large for 16-bit slots");
+  const int64_t N = sdag.rows;
+  const int ntiles = o->NT * o->NT;
+  const int origin_tile = tile_of(0, oG, TS) * o->NT + tile_of(0, oG, TS);
+  std::vector<int32_t> tile_of_row(N);
+  std::vector<int64_t> count(ntiles + 1, 0);
+  for (int64_t r = 0; r < N; ++r) {
+    int tl = origin_tile;   // rows without a window (unpaired Nyquist sample) still write zeros
+    const int32_t c1 = centres[(size_t)r * 2], c2 = centres[(size_t)r * 2 + 1];
+    if (c1 != INT32_MIN) {
+      const int t1 = std::min(std::max(tile_of(c1, oG, TS), 0), o->NT - 1);
+      const int t2 = std::min(std::max(tile_of(c2, oG, TS), 0), o->NT - 1);
+      tl = t1 * o->NT + t2;
+    }
+    tile_of_row[r] = tl;
+    count[tl + 1]++;
+  }
+  for (int i = 0; i < ntiles; ++i) count[i + 1] += count[i];
+  std::vector<int32_t> order(N);
+  {
+    std::vector<int64_t> next(count.begin(), count.end() - 1);
+    for (int64_t r = 0; r < N; ++r) order[next[tile_of_row[r]]++] = (int32_t)r;
+  }
+  o->pt_row = order;
+  o->pt_slot.assign((size_t)N * o->WS, 0xFFFF);
+  o->pt_val.assign((size_t)N * o->WS, 0.0);
+  o->wi_beg.push_back(0);
+  for (int tl = 0; tl < ntiles; ++tl) {
+    const int j01 = -oG + (tl / o->NT) * TS - h, j02 = -oG + (tl % o->NT) * TS - h;   // patch origin
+    for (int64_t i = count[tl]; i < count[tl + 1]; ++i) {
+      const int64_t r = order[i];
+      int s = 0;
+      for (int64_t e = sdag.rowptr[r]; e < sdag.rowptr[r + 1]; ++e, ++s) {
+        const int j1 = centred(sdag.col[e] / G, G, oG), j2 = centred(sdag.col[e] % G, G, oG);
+        const int p1 = j1 - j01, p2 = j2 - j02;
+        if (p1 < 0 || p1 >= o->PS || p2 < 0 || p2 >= o->PS)
+          return fail(TOMO_EINVAL, "internal: tap outside its tile patch (row %lld)", (long long)r);
+        o->pt_slot[(size_t)i * o->WS + s] = (uint16_t)(p1 * o->PS + p2);
+        o->pt_val[(size_t)i * o->WS + s] = sdag.val[e];
+      }
+    }
+    for (int64_t b = count[tl]; b < count[tl + 1]; b += t.tile_points) {
+      o->wi_tile.push_back(tl);
+      o->wi_beg.push_back((int32_t)std::min<int64_t>(b + t.tile_points, count[tl + 1]));
+    }
+  }
+  return TOMO_OK;
+}
+
+tomo_status build_adj_tiles(const Geom& g, const HostCSR& s, const Tuning& t, HostAdjTiles* o) {
+  *o = HostAdjTiles();
+  const int G = g.G, oG = G / 2, TS = t.tile;
+  o->TS = TS;
+  o->NT = (G + TS - 1) / TS;
+  const int R = TS * TS;
+  std::vector<int32_t> cols;
+  std::vector<int64_t> rows(R);
+  o->ch_pt_beg.push_back(0);
+  for (int t1 = 0; t1 < o->NT; ++t1) {
+    for (int t2 = 0; t2 < o->NT; ++t2) {
+      const int tl = t1 * o->NT + t2;
+      // the tile's output rows (library row index, -1 outside the grid)
+      cols.clear();
+      for (int a = 0; a < TS; ++a)
+        for (int b = 0; b < TS; ++b) {
+          const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
+          int64_t m = -1;
+          if (j1 <= G - 1 - oG && j2 <= G - 1 - oG)
+            m = (int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G);
+          rows[a * TS + b] = m;
+          if (m >= 0)
+            for (int64_t e = s.rowptr[m]; e < s.rowptr[m + 1]; ++e) cols.push_back(s.col[e]);
+        }
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      const int nch = (int)((cols.size() + t.tile_points - 1) / t.tile_points);
+      const int first_chunk = (int)o->ch_pt_beg.size() - 1;
+      for (int c = 0; c < nch; ++c) {
+        const size_t q0 = (size_t)c * t.tile_points;
+        const size_t q1 = std::min(cols.size(), q0 + (size_t)t.tile_points);
+        o->ch_pts.insert(o->ch_pts.end(), cols.begin() + q0, cols.begin() + q1);
+        o->ch_pt_beg.push_back((int32_t)o->ch_pts.size());
+        const int32_t lo = cols[q0], hi = cols[q1 - 1];
+        for (int rr = 0; rr < R; ++rr) {
+          o->ch_row_off.push_back((int32_t)o->en_slot.size());
+          const int64_t m = rows[rr];
+          if (m < 0) continue;
+          // the row's columns are sorted, so its entries inside [lo, hi] are one run
+          const int32_t* cb = s.col.data() + s.rowptr[m];
+          const int32_t* ce = s.col.data() + s.rowptr[m + 1];
+          const int32_t* it = std::lower_bound(cb, ce, lo);
+          for (; it != ce && *it <= hi; ++it) {
+            const size_t q = (size_t)(std::lower_bound(cols.begin() + q0, cols.begin() + q1, *it) - cols.begin());
+            o->en_slot.push_back((uint16_t)(q - q0));
+            o->en_val.push_back(s.val[s.rowptr[m] + (it - cb)]);
+          }
+        }
+        o->ch_row_off.push_back((int32_t)o->en_slot.size());
+        o->emax = std::max(o->emax, (int)(o->en_slot.size() - o->ch_row_off[o->ch_row_off.size() - R - 1]));
+      }
+      // work items: runs of <= kch chunks; a tile needing several writes partial sums
+      const int nwi = std::max(1, (nch + t.tile_chunks - 1) / t.tile_chunks);
+      if (nwi > 1) {
+        o->red_tile.push_back(tl);
+        o->red_beg.push_back((int32_t)o->n_pslots);
+        o->red_cnt.push_back(nwi);
+      }
+      for (int w = 0; w < nwi; ++w) {
+        o->wi_tile.push_back(tl);
+        o->wi_chunk_beg.push_back(first_chunk + std::min(nch, w * t.tile_chunks));
+        o->wi_chunk_end.push_back(first_chunk + std::min(nch, (w + 1) * t.tile_chunks));
+        o->wi_out.push_back(nwi > 1 ? (int32_t)(o->n_pslots++) : -1);
+      }
+    }
+  }
+  if (o->en_slot.size() >= (size_t)INT32_MAX) return fail(TOMO_EINVAL, "tile layout too large");
+  return TOMO_OK;
+}
+
+// Host replay of every kernel layout in float64, following the kernels' traversal, against the
+// CSR products; returns the largest relative difference (a self-check of the layout builders).
+tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
+                          const std::vector<int32_t>& centres, const Tuning& t, double* max_rel) {
+  const int64_t N = sdag.rows, M = s.rows;
+  const int G = g.G, oG = G / 2;
+  std::vector<double> x(M), y(N);
+  uint64_t st = 88172645463325252ull;   // xorshift64
+  auto rnd = [&]() { st ^= st << 13; st ^= st >> 7; st ^= st << 17; return (double)(st >> 11) / 9007199254740992.0 - 0.5; };
+  for (auto& v : x) v = rnd();
+  for (auto& v : y) v = rnd();
+  std::vector<double> yf(N, 0.0), xa(M, 0.0);
+  for (int64_t r = 0; r < N; ++r)
+    for (int64_t e = sdag.rowptr[r]; e < sdag.rowptr[r + 1]; ++e) yf[r] += sdag.val[e] * x[sdag.col[e]];
+  for (int64_t r = 0; r < M; ++r)
+    for (int64_t e = s.rowptr[r]; e < s.rowptr[r + 1]; ++e) xa[r] += s.val[e] * y[s.col[e]];
+  auto rel = [](const std::vector<double>& a, const std::vector<double>& b) {
+    double num = 0, den = 0;
+    for (size_t i = 0; i < a.size(); ++i) { num += (a[i] - b[i]) * (a[i] - b[i]); den += b[i] * b[i]; }
+    return std::sqrt(num / (den > 0 ? den : 1.0));
+  };
+  double worst = 0;
+  {  // fixed-stride forward
+    HostEll ell;
+    build_ell(sdag, g.kw * g.kw, &ell);
+    std::vector<double> out(N, 0.0);
+    for (int64_t r = 0; r < N; ++r)
+      for (int k = 0; k < ell.W2; ++k) {
+        const int32_t c = ell.col[(size_t)r * ell.W2 + k];
+        if (c >= 0) out[r] += ell.val[(size_t)r * ell.W2 + k] * x[c];
+      }
+    worst = std::max(worst, rel(out, yf));
+  }
+  {  // row-binned adjoint
+    HostAdj h;
+    build_adj_layout(s, t, &h);
+    std::vector<double> out(M, std::nan(""));
+    const int64_t ns = (int64_t)h.slice_ptr.size() - 1;
+    for (int64_t i = 0; i < ns; ++i) {
+      const int len = (h.slice_ptr[i + 1] - h.slice_ptr[i]) / kSliceRows;
+      for (int j = 0; j < kSliceRows; ++j) {
+        const int32_t row = h.slice_rows[i * kSliceRows + j];
+        double acc = 0;
+        for (int e = 0; e < len; ++e) {
+          const size_t k = (size_t)h.slice_ptr[i] + (size_t)e * kSliceRows + j;
+          if (h.col[k] >= 0) acc += h.val[k] * y[h.col[k]];
+        }
+        if (row >= 0) out[row] = acc;
+      }
+    }
+    for (size_t i = 0; i < h.tail_rows.size(); ++i) {
+      double acc = 0;
+      for (int32_t e = h.tail_ptr[i]; e < h.tail_ptr[i + 1]; ++e) acc += h.tail_val[e] * y[h.tail_col[e]];
+      out[h.tail_rows[i]] = acc;
+    }
+    worst = std::max(worst, rel(out, xa));
+  }
+  {  // staged forward
+    HostFwdTiles f;
+    TOMO_TRY(build_fwd_tiles(g, sdag, centres, t, &f));
+    std::vector<double> out(N, std::nan(""));
+    for (size_t w = 0; w < f.wi_tile.size(); ++w) {
+      const int tl = f.wi_tile[w];
+      const int j01 = -oG + (tl / f.NT) * f.TS - g.h, j02 = -oG + (tl % f.NT) * f.TS - g.h;
+      for (int32_t i = f.wi_beg[w]; i < f.wi_beg[w + 1]; ++i) {
+        double acc = 0;
+        for (int k = 0; k < f.WS; ++k) {
+          const uint16_t sl = f.pt_slot[(size_t)i * f.WS + k];
+          if (sl == 0xFFFF) continue;
+          const int g1 = ((j01 + sl / f.PS) % G + G) % G, g2 = ((j02 + sl % f.PS) % G + G) % G;
+          acc += f.pt_val[(size_t)i * f.WS + k] * x[(int64_t)g1 * G + g2];
+        }
+        out[f.pt_row[i]] = acc;
+      }
+    }
+    worst = std::max(worst, rel(out, yf));
+  }
+  {  // staged adjoint
+    HostAdjTiles a;
+    TOMO_TRY(build_adj_tiles(g, s, t, &a));
+    const int R = a.TS * a.TS;
+    std::vector<double> out(M, std::nan(""));
+    std::vector<double> part((size_t)a.n_pslots * R, 0.0);
+    for (size_t w = 0; w < a.wi_tile.size(); ++w) {
+      std::vector<double> acc(R, 0.0);
+      for (int ch = a.wi_chunk_beg[w]; ch < a.wi_chunk_end[w]; ++ch) {
+        const int32_t* off = a.ch_row_off.data() + (size_t)ch * (R + 1);
+        for (int rr = 0; rr < R; ++rr)
+          for (int32_t e = off[rr]; e < off[rr + 1]; ++e) {
+            if ((int)a.en_slot[e] >= a.ch_pt_beg[ch + 1] - a.ch_pt_beg[ch])
+              return fail(TOMO_EINVAL, "internal: entry slot beyond its chunk");
+            acc[rr] += a.en_val[e] * y[a.ch_pts[a.ch_pt_beg[ch] + a.en_slot[e]]];
+          }
+      }
+      const int tl = a.wi_tile[w];
+      for (int rr = 0; rr < R; ++rr) {
+        if (a.wi_out[w] >= 0) { part[(size_t)a.wi_out[w] * R + rr] = acc[rr]; continue; }
+        const int j1 = -oG + (tl / a.NT) * a.TS + rr / a.TS, j2 = -oG + (tl % a.NT) * a.TS + rr % a.TS;
+        if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
+        out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc[rr];
+      }
+    }
+    for (size_t i = 0; i < a.red_tile.size(); ++i) {
+      const int tl = a.red_tile[i];
+      for (int rr = 0; rr < R; ++rr) {
+        const int j1 = -oG + (tl / a.NT) * a.TS + rr / a.TS, j2 = -oG + (tl % a.NT) * a.TS + rr % a.TS;
+        if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
+        double acc = 0;
+        for (int k = 0; k < a.red_cnt[i]; ++k) acc += part[(size_t)(a.red_beg[i] + k) * R + rr];
+        out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc;
+      }
+    }
+    worst = std::max(worst, rel(out, xa));
+  }
+  *max_rel = worst;   // NaN if some output row was never written
+  return TOMO_OK;
 }
 
 void deapod_factors(const Geom& g, std::vector<double>* kd) {

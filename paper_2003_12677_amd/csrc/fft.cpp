@@ -1,8 +1,7 @@
-// rocFFT plans for the two Fourier steps of Eq. (2), on the channel-fastest layouts:
-//   2D: X[G][G][C] complex64, transforms over (g1, g2) with strides (G*C, C), C batches at
-//       distance 1 (the Cartesian grid F2D and its adjoint);
-//   1D: Y[L][nt][C] complex64, transforms over k with stride nt*C, nt*C batches at distance 1
-//       (F1D along each radial line).
+// rocFFT plans for the two Fourier steps of Eq. (2), on the channel-slowest buffers, so every
+// transform is a contiguous batch:
+//   2D: Xs[C][G][G] complex64, C transforms of G x G (the Cartesian grid F2D and its adjoint);
+//   1D: Ys[C][nt][L] complex64, C*nt transforms of length L (F1D along each radial line).
 // Both are in place and unnormalised (forward e^{-2 pi i}, backward e^{+2 pi i}); the 1/L of
 // the detector-side inverse is applied by the crop kernels.  Plans are created on first use for
 // each channel count and kept until the operator is destroyed (Sec. 3.1: plans cached until
@@ -46,16 +45,19 @@ tomo_status get_plans(tomo_op* op, int C, FFTPlans** out) {
   const Geom& g = op->g;
   FFTPlans p;
   const size_t len2[2] = {(size_t)g.G, (size_t)g.G};           // fastest dimension first
-  const size_t str2[2] = {(size_t)C, (size_t)g.G * C};
+  const size_t str2[2] = {1, (size_t)g.G};
+  const size_t dist2 = (size_t)g.G * g.G;
   const size_t len1[1] = {(size_t)g.L};
-  const size_t str1[1] = {(size_t)g.nt * C};
-  tomo_status st = make_plan(&p.fwd2, rocfft_transform_type_complex_forward, 2, len2, str2, 1, C);
+  const size_t str1[1] = {1};
+  const size_t dist1 = (size_t)g.L;
+  const size_t batch1 = (size_t)g.nt * C;
+  tomo_status st = make_plan(&p.fwd2, rocfft_transform_type_complex_forward, 2, len2, str2, dist2, C);
   if (st == TOMO_OK)
-    st = make_plan(&p.inv2, rocfft_transform_type_complex_inverse, 2, len2, str2, 1, C);
+    st = make_plan(&p.inv2, rocfft_transform_type_complex_inverse, 2, len2, str2, dist2, C);
   if (st == TOMO_OK)
-    st = make_plan(&p.fwd1, rocfft_transform_type_complex_forward, 1, len1, str1, 1, (size_t)g.nt * C);
+    st = make_plan(&p.fwd1, rocfft_transform_type_complex_forward, 1, len1, str1, dist1, batch1);
   if (st == TOMO_OK)
-    st = make_plan(&p.inv1, rocfft_transform_type_complex_inverse, 1, len1, str1, 1, (size_t)g.nt * C);
+    st = make_plan(&p.inv1, rocfft_transform_type_complex_inverse, 1, len1, str1, dist1, batch1);
   if (st == TOMO_OK) {
     size_t w = 0;
     for (rocfft_plan pl : {p.fwd2, p.inv2, p.fwd1, p.inv1}) {

@@ -62,6 +62,11 @@ struct Tuning {
   int sell_sigma = 4096;  // rows are sorted by length within windows of sell_sigma rows
   int medium_max = 256;   // longer rows up to medium_max entries: one wavefront per row
   int chunk = 256;        // rows above medium_max: chunks of <= chunk entries, one block each
+  int fwd_tiled = 0;      // forward: 1 = LDS-staged Cartesian tiles, 0 = row kernel
+  int adj_tiled = 0;      // adjoint: 1 = LDS-staged polar chunks per output tile, 0 = row kernels
+  int tile = 16;          // Cartesian tile side of the staged kernels (8, 16 or 32)
+  int tile_points = 256;  // forward: samples per block; adjoint: polar rows staged per chunk
+  int tile_chunks = 4;    // adjoint: chunks one block accumulates before writing
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
@@ -86,13 +91,45 @@ struct HostAdj {
   std::vector<int32_t> chunk_beg, chunk_end, long_chunk_ptr;   // into the tail entries
 };
 
+// Forward, LDS-staged: polar samples grouped by the Cartesian tile (side TS) that holds their
+// window centre; a block stages the tile plus a halo of h = (k_w-1)/2 (patch side PS = TS + 2h)
+// and reads every tap from LDS.  Tap s of sample i is patch slot pt_slot[i*W2 + s] (0xFFFF: none).
+struct HostFwdTiles {
+  int TS = 0, PS = 0, NT = 0, W2 = 0, WS = 0;   // WS: tap stride (W2 rounded up to 4)
+  std::vector<int32_t> wi_tile, wi_beg;    // [n_wi], [n_wi + 1] into the sample list
+  std::vector<int32_t> pt_row;             // polar row of each sample
+  std::vector<uint16_t> pt_slot;           // [P][WS]
+  std::vector<double> pt_val;              // [P][WS]
+};
+
+// Adjoint, LDS-staged: for each Cartesian output tile the polar rows its entries reference are
+// staged in chunks of <= qmax rows; a block accumulates up to kch chunks for the tile's TS*TS
+// rows and writes them to X (wi_out = -1) or to partial-sum slot wi_out, later reduced in order.
+struct HostAdjTiles {
+  int TS = 0, NT = 0;
+  std::vector<int32_t> wi_tile, wi_chunk_beg, wi_chunk_end, wi_out;   // [n_wi]
+  std::vector<int32_t> ch_pt_beg;          // [n_chunks + 1] into ch_pts
+  std::vector<int32_t> ch_pts;             // staged polar rows
+  std::vector<int32_t> ch_row_off;         // [n_chunks][TS*TS + 1] into the entries
+  std::vector<uint16_t> en_slot;           // LDS slot (position in the chunk) of each entry
+  std::vector<double> en_val;
+  std::vector<int32_t> red_tile, red_beg, red_cnt;   // tiles summed from partial slots
+  int64_t n_pslots = 0;
+  int emax = 0;                            // most entries in one chunk
+};
+
 tomo_status resolve_geometry(const tomo_geometry* in, Geom* g);
 double kernel_value(double t, int W, double beta);
-void build_sdag(const Geom& g, HostCSR* sdag);
+void build_sdag(const Geom& g, HostCSR* sdag, std::vector<int32_t>* centres = nullptr);
+tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
+                            const Tuning& t, HostFwdTiles* out);
+tomo_status build_adj_tiles(const Geom& g, const HostCSR& s, const Tuning& t, HostAdjTiles* out);
 void transpose_csr(const HostCSR& a, HostCSR* at);
 void build_ell(const HostCSR& a, int W2, HostEll* out);
 tomo_status check_tuning(const Tuning& t);
 void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* out);
+tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
+                          const std::vector<int32_t>& centres, const Tuning& t, double* max_rel);
 void deapod_factors(const Geom& g, std::vector<double>* kd);
 void filter_diagonal(const Geom& g, int filter, std::vector<double>* d);   // FFT-ordered k
 uint16_t f32_to_bf16_rne(float f);
@@ -114,6 +151,24 @@ struct DevAdj {
   int32_t *tail_rows = nullptr, *tail_ptr = nullptr, *tail_col = nullptr;
   void* tail_val[3] = {nullptr, nullptr, nullptr};
   int32_t *chunk_beg = nullptr, *chunk_end = nullptr, *long_chunk_ptr = nullptr;
+};
+
+struct DevFwdTiles {
+  int64_t n_wi = 0;
+  int TS = 0, PS = 0, NT = 0, WS = 0;
+  int32_t *wi_tile = nullptr, *wi_beg = nullptr, *pt_row = nullptr;
+  uint16_t* pt_slot = nullptr;
+  void* val[3] = {nullptr, nullptr, nullptr};
+};
+
+struct DevAdjTiles {
+  int64_t n_wi = 0, n_red = 0, n_pslots = 0;
+  int TS = 0, NT = 0, qmax = 0, emax = 0;
+  int32_t *wi_tile = nullptr, *wi_cb = nullptr, *wi_ce = nullptr, *wi_out = nullptr;
+  int32_t *ch_pt_beg = nullptr, *ch_pts = nullptr, *ch_row_off = nullptr;
+  uint16_t* en_slot = nullptr;
+  void* en_val[3] = {nullptr, nullptr, nullptr};
+  int32_t *red_tile = nullptr, *red_beg = nullptr, *red_cnt = nullptr;
 };
 
 struct FFTPlans {
@@ -148,11 +203,18 @@ struct tomo_op {
   float* kd_dev = nullptr;        // [n]
   float* filt_dev[4] = {nullptr, nullptr, nullptr, nullptr};   // D per tomo_filter, [L]
   int cmax = 0;                   // complex channels the workspace holds
-  float2* X = nullptr;            // [G*G][cmax]
-  float2* Y = nullptr;            // [L*nt][cmax]
+  float2* X = nullptr;            // [G*G][C]     channel-fastest Cartesian grid (SpMM side)
+  float2* Y = nullptr;            // [L*nt][C]    channel-fastest polar data (SpMM side)
+  float2* Xs = nullptr;           // [C][G][G]    channel-slowest Cartesian grid (FFT side)
+  float2* Ys = nullptr;           // [C][nt][L]   channel-slowest polar data (FFT side)
   float2* partials = nullptr;     // [n_chunks][cmax] long-row partial sums
   size_t partials_cap = 0;        // chunks the partials buffer holds
   bool adj_ready = false;         // false while (or after a failed) adjoint layout upload
+  std::vector<int32_t> centres;   // window centre (j1, j2) of every polar row, host
+  tomo::DevFwdTiles ftile;        // LDS-staged forward layout
+  tomo::DevAdjTiles atile;        // LDS-staged adjoint layout
+  float2* tile_partials = nullptr;   // [n_pslots][TS*TS][cmax]
+  bool tiles_ready = false;
   std::map<int, tomo::FFTPlans> plans;   // keyed by channel count C
   tomo::SolverBuffers sb;
 };
@@ -167,16 +229,30 @@ void destroy_plans(tomo_op* op);
 tomo_status fft_exec(rocfft_plan plan, FFTPlans* p, void* data, hipStream_t st);
 
 // kernel launchers (all enqueue on `st`)
-tomo_status launch_embed(const tomo_op* op, const float* x, float2* X, int B, hipStream_t st);
-tomo_status launch_crop_sino(const tomo_op* op, const float2* Y, float* y, int B, float scale,
+tomo_status launch_embed(const tomo_op* op, const float* x, float2* Xs, int B, hipStream_t st);
+tomo_status launch_crop_sino(const tomo_op* op, const float2* Ys, float* y, int B, float scale,
                              hipStream_t st);
-tomo_status launch_pad_sino(const tomo_op* op, const float* y, float2* Y, int B, hipStream_t st);
-tomo_status launch_crop_image(const tomo_op* op, const float2* X, float* x, int B, float scale,
+tomo_status launch_pad_sino(const tomo_op* op, const float* y, float2* Ys, int B, hipStream_t st);
+tomo_status launch_crop_image(const tomo_op* op, const float2* Xs, float* x, int B, float scale,
                               hipStream_t st);
+// channel-slowest <-> channel-fastest:  a[C][P] <-> b[P][C] with P = rows (grid points)
+tomo_status launch_to_channel_fastest(const float2* src, float2* dst, int64_t P, int C, hipStream_t st);
+tomo_status launch_to_channel_slowest(const float2* src, float2* dst, int64_t P, int C, hipStream_t st);
+// polar: Yf[kf][a][C] <-> Ys[C][a][kf]
+tomo_status launch_polar_to_slowest(const float2* Yf, float2* Ys, int L, int nt, int C, hipStream_t st);
+tomo_status launch_polar_to_fastest(const float2* Ys, float2* Yf, int L, int nt, int C, hipStream_t st);
 tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
                             hipStream_t st);
 tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
                             const float* dscale, hipStream_t st);
+
+tomo_status launch_fwd_tile(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
+                            hipStream_t st);
+tomo_status launch_adj_tile(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
+                            const float* dscale, hipStream_t st);
+size_t fwd_tile_lds_bytes(const tomo_op* op, int C);
+size_t adj_tile_lds_bytes(const tomo_op* op, int C);
+constexpr size_t kMaxTileLds = 65536;   // staged kernels are used when their LDS fits this
 
 // composite operators on caller buffers
 tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st);

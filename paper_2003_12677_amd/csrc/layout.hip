@@ -1,10 +1,11 @@
 // Streaming kernels around the FFTs (Sec. 3 Eq. (2)): pairing of real slices into complex
-// channels (Sec. 3.1), deapodisation, the index shifts that put the image origin and the
-// rotation axis at index 0 (so plain FFTs compute the centred transforms), zero padding,
-// cropping and the slice-major <-> channel-fastest transposes.  Each block stages a
-// 64-point x 32-slice tile in LDS so that both the slice-major side (256-byte runs per
-// slice) and the channel-fastest side (128-byte runs per point) are read and written in
-// contiguous segments.
+// channels (Sec. 3.1: channel c = slice 2c + i slice 2c+1), deapodisation, the index shifts that
+// put the image origin and the rotation axis at index 0 (so plain FFTs compute the centred
+// transforms), zero padding and cropping.
+//
+// The FFTs run on channel-slowest buffers (Xs[C][G][G], Ys[C][nt][L]: contiguous batched
+// transforms), the SpMMs on channel-fastest ones (X[G*G][C], Y[L*nt][C]: one cache line per
+// gathered column), so LDS-tiled transposes convert between the two.
 
 #include <hip/hip_runtime.h>
 
@@ -13,127 +14,147 @@
 namespace tomo {
 namespace {
 
-constexpr int kTile = 64;   // grid points per block
-constexpr int kCh = 16;     // complex channels (= 32 real slices) per block
+constexpr int kTP = 64;    // points per transpose tile
+constexpr int kTC = 16;    // channels per transpose tile
 
-// x[B][n][n] -> X[G][G][C]:  X[(i1-on) mod G][(i2-on) mod G][c] = kd[i1] kd[i2] (x[2c] + i x[2c+1])
-__global__ __launch_bounds__(256) void k_embed(const float* __restrict__ x, float2* __restrict__ X,
+// x[B][n][n] -> Xs[C][G][G]:  Xs[c][(i1-on) mod G][(i2-on) mod G] = kd[i1] kd[i2] (x[2c] + i x[2c+1])
+__global__ __launch_bounds__(256) void k_embed(const float* __restrict__ x, float2* __restrict__ Xs,
                                                const float* __restrict__ kd, int B, int n, int G,
-                                               int C, int on) {
-  __shared__ float tile[2 * kCh][kTile + 1];
-  const int g1 = blockIdx.y;
-  const int g20 = blockIdx.x * kTile;
-  const int c0 = blockIdx.z * kCh;
-  int i1 = g1 + on;
+                                               int on) {
+  const int g2 = blockIdx.x * 256 + threadIdx.x;
+  const int g1 = blockIdx.y, c = blockIdx.z;
+  if (g2 >= G) return;
+  int i1 = g1 + on, i2 = g2 + on;
   if (i1 >= G) i1 -= G;
-  const bool rowok = i1 < n;
-  const int tt = threadIdx.x & (kTile - 1);
-  const int g2 = g20 + tt;
-  int i2 = g2 + on;
   if (i2 >= G) i2 -= G;
-  const bool ok = rowok && g2 < G && i2 < n;
-  const float k = ok ? kd[i1] * kd[i2] : 0.f;
-  for (int sl = threadIdx.x >> 6; sl < 2 * kCh; sl += 4) {
-    const int s = 2 * c0 + sl;
-    float v = 0.f;
-    if (ok && s < B) v = x[((int64_t)s * n + i1) * n + i2] * k;
-    tile[sl][tt] = v;
+  float2 v = make_float2(0.f, 0.f);
+  if (i1 < n && i2 < n) {
+    const float k = kd[i1] * kd[i2];
+    const int64_t off = (int64_t)i1 * n + i2;
+    v.x = x[(int64_t)(2 * c) * n * n + off] * k;
+    if (2 * c + 1 < B) v.y = x[(int64_t)(2 * c + 1) * n * n + off] * k;
   }
-  __syncthreads();
-  const int nc = min(kCh, C - c0);
-  const int nt = min(kTile, G - g20);
-  float2* out = X + ((int64_t)g1 * G + g20) * C + c0;
-  for (int e = threadIdx.x; e < nt * nc; e += 256) {
-    const int t = e / nc, cl = e - t * nc;
-    out[(int64_t)t * C + cl] = make_float2(tile[2 * cl][t], tile[2 * cl + 1][t]);
-  }
+  Xs[((int64_t)c * G + g1) * G + g2] = v;
 }
 
-// X[G][G][C] -> x[B][n][n]:  x[s][i1][i2] = scale kd[i1] kd[i2] part_s(X[(i1-on) mod G][(i2-on) mod G][s/2])
-__global__ __launch_bounds__(256) void k_crop_image(const float2* __restrict__ X, float* __restrict__ x,
+// Xs[C][G][G] -> x[B][n][n]:  x[s][i1][i2] = scale kd[i1] kd[i2] part_s(Xs[s/2][(i1-on) mod G][(i2-on) mod G])
+__global__ __launch_bounds__(256) void k_crop_image(const float2* __restrict__ Xs, float* __restrict__ x,
                                                     const float* __restrict__ kd, int B, int n, int G,
-                                                    int C, int on, float scale) {
-  __shared__ float tile[2 * kCh][kTile + 1];
-  const int i1 = blockIdx.y;
-  const int i20 = blockIdx.x * kTile;
-  const int c0 = blockIdx.z * kCh;
-  int g1 = i1 - on;
-  if (g1 < 0) g1 += G;
-  const int nc = min(kCh, C - c0);
-  const int nt = min(kTile, n - i20);
-  for (int e = threadIdx.x; e < nt * nc; e += 256) {
-    const int t = e / nc, cl = e - t * nc;
-    int g2 = i20 + t - on;
-    if (g2 < 0) g2 += G;
-    const float2 v = X[((int64_t)g1 * G + g2) * C + c0 + cl];
-    tile[2 * cl][t] = v.x;
-    tile[2 * cl + 1][t] = v.y;
-  }
-  __syncthreads();
-  const int tt = threadIdx.x & (kTile - 1);
-  const int i2 = i20 + tt;
+                                                    int on, float scale) {
+  const int i2 = blockIdx.x * 256 + threadIdx.x;
+  const int i1 = blockIdx.y, c = blockIdx.z;
   if (i2 >= n) return;
+  int g1 = i1 - on, g2 = i2 - on;
+  if (g1 < 0) g1 += G;
+  if (g2 < 0) g2 += G;
+  const float2 v = Xs[((int64_t)c * G + g1) * G + g2];
   const float k = scale * kd[i1] * kd[i2];
-  for (int sl = threadIdx.x >> 6; sl < 2 * nc; sl += 4) {
-    const int s = 2 * c0 + sl;
-    if (s < B) x[((int64_t)s * n + i1) * n + i2] = tile[sl][tt] * k;
-  }
+  const int64_t off = (int64_t)i1 * n + i2;
+  x[(int64_t)(2 * c) * n * n + off] = v.x * k;
+  if (2 * c + 1 < B) x[(int64_t)(2 * c + 1) * n * n + off] = v.y * k;
 }
 
-// Y[L][nt][C] -> y[B][nt][np]:  y[s][a][b] = scale part_s(Y[(b - cdet) mod L][a][s/2])
-__global__ __launch_bounds__(256) void k_crop_sino(const float2* __restrict__ Y, float* __restrict__ y,
-                                                   int B, int nt, int np, int L, int C, int cdet,
-                                                   float scale) {
-  __shared__ float tile[2 * kCh][kTile + 1];
-  const int a = blockIdx.y;
-  const int b0 = blockIdx.x * kTile;
-  const int c0 = blockIdx.z * kCh;
-  const int nc = min(kCh, C - c0);
-  const int nb = min(kTile, np - b0);
-  for (int e = threadIdx.x; e < nb * nc; e += 256) {
-    const int t = e / nc, cl = e - t * nc;
-    int m = b0 + t - cdet;
-    m %= L;
-    if (m < 0) m += L;
-    const float2 v = Y[((int64_t)m * nt + a) * C + c0 + cl];
-    tile[2 * cl][t] = v.x;
-    tile[2 * cl + 1][t] = v.y;
-  }
-  __syncthreads();
-  const int tt = threadIdx.x & (kTile - 1);
-  const int b = b0 + tt;
+// Ys[C][nt][L] -> y[B][nt][np]:  y[s][a][b] = scale part_s(Ys[s/2][a][(b - cdet) mod L])
+__global__ __launch_bounds__(256) void k_crop_sino(const float2* __restrict__ Ys, float* __restrict__ y,
+                                                   int B, int nt, int np, int L, int cdet, float scale) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  const int a = blockIdx.y, c = blockIdx.z;
   if (b >= np) return;
-  for (int sl = threadIdx.x >> 6; sl < 2 * nc; sl += 4) {
-    const int s = 2 * c0 + sl;
-    if (s < B) y[((int64_t)s * nt + a) * np + b] = tile[sl][tt] * scale;
-  }
+  int m = (b - cdet) % L;
+  if (m < 0) m += L;
+  const float2 v = Ys[((int64_t)c * nt + a) * L + m];
+  const int64_t off = (int64_t)a * np + b;
+  y[(int64_t)(2 * c) * nt * np + off] = v.x * scale;
+  if (2 * c + 1 < B) y[(int64_t)(2 * c + 1) * nt * np + off] = v.y * scale;
 }
 
-// y[B][nt][np] -> Y[L][nt][C]:  Y[m][a][c] = y[2c][a][b] + i y[2c+1][a][b], b = (m + cdet) mod L
+// y[B][nt][np] -> Ys[C][nt][L]:  Ys[c][a][m] = y[2c][a][b] + i y[2c+1][a][b], b = (m + cdet) mod L
 // (zero where b >= np or the slice does not exist)
-__global__ __launch_bounds__(256) void k_pad_sino(const float* __restrict__ y, float2* __restrict__ Y,
-                                                  int B, int nt, int np, int L, int C, int cdet) {
-  __shared__ float tile[2 * kCh][kTile + 1];
-  const int a = blockIdx.y;
-  const int m0 = blockIdx.x * kTile;
-  const int c0 = blockIdx.z * kCh;
-  const int tt = threadIdx.x & (kTile - 1);
-  const int m = m0 + tt;
+__global__ __launch_bounds__(256) void k_pad_sino(const float* __restrict__ y, float2* __restrict__ Ys,
+                                                  int B, int nt, int np, int L, int cdet) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  const int a = blockIdx.y, c = blockIdx.z;
+  if (m >= L) return;
   int b = m + cdet;
   if (b >= L) b -= L;
-  const bool ok = m < L && b < np;
-  for (int sl = threadIdx.x >> 6; sl < 2 * kCh; sl += 4) {
-    const int s = 2 * c0 + sl;
-    float v = 0.f;
-    if (ok && s < B) v = y[((int64_t)s * nt + a) * np + b];
-    tile[sl][tt] = v;
+  float2 v = make_float2(0.f, 0.f);
+  if (b < np) {
+    const int64_t off = (int64_t)a * np + b;
+    v.x = y[(int64_t)(2 * c) * nt * np + off];
+    if (2 * c + 1 < B) v.y = y[(int64_t)(2 * c + 1) * nt * np + off];
+  }
+  Ys[((int64_t)c * nt + a) * L + m] = v;
+}
+
+// a[C][P] -> b[P][C], tiles of 64 points x 16 channels through LDS
+__global__ __launch_bounds__(256) void k_to_fastest(const float2* __restrict__ a, float2* __restrict__ b,
+                                                    int64_t P, int C) {
+  __shared__ float2 tile[kTC][kTP + 1];
+  const int64_t p0 = (int64_t)blockIdx.x * kTP;
+  const int c0 = blockIdx.y * kTC;
+  const int nc = min(kTC, C - c0);
+  const int np = (int)min((int64_t)kTP, P - p0);
+  for (int i = threadIdx.x; i < kTC * kTP; i += 256) {
+    const int c = i / kTP, p = i % kTP;
+    if (c < nc && p < np) tile[c][p] = a[(int64_t)(c0 + c) * P + p0 + p];
   }
   __syncthreads();
-  const int nc = min(kCh, C - c0);
-  const int nm = min(kTile, L - m0);
-  for (int e = threadIdx.x; e < nm * nc; e += 256) {
-    const int t = e / nc, cl = e - t * nc;
-    Y[((int64_t)(m0 + t) * nt + a) * C + c0 + cl] = make_float2(tile[2 * cl][t], tile[2 * cl + 1][t]);
+  for (int i = threadIdx.x; i < np * nc; i += 256) {
+    const int p = i / nc, c = i % nc;
+    b[(p0 + p) * C + c0 + c] = tile[c][p];
+  }
+}
+
+// b[P][C] -> a[C][P]
+__global__ __launch_bounds__(256) void k_to_slowest(const float2* __restrict__ b, float2* __restrict__ a,
+                                                    int64_t P, int C) {
+  __shared__ float2 tile[kTC][kTP + 1];
+  const int64_t p0 = (int64_t)blockIdx.x * kTP;
+  const int c0 = blockIdx.y * kTC;
+  const int nc = min(kTC, C - c0);
+  const int np = (int)min((int64_t)kTP, P - p0);
+  for (int i = threadIdx.x; i < np * nc; i += 256) {
+    const int p = i / nc, c = i % nc;
+    tile[c][p] = b[(p0 + p) * C + c0 + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTC * kTP; i += 256) {
+    const int c = i / kTP, p = i % kTP;
+    if (c < nc && p < np) a[(int64_t)(c0 + c) * P + p0 + p] = tile[c][p];
+  }
+}
+
+// Yf[kf][a][C] -> Ys[C][a][kf]
+__global__ __launch_bounds__(256) void k_polar_to_slowest(const float2* __restrict__ Yf,
+                                                          float2* __restrict__ Ys, int L, int nt, int C) {
+  __shared__ float2 tile[kTC][kTP + 1];
+  const int k0 = blockIdx.x * kTP, a = blockIdx.y, c0 = blockIdx.z * kTC;
+  const int nc = min(kTC, C - c0), nk = min(kTP, L - k0);
+  for (int i = threadIdx.x; i < nk * nc; i += 256) {
+    const int k = i / nc, c = i % nc;
+    tile[c][k] = Yf[((int64_t)(k0 + k) * nt + a) * C + c0 + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTC * kTP; i += 256) {
+    const int c = i / kTP, k = i % kTP;
+    if (c < nc && k < nk) Ys[((int64_t)(c0 + c) * nt + a) * L + k0 + k] = tile[c][k];
+  }
+}
+
+// Ys[C][a][kf] -> Yf[kf][a][C]
+__global__ __launch_bounds__(256) void k_polar_to_fastest(const float2* __restrict__ Ys,
+                                                          float2* __restrict__ Yf, int L, int nt, int C) {
+  __shared__ float2 tile[kTC][kTP + 1];
+  const int k0 = blockIdx.x * kTP, a = blockIdx.y, c0 = blockIdx.z * kTC;
+  const int nc = min(kTC, C - c0), nk = min(kTP, L - k0);
+  for (int i = threadIdx.x; i < kTC * kTP; i += 256) {
+    const int c = i / kTP, k = i % kTP;
+    if (c < nc && k < nk) tile[c][k] = Ys[((int64_t)(c0 + c) * nt + a) * L + k0 + k];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nk * nc; i += 256) {
+    const int k = i / nc, c = i % nc;
+    Yf[((int64_t)(k0 + k) * nt + a) * C + c0 + c] = tile[c][k];
   }
 }
 
@@ -141,42 +162,66 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 }  // namespace
 
-tomo_status launch_embed(const tomo_op* op, const float* x, float2* X, int B, hipStream_t st) {
+tomo_status launch_embed(const tomo_op* op, const float* x, float2* Xs, int B, hipStream_t st) {
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
-  dim3 grid(cdiv(g.G, kTile), (unsigned)g.G, cdiv(C, kCh));
-  hipLaunchKernelGGL(k_embed, grid, dim3(256), 0, st, x, X, op->kd_dev, B, g.n, g.G, C, g.on);
+  hipLaunchKernelGGL(k_embed, dim3(cdiv(g.G, 256), (unsigned)g.G, (unsigned)C), dim3(256), 0, st, x,
+                     Xs, op->kd_dev, B, g.n, g.G, g.on);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
 
-tomo_status launch_crop_image(const tomo_op* op, const float2* X, float* x, int B, float scale,
+tomo_status launch_crop_image(const tomo_op* op, const float2* Xs, float* x, int B, float scale,
                               hipStream_t st) {
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
-  dim3 grid(cdiv(g.n, kTile), (unsigned)g.n, cdiv(C, kCh));
-  hipLaunchKernelGGL(k_crop_image, grid, dim3(256), 0, st, X, x, op->kd_dev, B, g.n, g.G, C, g.on,
-                     scale);
+  hipLaunchKernelGGL(k_crop_image, dim3(cdiv(g.n, 256), (unsigned)g.n, (unsigned)C), dim3(256), 0, st,
+                     Xs, x, op->kd_dev, B, g.n, g.G, g.on, scale);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
 
-tomo_status launch_crop_sino(const tomo_op* op, const float2* Y, float* y, int B, float scale,
+tomo_status launch_crop_sino(const tomo_op* op, const float2* Ys, float* y, int B, float scale,
                              hipStream_t st) {
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
-  dim3 grid(cdiv(g.np, kTile), (unsigned)g.nt, cdiv(C, kCh));
-  hipLaunchKernelGGL(k_crop_sino, grid, dim3(256), 0, st, Y, y, B, g.nt, g.np, g.L, C, g.cdet,
-                     scale);
+  hipLaunchKernelGGL(k_crop_sino, dim3(cdiv(g.np, 256), (unsigned)g.nt, (unsigned)C), dim3(256), 0,
+                     st, Ys, y, B, g.nt, g.np, g.L, g.cdet, scale);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
 
-tomo_status launch_pad_sino(const tomo_op* op, const float* y, float2* Y, int B, hipStream_t st) {
+tomo_status launch_pad_sino(const tomo_op* op, const float* y, float2* Ys, int B, hipStream_t st) {
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
-  dim3 grid(cdiv(g.L, kTile), (unsigned)g.nt, cdiv(C, kCh));
-  hipLaunchKernelGGL(k_pad_sino, grid, dim3(256), 0, st, y, Y, B, g.nt, g.np, g.L, C, g.cdet);
+  hipLaunchKernelGGL(k_pad_sino, dim3(cdiv(g.L, 256), (unsigned)g.nt, (unsigned)C), dim3(256), 0, st,
+                     y, Ys, B, g.nt, g.np, g.L, g.cdet);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+tomo_status launch_to_channel_fastest(const float2* src, float2* dst, int64_t P, int C, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_fastest, dim3(cdiv(P, kTP), cdiv(C, kTC)), dim3(256), 0, st, src, dst, P, C);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+tomo_status launch_to_channel_slowest(const float2* src, float2* dst, int64_t P, int C, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_slowest, dim3(cdiv(P, kTP), cdiv(C, kTC)), dim3(256), 0, st, src, dst, P, C);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+tomo_status launch_polar_to_slowest(const float2* Yf, float2* Ys, int L, int nt, int C, hipStream_t st) {
+  hipLaunchKernelGGL(k_polar_to_slowest, dim3(cdiv(L, kTP), (unsigned)nt, cdiv(C, kTC)), dim3(256), 0,
+                     st, Yf, Ys, L, nt, C);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
+tomo_status launch_polar_to_fastest(const float2* Ys, float2* Yf, int L, int nt, int C, hipStream_t st) {
+  hipLaunchKernelGGL(k_polar_to_fastest, dim3(cdiv(L, kTP), (unsigned)nt, cdiv(C, kTC)), dim3(256), 0,
+                     st, Ys, Yf, L, nt, C);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }

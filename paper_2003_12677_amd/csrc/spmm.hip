@@ -401,6 +401,8 @@ tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C
   if (vt < 0 || vt > 2 || !op->fwd.val[vt])
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
+  if (op->tune.fwd_tiled && op->tiles_ready && fwd_tile_lds_bytes(op, C) <= kMaxTileLds)
+    return launch_fwd_tile(op, X, Y, C, vt, st);
   switch (vt) {
     case TOMO_VAL_F32: return fwd_cpl<float>(op, op->fwd.val[vt], X, Y, C, st);
     case TOMO_VAL_BF16: return fwd_cpl<bf16_t>(op, op->fwd.val[vt], X, Y, C, st);
@@ -414,6 +416,8 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (!op->adj_ready) return fail(TOMO_ESTATE, "adjoint layout unavailable (failed re-tuning)");
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
+  if (op->tune.adj_tiled && op->tiles_ready && adj_tile_lds_bytes(op, C) <= kMaxTileLds)
+    return launch_adj_tile(op, Y, X, C, vt, dscale, st);
   switch (vt) {
     case TOMO_VAL_F32: return adj_cpl<float>(op, vt, Y, X, C, dscale, st);
     case TOMO_VAL_BF16: return adj_cpl<bf16_t>(op, vt, Y, X, C, dscale, st);

@@ -190,12 +190,16 @@ def test_gpu_determinism_and_batch_edges(tomo):
     op.close()
 
 
+ROW = dict(fwd_tiled=0, adj_tiled=0)
 TUNINGS = [
-    dict(fwd_channels_per_lane=1, adj_channels_per_lane=1),
-    dict(fwd_channels_per_lane=4, adj_channels_per_lane=4),
-    dict(adj_sell_max=0, adj_medium_max=0, adj_chunk=8),          # every row chunked
-    dict(adj_sell_max=1024, adj_medium_max=1024),                 # every row in sliced ELL
-    dict(adj_sell_max=4, adj_medium_max=16, adj_chunk=24, adj_sell_sigma=1),
+    dict(ROW, fwd_channels_per_lane=1, adj_channels_per_lane=1),
+    dict(ROW, fwd_channels_per_lane=4, adj_channels_per_lane=4),
+    dict(ROW, adj_sell_max=0, adj_medium_max=0, adj_chunk=8),     # every row chunked
+    dict(ROW, adj_sell_max=1024, adj_medium_max=1024),            # every row in sliced ELL
+    dict(ROW, adj_sell_max=4, adj_medium_max=16, adj_chunk=24, adj_sell_sigma=1),
+    dict(tile=8, tile_points=32, tile_chunks=1),                  # staged, many split tiles
+    dict(tile=32, tile_points=64, tile_chunks=2),
+    dict(fwd_tiled=1, adj_tiled=0),
 ]
 
 
