@@ -118,7 +118,7 @@ typedef struct {
 
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB, else the row kernels.
- * Defaults: 2, 2, 16, 4096, 256, 256, 0, 0, 16, 256, 4. */
+ * Defaults: 2, 2, 16, 4096, 256, 256, 0, 0, 8, 128, 1. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -135,7 +135,7 @@ typedef struct {
                                      in chunks; 0: the row-binned layouts above                */
   int32_t tile;                   /* Cartesian tile side of the staged kernels: 8, 16 or 32   */
   int32_t tile_points;            /* forward: samples per block; adjoint: polar rows staged per
-                                     chunk (multiple of 32, 32..1024)                          */
+                                     chunk (32, 64, 96 or 128)                                 */
   int32_t tile_chunks;            /* adjoint: chunks one block accumulates before a tile is
                                      split into partial sums (1..64)                           */
 } tomo_tuning;

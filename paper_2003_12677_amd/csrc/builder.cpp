@@ -230,8 +230,8 @@ tomo_status check_tuning(const Tuning& t) {
   if ((t.fwd_tiled != 0 && t.fwd_tiled != 1) || (t.adj_tiled != 0 && t.adj_tiled != 1))
     return fail(TOMO_EINVAL, "fwd_tiled / adj_tiled must be 0 or 1");
   if (t.tile != 8 && t.tile != 16 && t.tile != 32) return fail(TOMO_EINVAL, "tile must be 8, 16 or 32");
-  if (t.tile_points < 32 || t.tile_points > 1024 || t.tile_points % 32 != 0)
-    return fail(TOMO_EINVAL, "tile_points must be a multiple of 32 in [32, 1024]");
+  if (t.tile_points < 32 || t.tile_points > 128 || t.tile_points % 32 != 0)
+    return fail(TOMO_EINVAL, "tile_points must be 32, 64, 96 or 128");
   if (t.tile_chunks < 1 || t.tile_chunks > 64) return fail(TOMO_EINVAL, "tile_chunks must be in [1, 64]");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
     return fail(TOMO_EINVAL, "channels per lane must be 1, 2 or 4 (got %d, %d)", t.fwd_cpl, t.adj_cpl);

@@ -64,9 +64,9 @@ struct Tuning {
   int chunk = 256;        // rows above medium_max: chunks of <= chunk entries, one block each
   int fwd_tiled = 0;      // forward: 1 = LDS-staged Cartesian tiles, 0 = row kernel
   int adj_tiled = 0;      // adjoint: 1 = LDS-staged polar chunks per output tile, 0 = row kernels
-  int tile = 16;          // Cartesian tile side of the staged kernels (8, 16 or 32)
-  int tile_points = 256;  // forward: samples per block; adjoint: polar rows staged per chunk
-  int tile_chunks = 4;    // adjoint: chunks one block accumulates before writing
+  int tile = 8;           // Cartesian tile side of the staged kernels (8, 16 or 32)
+  int tile_points = 128;  // forward: samples per block; adjoint: polar rows staged per chunk
+  int tile_chunks = 1;    // adjoint: chunks one block accumulates before writing
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
@@ -251,6 +251,7 @@ tomo_status launch_fwd_tile(const tomo_op* op, const float2* X, float2* Y, int C
 tomo_status launch_adj_tile(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
                             const float* dscale, hipStream_t st);
 size_t fwd_tile_lds_bytes(const tomo_op* op, int C);
+bool fwd_tile_supported(const tomo_op* op);
 size_t adj_tile_lds_bytes(const tomo_op* op, int C);
 constexpr size_t kMaxTileLds = 65536;   // staged kernels are used when their LDS fits this
 

@@ -33,12 +33,6 @@ constexpr int kRound = 8;   // entries per round in the adjoint paths
 
 struct bf16_t { uint16_t bits; };
 
-__device__ __forceinline__ float ldv(const float* v, int64_t e) { return v[e]; }
-__device__ __forceinline__ float ldv(const bf16_t* v, int64_t e) {
-  return __uint_as_float((uint32_t)v[e].bits << 16);
-}
-__device__ __forceinline__ float ldv(const _Float16* v, int64_t e) { return (float)v[e]; }
-
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD walks a contiguous
 // range of rows and neighbouring rows (which share gathered columns) share one L2.
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
@@ -87,8 +81,24 @@ __device__ __forceinline__ void vzero(Vec<CPL>& a) {
   for (int i = 0; i < 2 * CPL; ++i) a.v[i] = 0.f;
 }
 
+// raw 16/32-bit value storage, converted after every load of a round has been issued
+__device__ __forceinline__ uint32_t ldraw(const float* v, int e) { return __float_as_uint(v[e]); }
+__device__ __forceinline__ uint32_t ldraw(const bf16_t* v, int e) { return v[e].bits; }
+__device__ __forceinline__ uint32_t ldraw(const _Float16* v, int e) {
+  return *reinterpret_cast<const uint16_t*>(v + e);
+}
+__device__ __forceinline__ float cvt(const float*, uint32_t r) { return __uint_as_float(r); }
+__device__ __forceinline__ float cvt(const bf16_t*, uint32_t r) { return __uint_as_float(r << 16); }
+__device__ __forceinline__ float cvt(const _Float16*, uint32_t r) {
+  const uint16_t h = (uint16_t)r;
+  return (float)*reinterpret_cast<const _Float16*>(&h);
+}
+
 // One round: entries base + u*stride for u < count (count <= U).  Entries with a negative column
-// are padding and contribute nothing.
+// are padding and contribute nothing.  The round is branch-free: every index/value load and
+// every gather is issued unconditionally (padding and out-of-round slots read a valid address
+// and are replaced by zero with a select), so the compiler keeps all of them in flight instead
+// of waiting at each predicated block.
 template <int CPL, int U, typename V, bool FILT>
 __device__ __forceinline__ void gather_round(const int32_t* __restrict__ col,
                                              const V* __restrict__ val, int base,
@@ -97,34 +107,28 @@ __device__ __forceinline__ void gather_round(const int32_t* __restrict__ col,
                                              const float* __restrict__ dscale, double inv_nt,
                                              Vec<CPL>& acc) {
   int c[U];
+  uint32_t raw[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = (u < count) ? base + u * stride : base;   // entry indices fit in 32 bits
+    c[u] = col[e];
+    raw[u] = ldraw(val, e);
+  }
+  bool ok[U];
   float w[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    c[u] = -1;
-    w[u] = 0.f;
-    if (u < count) {
-      const int e = base + u * stride;   // entry indices fit in 32 bits (checked at build)
-      c[u] = col[e];
-      w[u] = ldv(val, e);
-    }
-  }
-  if constexpr (FILT) {
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (c[u] >= 0) w[u] *= dscale[(int)(((double)c[u] + 0.5) * inv_nt)];
+    ok[u] = (u < count) && (c[u] >= 0);
+    w[u] = cvt(val, raw[u]);
+    if constexpr (FILT) w[u] *= dscale[ok[u] ? (int)(((double)c[u] + 0.5) * inv_nt) : 0];
   }
   Vec<CPL> x[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (c[u] >= 0)
-      x[u] = load_vec<CPL>(src + (int64_t)c[u] * C + cb);
-    else
-      vzero(x[u]);
-  }
+  for (int u = 0; u < U; ++u) x[u] = load_vec<CPL>(src + (int64_t)(ok[u] ? c[u] : 0) * C + cb);
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int i = 0; i < 2 * CPL; ++i) acc.v[i] += w[u] * x[u].v[i];
+    for (int i = 0; i < 2 * CPL; ++i) acc.v[i] += w[u] * (ok[u] ? x[u].v[i] : 0.f);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -401,7 +405,8 @@ tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C
   if (vt < 0 || vt > 2 || !op->fwd.val[vt])
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
-  if (op->tune.fwd_tiled && op->tiles_ready && fwd_tile_lds_bytes(op, C) <= kMaxTileLds)
+  if (op->tune.fwd_tiled && op->tiles_ready && fwd_tile_supported(op) &&
+      fwd_tile_lds_bytes(op, C) <= kMaxTileLds)
     return launch_fwd_tile(op, X, Y, C, vt, st);
   switch (vt) {
     case TOMO_VAL_F32: return fwd_cpl<float>(op, op->fwd.val[vt], X, Y, C, st);

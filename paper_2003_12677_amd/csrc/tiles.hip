@@ -93,7 +93,11 @@ struct FwdTileArgs {
   int C, G, oG, TS, PS, NT, h, WS, n_wi;
 };
 
-template <int CPL, typename V, int WS>
+// Staging is written as batches of independent loads into registers followed by LDS stores, so
+// a block pays one memory round trip per batch instead of one per element.
+constexpr int kStageBatch = 8;
+
+template <int CPL, typename V, int WS, int SPG>
 __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __restrict__ val) {
   extern __shared__ float2 patch[];          // [PS*PS][CH]
   constexpr int CH = kLanes * CPL;
@@ -101,40 +105,64 @@ __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __r
   const int c0 = blockIdx.y * CH;
   const int nch = min(CH, a.C - c0);
   const int tl = a.wi_tile[wi];
+  const int b0 = a.wi_beg[wi], b1 = a.wi_beg[wi + 1];
+  const int g = threadIdx.x / kLanes;
+  const int cl = (threadIdx.x % kLanes) * CPL;
+  // this group's samples: indices, taps and weights, loaded before the patch is complete
+  int row[SPG];
+  uint16_t sl[SPG][WS];
+  float w[SPG][WS];
+#pragma unroll
+  for (int q = 0; q < SPG; ++q) {
+    const int i = b0 + g + q * kGroups;
+    row[q] = -1;
+    if (i < b1) {
+      row[q] = a.pt_row[i];
+#pragma unroll
+      for (int s = 0; s < WS; ++s) {
+        sl[q][s] = a.pt_slot[(int64_t)i * WS + s];
+        w[q][s] = ldv(val, (int64_t)i * WS + s);
+      }
+    }
+  }
+  // stage the tile plus halo
   const int j01 = -a.oG + (tl / a.NT) * a.TS - a.h;
   const int j02 = -a.oG + (tl % a.NT) * a.TS - a.h;
   const int PP = a.PS * a.PS;
-  for (int idx = threadIdx.x; idx < PP * kLanes; idx += kBlock) {
-    const int p = idx / kLanes, cl = (idx % kLanes) * CPL;
-    if (cl >= nch) continue;
-    const int g1 = wrap(j01 + p / a.PS, a.G), g2 = wrap(j02 + p % a.PS, a.G);
-    vstore<CPL>(patch + p * CH + cl, vload<CPL>(a.X + ((int64_t)g1 * a.G + g2) * a.C + c0 + cl));
+  for (int base = threadIdx.x; base < PP * kLanes; base += kBlock * kStageBatch) {
+    Vec<CPL> v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int idx = base + u * kBlock;
+      const int p = idx / kLanes, l = (idx % kLanes) * CPL;
+      if (idx < PP * kLanes && l < nch) {
+        const int g1 = wrap(j01 + p / a.PS, a.G), g2 = wrap(j02 + p % a.PS, a.G);
+        v[u] = vload<CPL>(a.X + ((int64_t)g1 * a.G + g2) * a.C + c0 + l);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int idx = base + u * kBlock;
+      const int p = idx / kLanes, l = (idx % kLanes) * CPL;
+      if (idx < PP * kLanes && l < nch) vstore<CPL>(patch + p * CH + l, v[u]);
+    }
   }
   __syncthreads();
-  const int g = threadIdx.x / kLanes;
-  const int cl = (threadIdx.x % kLanes) * CPL;
   if (cl >= nch) return;
-  const int end = a.wi_beg[wi + 1];
-  for (int i = a.wi_beg[wi] + g; i < end; i += kGroups) {
-    const int row = a.pt_row[i];
-    uint16_t sl[WS];
-    float w[WS];
 #pragma unroll
-    for (int s = 0; s < WS; ++s) {
-      sl[s] = a.pt_slot[(int64_t)i * WS + s];
-      w[s] = ldv(val, (int64_t)i * WS + s);
-    }
+  for (int q = 0; q < SPG; ++q) {
+    if (row[q] < 0) continue;
     Vec<CPL> acc;
     vzero(acc);
 #pragma unroll
     for (int s = 0; s < WS; ++s) {
-      if (sl[s] != 0xFFFF) {
-        const Vec<CPL> x = vload<CPL>(patch + sl[s] * CH + cl);
+      if (sl[q][s] != 0xFFFF) {
+        const Vec<CPL> x = vload<CPL>(patch + sl[q][s] * CH + cl);
 #pragma unroll
-        for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += w[s] * x.v[k];
+        for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += w[q][s] * x.v[k];
       }
     }
-    vstore<CPL>(a.Y + (int64_t)row * a.C + c0 + cl, acc);
+    vstore<CPL>(a.Y + (int64_t)row[q] * a.C + c0 + cl, acc);
   }
 }
 
@@ -181,26 +209,57 @@ __global__ __launch_bounds__(kBlock) void k_adj_tile(AdjTileArgs a, const V* __r
 #pragma unroll
     for (int c = 0; c < 2 * CPL; ++c) acc[r][c] = 0.0;
   for (int ch = a.wi_cb[wi]; ch < a.wi_ce[wi]; ++ch) {
-    // stage the chunk: polar rows (times D), entries, row offsets
+    // stage the chunk: polar rows (times D), entries, row offsets; every phase issues a batch
+    // of independent loads before storing to LDS
     const int q0 = a.ch_pt_beg[ch], nq = a.ch_pt_beg[ch + 1] - q0;
-    for (int idx = threadIdx.x; idx < nq * kLanes; idx += kBlock) {
-      const int q = idx / kLanes, l = (idx % kLanes) * CPL;
-      if (l >= nch) continue;
-      const int pcol = a.ch_pts[q0 + q];
-      Vec<CPL> v = vload<CPL>(a.Y + (int64_t)pcol * a.C + c0 + l);
-      if (a.dscale) {
-        const float d = a.dscale[(int)(((double)pcol + 0.5) * a.inv_nt)];
-#pragma unroll
-        for (int k = 0; k < 2 * CPL; ++k) v.v[k] *= d;
-      }
-      vstore<CPL>(pts + q * CH + l, v);
-    }
     const int* off = a.ch_row_off + (int64_t)ch * (R + 1);
     const int e0 = off[0], ne = off[R] - e0;
+    for (int base = threadIdx.x; base < nq * kLanes; base += kBlock * kStageBatch) {
+      int pcol[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int idx = base + u * kBlock;
+        pcol[u] = (idx < nq * kLanes) ? a.ch_pts[q0 + idx / kLanes] : -1;
+      }
+      Vec<CPL> v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int l = ((base + u * kBlock) % kLanes) * CPL;
+        if (pcol[u] >= 0 && l < nch) v[u] = vload<CPL>(a.Y + (int64_t)pcol[u] * a.C + c0 + l);
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int idx = base + u * kBlock;
+        const int l = (idx % kLanes) * CPL;
+        if (pcol[u] < 0 || l >= nch) continue;
+        if (a.dscale) {
+          const float d = a.dscale[(int)(((double)pcol[u] + 0.5) * a.inv_nt)];
+#pragma unroll
+          for (int k = 0; k < 2 * CPL; ++k) v[u].v[k] *= d;
+        }
+        vstore<CPL>(pts + (idx / kLanes) * CH + l, v[u]);
+      }
+    }
     for (int i = threadIdx.x; i <= R; i += kBlock) soff[i] = off[i] - e0;
-    for (int i = threadIdx.x; i < ne; i += kBlock) {
-      sslot[i] = a.en_slot[e0 + i];
-      sval[i] = ldv(val, (int64_t)e0 + i);
+    for (int base = threadIdx.x; base < ne; base += kBlock * kStageBatch) {
+      uint16_t ts[kStageBatch];
+      float tv[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = base + u * kBlock;
+        if (i < ne) {
+          ts[u] = a.en_slot[e0 + i];
+          tv[u] = ldv(val, (int64_t)e0 + i);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = base + u * kBlock;
+        if (i < ne) {
+          sslot[i] = ts[u];
+          sval[i] = tv[u];
+        }
+      }
     }
     __syncthreads();
     if (active) {
@@ -283,12 +342,18 @@ tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y,
   const size_t lds = (size_t)d.PS * d.PS * CH * sizeof(float2);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
   const V* v = (const V*)d.val[vt];
-  if (d.WS == 12)
-    hipLaunchKernelGGL((k_fwd_tile<CPL, V, 12>), grid, dim3(kBlock), lds, st, a, v);
-  else if (d.WS == 28)
-    hipLaunchKernelGGL((k_fwd_tile<CPL, V, 28>), grid, dim3(kBlock), lds, st, a, v);
-  else
-    return fail(TOMO_EUNSUPPORTED, "staged forward kernel has no variant for %d taps", d.WS);
+  const int spg = (op->tune.tile_points + kGroups - 1) / kGroups;   // samples per lane group
+#define TOMO_FWD_TILE(WS_, SPG_)                                                                  \
+  if (d.WS == WS_ && spg <= SPG_) {                                                             \
+    hipLaunchKernelGGL((k_fwd_tile<CPL, V, WS_, SPG_>), grid, dim3(kBlock), lds, st, a, v);     \
+    TOMO_HIP(hipGetLastError());                                                                \
+    return TOMO_OK;                                                                             \
+  }
+  TOMO_FWD_TILE(12, 1) TOMO_FWD_TILE(12, 2) TOMO_FWD_TILE(12, 4)
+  TOMO_FWD_TILE(28, 1) TOMO_FWD_TILE(28, 2)
+#undef TOMO_FWD_TILE
+  return fail(TOMO_EUNSUPPORTED, "staged forward kernel has no variant for %d taps, %d samples",
+              d.WS, op->tune.tile_points);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
@@ -323,6 +388,11 @@ tomo_status adj_tile_impl(const tomo_op* op, int vt, const float2* Y, float2* X,
 }
 
 }  // namespace
+
+bool fwd_tile_supported(const tomo_op* op) {
+  const int spg = (op->tune.tile_points + kGroups - 1) / kGroups;
+  return (op->ftile.WS == 12 && spg <= 4) || (op->ftile.WS == 28 && spg <= 2);
+}
 
 size_t fwd_tile_lds_bytes(const tomo_op* op, int C) {
   const int cpl = (C % 2 == 0) ? 2 : 1;
