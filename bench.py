@@ -3,17 +3,19 @@ image, 1501 angles over [0, pi), 2048 detector bins, one batch of 32 slices (16 
 channels), matrix values in bfloat16 (mixed) and float32, float32 accumulation.
 
 One step = one forward SpMM + one adjoint SpMM over the batch, inputs resident in HBM.
-Besides the contract line it reports, for the same workload: per-kernel durations and the
-HBM roofline fraction of the dominant kernel, the float32-value rate, the full operator
-(project + backproject incl. FFTs) and a CGLS iteration, and the FP64 oracle timed on the
-host cores.  Prints one JSON line.
+Besides the contract line it reports, for the same workload: per-step percentiles, per-kernel
+durations and the HBM roofline fraction of the dominant kernel (with the HBM bytes that the
+counter summary under profiles/ measured for the same kernel source, when it matches), the
+float32-value rate, the two-slice (one complex channel) form, the full operator (project +
+backproject incl. FFTs) and a CGLS iteration, and the FP64 oracle timed on the host cores
+(before the GPU is touched).  Prints one JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -24,6 +26,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 N_IMG, N_ANG, N_DET, BATCH = 2048, 1501, 2048, 32
 WORKLOAD = "parallel-beam 2048x2048, 1501 angles in [0,pi), 2048 bins, batch 32 slices"
+COUNTERS = os.path.join(ROOT, "profiles", "spmm_2048_1501_b32_counters.json")
+SPMM_SOURCES = [os.path.join(ROOT, "paper_2003_12677_amd", "csrc", f)
+                for f in ("spmm.hip", "tiles.hip", "internal.h", "builder.cpp")]
 
 
 def parse():
@@ -32,7 +37,8 @@ def parse():
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    p.add_argument("--cpu-seconds", type=float, default=8.0,
+                   help="budget of each oracle sample (one process, then all host cores)")
     p.add_argument("--extras", type=int, default=1, help="also time the full operator and CGLS")
     return p.parse_args()
 
@@ -59,17 +65,56 @@ def time_loop(torch, fn, iters: int) -> float:
     return start.elapsed_time(stop) / iters
 
 
-def cpu_baseline(budget_s: float):
-    """The FP64 oracle's forward and adjoint sparse products (S^dagger U, S V') per slice on the
-    host, on as many slices as fit the time budget."""
+def step_percentiles(torch, fn, iters: int):
+    """p10 / p50 / p90 of single-step durations (ms), one event pair per step."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(iters)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    d = sorted(a.elapsed_time(b) for a, b in ev)
+
+    def q(f):
+        return d[min(len(d) - 1, int(round(f * (len(d) - 1))))]
+
+    return {"p10": q(0.1), "p50": q(0.5), "p90": q(0.9)}
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in SPMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy-kernel calibration), or None when the summary is missing or
+    was taken from different kernel sources."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256") != source_digest() or kernel not in c.get("kernels", {}):
+        return None
+    k = c["kernels"][kernel]
+    return {"read_bytes": k["read_bytes"], "write_bytes": k["write_bytes"],
+            "total_bytes": k["read_bytes"] + k["write_bytes"], "unit": "bytes per launch",
+            "calibration": c.get("calibration")}
+
+
+def _oracle_slices(budget_s: float, max_slices: int, seed: int):
+    """Forward + adjoint sparse products of the FP64 oracle on as many slices as fit the budget;
+    returns (slices, seconds).  Uses the operator built in the parent process (fork)."""
     import numpy as np
 
-    from oracle import Geometry, Operator
-
-    t0 = time.perf_counter()
-    ref = Operator(Geometry(N_IMG, N_ANG, N_DET))
-    build_s = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
+    ref = _ORACLE["op"]
+    rng = np.random.default_rng(seed)
     U = rng.standard_normal((N_DET, N_DET)) + 1j * rng.standard_normal((N_DET, N_DET))
     V = rng.standard_normal((N_ANG, N_DET)) + 1j * rng.standard_normal((N_ANG, N_DET))
     done = 0
@@ -79,11 +124,41 @@ def cpu_baseline(budget_s: float):
         ref.slice_adjoint(V)
         done += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or done >= 64:
-            break
-    return {"value": done / el, "unit": "slices/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} slices of S^dagger U + S V' (scipy CSR, complex128 vectors), "
-                      f"{el:.1f} s; operator build {build_s:.1f} s not timed"}
+        if el >= budget_s or done >= max_slices:
+            return done, el
+
+
+_ORACLE = {}
+
+
+def cpu_baseline(budget_s: float):
+    """The FP64 oracle's forward and adjoint sparse products (S^dagger U, S V') per slice on the
+    host: one process, then one process per usable host core, each on its own slices (the
+    slice decomposition of Sec. 3.1).  Runs before anything touches the GPU, so the forked
+    workers hold no GPU state."""
+    import multiprocessing as mp
+
+    from oracle import Geometry, Operator
+
+    t0 = time.perf_counter()
+    _ORACLE["op"] = Operator(Geometry(N_IMG, N_ANG, N_DET))
+    build_s = time.perf_counter() - t0
+    one, el1 = _oracle_slices(budget_s, 64, 0)
+    cores = min(16, len(os.sched_getaffinity(0)))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        parts = pool.starmap(_oracle_slices, [(budget_s, 64, 1 + i) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    done = sum(p[0] for p in parts)
+    rate = sum(p[0] / p[1] for p in parts)      # concurrent processes, each over its own loop
+    _ORACLE.clear()
+    return {"value": rate, "unit": "slices/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} slices of S^dagger U + S V' (scipy CSR, complex128 vectors) in "
+                      f"{cores} concurrent processes, about {budget_s:.0f} s each ({wall:.1f} s "
+                      f"wall); operator build {build_s:.1f} s not timed",
+            "single_process": {"value": one / el1, "cores": 1,
+                               "sample": f"{one} slices in {el1:.1f} s"}}
 
 
 def main():
@@ -91,6 +166,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
     import torch
 
     import paper_2003_12677_amd as tomo
@@ -119,6 +195,7 @@ def main():
     torch.cuda.synchronize()
     ms_step = time_loop(torch, lambda: step("bf16"), args.steps)
     value = BATCH / (ms_step * 1e-3)
+    pct = step_percentiles(torch, lambda: step("bf16"), args.steps)
 
     res = {}
     for vt, vb in (("bf16", 2), ("f32", 4)):
@@ -128,6 +205,17 @@ def main():
         res[vt] = {"fwd_ms": fwd_ms, "adj_ms": adj_ms, "fwd_GBs": fb / fwd_ms / 1e6,
                    "adj_GBs": ab / adj_ms / 1e6, "fwd_bytes": fb, "adj_bytes": ab}
     ms_f32 = time_loop(torch, lambda: step("f32"), args.steps)
+
+    # the paper's form: one pair of slices (a single complex channel) per product
+    X2 = Xc[:, :1].contiguous()
+    Y2 = Yp[:, :1].contiguous()
+    Y2o = torch.empty_like(Y2)
+    X2o = torch.empty_like(X2)
+    pair = {}
+    for vt in ("bf16", "f32"):
+        ms = time_loop(torch, lambda: (op.slice_fwd(X2, 2, Yp=Y2o, values=vt),
+                                       op.slice_adj(Y2, 2, Xc=X2o, values=vt)), args.steps)
+        pair[vt] = {"ms_per_step": ms, "slices_per_s": 2 / (ms * 1e-3)}
 
     # device-to-device copy of a known size: the achievable streaming bandwidth on this GPU, and
     # the calibration kernel for HBM byte counters
@@ -158,13 +246,16 @@ def main():
         "config": {"workload": WORKLOAD, "n": N_IMG, "n_angles": N_ANG, "n_det": N_DET,
                    "batch": BATCH, "complex_channels": C, "values": "bf16", "accumulate": "f32",
                    "kernel_width": info.kw, "nnz": info.nnz, "parallelism": "single GPU"},
+        "step_ms_percentiles": pct,
         "roofline": {"bound": "hbm", "kernel": f"spmm_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "frac_of_copy": achieved / copy_gbs},
+                     "traffic": measured_traffic(f"spmm_{dom}_bf16"),
+                     "algorithmic_bytes": m[f"{dom}_bytes"], "frac_of_copy": achieved / copy_gbs},
         "copy_GBs": {"value": copy_gbs, "what": "torch copy_ of 1 GiB (read + write bytes / time)"},
         "kernels": res,
         "fp32_values": {"value": BATCH / (ms_f32 * 1e-3), "ms_per_step": ms_f32},
         "mixed_vs_fp32": ms_f32 / ms_step,
+        "pair_form_b2": pair,
         "operator_build_s": build_s,
     }
     if args.extras:
@@ -181,12 +272,24 @@ def main():
                            "slices_per_s_bf16": BATCH / (ms_op["bf16"] * 1e-3),
                            "slices_per_s_f32": BATCH / (ms_op["f32"] * 1e-3),
                            "ms_bf16": ms_op["bf16"], "ms_f32": ms_op["f32"]}
+        ms_nrm = {}
+        for vt in ("bf16", "f32"):
+            op.normal(x, xb, values=vt)
+            ms_nrm[vt] = time_loop(torch, lambda: op.normal(x, xb, values=vt), 10)
+        out["normal_operator"] = {
+            "what": "A^T A in one pass (embed, 2D FFT, S S^dagger stencil, inverse 2D FFT, crop)",
+            "ms_bf16": ms_nrm["bf16"], "ms_f32": ms_nrm["f32"],
+            "speedup_vs_project_backproject_bf16": ms_op["bf16"] / ms_nrm["bf16"]}
         op.solve(y, xb, iters=1)
         ms_cg = time_loop(torch, lambda: op.solve(y, xb, iters=10), 2)
         ms_cg1 = time_loop(torch, lambda: op.solve(y, xb, iters=0), 2)
-        out["cgls"] = {"ms_per_iteration_f32": (ms_cg - ms_cg1) / 10, "batch": BATCH}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        op.solve(y, xb, iters=1, method="cgnr")
+        ms_cn = time_loop(torch, lambda: op.solve(y, xb, iters=10, method="cgnr"), 2)
+        ms_cn1 = time_loop(torch, lambda: op.solve(y, xb, iters=0, method="cgnr"), 2)
+        out["cgls"] = {"ms_per_iteration_f32": (ms_cg - ms_cg1) / 10, "batch": BATCH,
+                       "normal_form_ms_per_iteration_f32": (ms_cn - ms_cn1) / 10}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     op.close()
     print(json.dumps(out))
 

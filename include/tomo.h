@@ -138,10 +138,18 @@ typedef struct {
                                      chunk (32, 64, 96 or 128)                                 */
   int32_t tile_chunks;            /* adjoint: chunks one block accumulates before a tile is
                                      split into partial sums (1..64)                           */
+  int32_t normal_tiled;           /* normal operator: 1 stages each channel's grid tile (+ halo)
+                                     in LDS; 0 reads every stencil tap through L1/L2           */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */
-typedef enum { TOMO_SOLVE_CGLS = 0, TOMO_SOLVE_SIRT_BB = 1 } tomo_solver;
+typedef enum {
+  TOMO_SOLVE_CGLS = 0,           /* CGLS on A (Sec. 3.1)                                        */
+  TOMO_SOLVE_SIRT_BB = 1,        /* SIRT, preconditioner D, Barzilai-Borwein steps (Sec. 3.1)  */
+  TOMO_SOLVE_CGNR = 2,           /* CG on A^T A x = A^T b with A^T A from tomo_normal (Sec. 4,
+                                    Toeplitz approach); needs n_det == grid                   */
+  TOMO_SOLVE_SIRT_BB_NORMAL = 3  /* SIRT_BB with A^T_D A from tomo_normal; needs n_det == grid */
+} tomo_solver;
 
 typedef struct {
   int32_t method;         /* tomo_solver                                                    */
@@ -202,6 +210,42 @@ tomo_status tomo_slice_adj(tomo_op* op, const float* Yp, float* Xc, int32_t batc
  * allocates the solver's device vectors (kept until tomo_destroy_operator). */
 tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
                        const tomo_solve_opts* opts, void* stream);
+
+/* Normal operator out = A^T D A x for `batch` slices in one pass of the Cartesian grid (Sec. 4:
+ * the Toeplitz approach, the transform combined with its adjoint without the two 1D FFTs).
+ * Exact for this discretisation when n_det == grid (L) and the centre is an integer: then
+ *   A^T D A x = (1/L) k* . F2D^H W F2D (k* . x),   W = S diag(D) S^dagger,
+ * and W is a fixed (2kw-1)^2 stencil of weights per Cartesian frequency (no column indices).
+ * filter: tomo_filter, D in the polar domain (TOMO_FILTER_NONE: A^T A).  The first call per
+ * filter builds W on the host in float64 and uploads it in every value type the operator holds
+ * (synchronous; kept until tomo_destroy_operator).
+ * x: device [batch][n][n] f32 (read); out: device [batch][n][n] f32 (written), 16-byte aligned.
+ * Errors: as tomo_project, plus TOMO_EUNSUPPORTED (n_det != grid, or kw > 5). */
+tomo_status tomo_normal(tomo_op* op, const float* x, float* out, int32_t batch, int32_t values,
+                        int32_t filter, void* stream);
+
+/* Host copy of the normal-operator stencil W = S diag(D) S^dagger for `filter`: w is a host
+ * array [grid*grid][(2kw-1)^2] (float64, FFT-ordered Cartesian rows j = j1*G + j2), entry
+ * (d1 + R)(2R+1) + (d2 + R) of row j the weight of frequency ((j1+d1) mod G, (j2+d2) mod G),
+ * R = kw - 1.  Recomputed on every call (host only, also for host-only operators).
+ * Errors: TOMO_EINVAL, TOMO_EUNSUPPORTED (n_det != grid, or kw > 5). */
+tomo_status tomo_export_normal(const tomo_op* op, int32_t filter, double* w);
+
+/* Smoothed isotropic total variation of `batch` n x n images and its gradient: the
+ * regularisation term mu * Reg(u) of the model-based problem (Sec. 2, Reg = the total-variation
+ * norm).  The paper fixes no discretisation; this one uses forward differences with a zero
+ * difference past the last row and column,
+ *   TV_eps(u) = sum over pixels of sqrt((u[i1+1][i2]-u[i1][i2])^2 + (u[i1][i2+1]-u[i1][i2])^2 + eps).
+ * x:     device [batch][n][n] f32, n = the operator's image size (read).
+ * grad:  device [batch][n][n] f32 or NULL: overwritten with weight * dTV_eps/dx (float32 math).
+ * value: device [batch] f64 or NULL: overwritten with weight * TV_eps per slice (float64 sums
+ *        in a fixed order: bitwise reproducible).
+ * eps > 0 and finite; weight finite.  The first call with value != NULL allocates a small
+ * reduction buffer owned by the operator; calls on one operator must not overlap.
+ * Errors: TOMO_EINVAL (NULL op/x, batch outside [0, max_batch], eps, weight, misaligned
+ * pointers), TOMO_ESTATE (host-only operator), TOMO_ENOMEM, TOMO_EHIP. */
+tomo_status tomo_tv(tomo_op* op, const float* x, int32_t batch, double eps, double weight,
+                    float* grad, double* value, void* stream);
 
 /* Sizes and statistics of a built operator (host only, no synchronisation). */
 tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out);

@@ -45,11 +45,13 @@ def normal_factored(op, u: np.ndarray, W: sp.csr_matrix | None = None) -> np.nda
     return (op.kstar * op.ifft2_centered_adjoint(Z)).real
 
 
-def cg_normal(T, rhs: np.ndarray, iters: int, x0: np.ndarray | None = None):
+def cg_normal(T, rhs: np.ndarray, iters: int, x0: np.ndarray | None = None, store=None):
     """Conjugate gradients on T x = rhs for a symmetric positive semi-definite T (the normal
-    equations A^T A x = A^T b; in exact arithmetic the iterates equal CGLS's)."""
+    equations A^T A x = A^T b; in exact arithmetic the iterates equal CGLS's).  ``store`` (default
+    identity) is applied to every stored vector, e.g. to model float32 storage."""
+    keep = store if store is not None else (lambda v: v)
     x = np.zeros_like(rhs) if x0 is None else np.array(x0, dtype=np.float64)
-    r = rhs - T(x) if x0 is not None else rhs.copy()
+    r = keep(rhs - T(x)) if x0 is not None else keep(np.array(rhs, dtype=np.float64))
     p = r.copy()
     rr = float(np.vdot(r, r).real)
     for _ in range(iters):
@@ -60,9 +62,9 @@ def cg_normal(T, rhs: np.ndarray, iters: int, x0: np.ndarray | None = None):
         if pq <= 0.0:
             break
         a = rr / pq
-        x = x + a * p
-        r = r - a * q
+        x = keep(x + a * p)
+        r = keep(r - a * q)
         rr_new = float(np.vdot(r, r).real)
-        p = r + (rr_new / rr) * p
+        p = keep(r + (rr_new / rr) * p)
         rr = rr_new
     return x

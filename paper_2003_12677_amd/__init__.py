@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libtomo.so")
 VALUES = {"f32": 0, "bf16": 1, "f16": 2}
 VALUE_MASK = {"f32": 1, "bf16": 2, "f16": 4}
 FILTERS = {"none": 0, "ramlak": 1, "shepp": 2, "hamming": 3}
-SOLVERS = {"cgls": 0, "sirt_bb": 1}
+SOLVERS = {"cgls": 0, "sirt_bb": 1, "cgnr": 2, "sirt_bb_normal": 3}
 STATUS = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EHIP", -4: "TOMO_EFFT",
           -5: "TOMO_ESTATE", -6: "TOMO_EUNSUPPORTED"}
 
@@ -56,7 +56,8 @@ class tomo_tuning(ctypes.Structure):
                 ("adj_sell_max", ctypes.c_int32), ("adj_sell_sigma", ctypes.c_int32),
                 ("adj_medium_max", ctypes.c_int32), ("adj_chunk", ctypes.c_int32),
                 ("fwd_tiled", ctypes.c_int32), ("adj_tiled", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("tile_points", ctypes.c_int32), ("tile_chunks", ctypes.c_int32)]
+                ("tile_points", ctypes.c_int32), ("tile_chunks", ctypes.c_int32),
+                ("normal_tiled", ctypes.c_int32)]
 
 
 class tomo_solve_opts(ctypes.Structure):
@@ -77,6 +78,9 @@ SIGNATURES = {
     "tomo_slice_fwd": (ctypes.c_int, [_P, _P, _P, _I, _I, _P]),
     "tomo_slice_adj": (ctypes.c_int, [_P, _P, _P, _I, _I, _I, _P]),
     "tomo_solve": (ctypes.c_int, [_P, _P, _P, _I, ctypes.POINTER(tomo_solve_opts), _P]),
+    "tomo_normal": (ctypes.c_int, [_P, _P, _P, _I, _I, _I, _P]),
+    "tomo_export_normal": (ctypes.c_int, [_P, _I, _P]),
+    "tomo_tv": (ctypes.c_int, [_P, _P, _I, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "tomo_op_info_get": (ctypes.c_int, [_P, ctypes.POINTER(tomo_op_info)]),
     "tomo_export_csr": (ctypes.c_int, [_P, _I, _P, _P, _P]),
     "tomo_export_factors": (ctypes.c_int, [_P, _I, _P, _P]),
@@ -157,6 +161,7 @@ class Operator:
         self.info = self.op_info()
         self.n, self.n_angles, self.n_det = n, n_angles, n_det
         self.grid = self.info.grid
+        self.kw = self.info.kw
 
     # ---- lifecycle ---------------------------------------------------------------------
     def destroy_operator(self) -> None:
@@ -305,6 +310,36 @@ class Operator:
         _check(_lib.tomo_solve(self._handle, _ptr(b), _ptr(x), B, ctypes.byref(o), _stream(self.device)))
         return x
 
+    def normal(self, x: torch.Tensor, out: torch.Tensor | None = None, values: str = "f32",
+               filter: str = "none") -> torch.Tensor:
+        """``tomo_normal``: A^T D A x through the normal-operator stencil (no 1D FFTs)."""
+        B = x.shape[0]
+        _need(x, self._image_shape(B), self.device, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        _need(out, self._image_shape(B), self.device, "out")
+        _check(_lib.tomo_normal(self._handle, _ptr(x), _ptr(out), B, VALUES[values],
+                                FILTERS[filter], _stream(self.device)))
+        return out
+
+    def export_normal(self, filter: str = "none"):
+        """Host float64 stencil of W = S diag(D) S^dagger: array [grid*grid, (2kw-1)^2]."""
+        import numpy as np
+        d = 2 * self.kw - 1
+        w = np.empty((self.grid * self.grid, d * d), dtype=np.float64)
+        _check(_lib.tomo_export_normal(self._handle, FILTERS[filter], w.ctypes.data))
+        return w
+
+    def tv(self, x: torch.Tensor, eps: float = 1e-8, weight: float = 1.0, *, value: bool = True,
+           grad: bool = True):
+        """``tomo_tv``: (per-slice weight*TV_eps as float64 [B] or None, weight*gradient or None)."""
+        B = x.shape[0]
+        _need(x, self._image_shape(B), self.device, "x")
+        v = torch.empty(B, dtype=torch.float64, device=x.device) if value else None
+        g = torch.empty_like(x) if grad else None
+        _check(_lib.tomo_tv(self._handle, _ptr(x), B, float(eps), float(weight), _ptr(g), _ptr(v),
+                            _stream(self.device)))
+        return v, g
 
 def build_operator(*args, **kwargs) -> Operator:
     """``tomo_build_operator``: see :class:`Operator`."""

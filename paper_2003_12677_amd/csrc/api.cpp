@@ -182,6 +182,9 @@ void free_device(tomo_op* op) {
   free_tiles(op);
   destroy_plans(op);
   free_solver(op);
+  free_tv(op);
+  for (auto& f : op->nrm.val)
+    for (auto& v : f) dfree(v);
   dfree(op->fwd.col);
   for (auto& v : op->fwd.val) dfree(v);
   free_adj(op);
@@ -292,6 +295,57 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
   return TOMO_OK;
 }
 
+tomo_status normal_supported(const tomo_op* op) {
+  const Geom& g = op->g;
+  if (g.np != g.L)
+    return fail(TOMO_EUNSUPPORTED, "the normal operator needs n_det == grid (n_det=%d, grid=%d)",
+                g.np, g.L);
+  if (g.kw > 5) return fail(TOMO_EUNSUPPORTED, "the normal operator needs kw <= 5 (kw=%d)", g.kw);
+  return TOMO_OK;
+}
+
+// Build (host, float64) and upload W = S diag(D) S^dagger for `filter` in every value type the
+// operator holds; synchronous, first use per filter.
+tomo_status ensure_normal(tomo_op* op, int filter) {
+  DevNormal& nrm = op->nrm;
+  bool have = false;
+  for (int vt = 0; vt < 3; ++vt) have |= nrm.val[filter][vt] != nullptr;
+  if (have) return TOMO_OK;
+  TOMO_TRY(normal_supported(op));
+  const Geom& g = op->g;
+  const int R = g.kw - 1, S2 = (2 * R + 1) * (2 * R + 1);
+  nrm.R = R;
+  nrm.stride = (S2 + 7) / 8 * 8;
+  std::vector<double> d;
+  if (filter != TOMO_FILTER_NONE) filter_diagonal(g, filter, &d);
+  std::vector<double> w;
+  TOMO_TRY(build_normal_values(g, op->s, op->sdag, d.empty() ? nullptr : d.data(), nrm.stride, &w));
+  void* dst[3] = {nullptr, nullptr, nullptr};
+  const tomo_status st = upload_values(w, op->values, dst);
+  if (st != TOMO_OK) {
+    for (auto& v : dst) dfree(v);
+    return st;
+  }
+  for (int vt = 0; vt < 3; ++vt) nrm.val[filter][vt] = dst[vt];
+  return TOMO_OK;
+}
+
+// A^T D A x = crop(k*, 1/L) F2D^H W F2D embed(k* x), all on the channel-slowest grid buffers
+tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
+                         hipStream_t st) {
+  const Geom& g = op->g;
+  const int C = (B + 1) / 2;
+  TOMO_TRY(ensure_normal(op, filter));
+  FFTPlans* p = nullptr;
+  TOMO_TRY(get_plans(op, C, &p));
+  TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
+  TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  TOMO_TRY(launch_normal_stencil(op, op->Xs, op->X, C, vt, filter, st));
+  TOMO_TRY(fft_exec(p->inv2, p, op->X, st));
+  TOMO_TRY(launch_crop_image(op, op->X, out, B, 1.0f / (float)g.L, st));
+  return TOMO_OK;
+}
+
 }  // namespace tomo
 
 using namespace tomo;
@@ -397,17 +451,65 @@ tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
   clear_error();
   if (!opts) return fail(TOMO_EINVAL, "opts is NULL");
   TOMO_TRY(check_apply(op, b, x, batch, opts->values));
-  if (opts->method != TOMO_SOLVE_CGLS && opts->method != TOMO_SOLVE_SIRT_BB)
+  if (opts->method < TOMO_SOLVE_CGLS || opts->method > TOMO_SOLVE_SIRT_BB_NORMAL)
     return fail(TOMO_EINVAL, "unknown solver %d", opts->method);
+  if (opts->method == TOMO_SOLVE_CGNR || opts->method == TOMO_SOLVE_SIRT_BB_NORMAL)
+    TOMO_TRY(normal_supported(op));
   if (opts->iters < 0 || opts->refine_outer < 1)
     return fail(TOMO_EINVAL, "iters must be >= 0 and refine_outer >= 1");
   if (opts->filter < TOMO_FILTER_NONE || opts->filter > TOMO_FILTER_HAMMING)
     return fail(TOMO_EINVAL, "unknown filter %d", opts->filter);
-  if (opts->method == TOMO_SOLVE_SIRT_BB && (opts->refine_outer != 1 || opts->use_x0))
+  if ((opts->method == TOMO_SOLVE_SIRT_BB || opts->method == TOMO_SOLVE_SIRT_BB_NORMAL) &&
+      (opts->refine_outer != 1 || opts->use_x0))
     return fail(TOMO_EUNSUPPORTED, "SIRT-BB runs from zero without refinement");
   if (batch == 0) return TOMO_OK;
   DeviceGuard guard(op->device);
   return run_solve(op, b, x, batch, opts, (hipStream_t)stream);
+}
+
+tomo_status tomo_normal(tomo_op* op, const float* x, float* out, int32_t batch, int32_t values,
+                        int32_t filter, void* stream) {
+  clear_error();
+  TOMO_TRY(check_apply(op, x, out, batch, values));
+  if (filter < TOMO_FILTER_NONE || filter > TOMO_FILTER_HAMMING)
+    return fail(TOMO_EINVAL, "unknown filter %d", filter);
+  TOMO_TRY(normal_supported(op));
+  if (batch == 0) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return apply_normal(op, x, out, batch, values, filter, (hipStream_t)stream);
+}
+
+tomo_status tomo_export_normal(const tomo_op* op, int32_t filter, double* w) {
+  clear_error();
+  if (!op || !w) return fail(TOMO_EINVAL, "NULL argument");
+  if (filter < TOMO_FILTER_NONE || filter > TOMO_FILTER_HAMMING)
+    return fail(TOMO_EINVAL, "unknown filter %d", filter);
+  TOMO_TRY(normal_supported(op));
+  const Geom& g = op->g;
+  const int D = 2 * g.kw - 1;
+  std::vector<double> d;
+  if (filter != TOMO_FILTER_NONE) filter_diagonal(g, filter, &d);
+  std::vector<double> all;
+  TOMO_TRY(build_normal_values(g, op->s, op->sdag, d.empty() ? nullptr : d.data(), D * D, &all));
+  std::memcpy(w, all.data(), all.size() * sizeof(double));
+  return TOMO_OK;
+}
+
+tomo_status tomo_tv(tomo_op* op, const float* x, int32_t batch, double eps, double weight,
+                    float* grad, double* value, void* stream) {
+  clear_error();
+  if (!op) return fail(TOMO_EINVAL, "operator is NULL");
+  if (op->device < 0) return fail(TOMO_ESTATE, "operator was built without a device");
+  if (batch < 0 || batch > op->g.max_batch)
+    return fail(TOMO_EINVAL, "batch %d outside [0, max_batch=%d]", batch, op->g.max_batch);
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(TOMO_EINVAL, "eps must be positive and finite");
+  if (!std::isfinite(weight)) return fail(TOMO_EINVAL, "weight must be finite");
+  if (batch > 0 && !x) return fail(TOMO_EINVAL, "NULL image pointer");
+  if (batch > 0 && (misaligned(x, 4) || misaligned(grad, 4) || misaligned(value, 8)))
+    return fail(TOMO_EINVAL, "misaligned pointer");
+  if (batch == 0 || (!grad && !value)) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  return launch_tv(op, x, batch, eps, weight, grad, value, (hipStream_t)stream);
 }
 
 tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out) {
@@ -484,6 +586,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->tile = op->tune.tile;
   out->tile_points = op->tune.tile_points;
   out->tile_chunks = op->tune.tile_chunks;
+  out->normal_tiled = op->tune.normal_tiled;
   return TOMO_OK;
 }
 
@@ -502,6 +605,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.tile = in->tile;
   t.tile_points = in->tile_points;
   t.tile_chunks = in->tile_chunks;
+  t.normal_tiled = in->normal_tiled;
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;

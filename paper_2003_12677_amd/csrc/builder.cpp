@@ -17,10 +17,12 @@
 // complex channel (Sec. 3.1).
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 
 #include "internal.h"
 
@@ -233,6 +235,7 @@ tomo_status check_tuning(const Tuning& t) {
   if (t.tile_points < 32 || t.tile_points > 128 || t.tile_points % 32 != 0)
     return fail(TOMO_EINVAL, "tile_points must be 32, 64, 96 or 128");
   if (t.tile_chunks < 1 || t.tile_chunks > 64) return fail(TOMO_EINVAL, "tile_chunks must be in [1, 64]");
+  if (t.normal_tiled != 0 && t.normal_tiled != 1) return fail(TOMO_EINVAL, "normal_tiled must be 0 or 1");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
     return fail(TOMO_EINVAL, "channels per lane must be 1, 2 or 4 (got %d, %d)", t.fwd_cpl, t.adj_cpl);
   if (t.sell_max < 0 || t.sell_max > 1024) return fail(TOMO_EINVAL, "sell_max %d not in [0, 1024]", t.sell_max);
@@ -607,6 +610,58 @@ void filter_diagonal(const Geom& g, int filter, std::vector<double>* d) {
     }
     (*d)[kf] = R * win;
   }
+}
+
+// Row j of W = S diag(d) S^dagger as a (2R+1)^2 stencil, R = kw - 1 (Sec. 4, Toeplitz form of
+// A^T A): over the polar samples p of row j of S, add S[j][p] d(p) S^dagger[p][j'] at the slot
+// of the offset j' - j, both FFT-ordered Cartesian indices with the offset taken mod G into
+// [-G/2, G/2).  Fixed summation order.  False if an entry falls outside the stencil.
+bool normal_stencil_row(const Geom& g, const HostCSR& s, const HostCSR& sdag, const double* dk,
+                        int64_t j, double* out) {
+  const int R = g.kw - 1, D = 2 * R + 1;
+  const int64_t G = g.G;
+  std::fill(out, out + (size_t)D * D, 0.0);
+  const int64_t j1 = j / G, j2 = j % G;
+  for (int64_t e = s.rowptr[j]; e < s.rowptr[j + 1]; ++e) {
+    const int64_t p = s.col[e];
+    const double a = s.val[e] * (dk ? dk[p / g.nt] : 1.0);
+    for (int64_t f = sdag.rowptr[p]; f < sdag.rowptr[p + 1]; ++f) {
+      const int64_t c = sdag.col[f];
+      int64_t d1 = c / G - j1, d2 = c % G - j2;
+      if (2 * d1 >= G) d1 -= G;
+      if (2 * d1 < -G) d1 += G;
+      if (2 * d2 >= G) d2 -= G;
+      if (2 * d2 < -G) d2 += G;
+      if (d1 < -R || d1 > R || d2 < -R || d2 > R) return false;
+      out[(d1 + R) * D + (d2 + R)] += a * sdag.val[f];
+    }
+  }
+  return true;
+}
+
+tomo_status build_normal_values(const Geom& g, const HostCSR& s, const HostCSR& sdag,
+                                const double* dk, int stride, std::vector<double>* w) {
+  const int D = 2 * g.kw - 1;
+  const int64_t M = (int64_t)g.G * g.G;
+  w->assign((size_t)M * stride, 0.0);
+  std::atomic<bool> ok{true};
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t) {
+    pool.emplace_back([&, t] {
+      std::vector<double> row((size_t)D * D);
+      for (int64_t j = M * t / nth; j < M * (t + 1) / nth; ++j) {
+        if (!normal_stencil_row(g, s, sdag, dk, j, row.data())) {
+          ok = false;
+          return;
+        }
+        std::copy(row.begin(), row.end(), w->begin() + (size_t)j * stride);
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+  if (!ok) return fail(TOMO_EINVAL, "S S^dagger entry outside the (2kw-1)^2 stencil");
+  return TOMO_OK;
 }
 
 uint16_t f32_to_bf16_rne(float f) {

@@ -67,6 +67,7 @@ struct Tuning {
   int tile = 8;           // Cartesian tile side of the staged kernels (8, 16 or 32)
   int tile_points = 128;  // forward: samples per block; adjoint: polar rows staged per chunk
   int tile_chunks = 1;    // adjoint: chunks one block accumulates before writing
+  int normal_tiled = 1;   // normal operator: LDS-staged grid tiles (1) or direct taps (0)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
@@ -133,6 +134,10 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
 void deapod_factors(const Geom& g, std::vector<double>* kd);
 void filter_diagonal(const Geom& g, int filter, std::vector<double>* d);   // FFT-ordered k
 uint16_t f32_to_bf16_rne(float f);
+bool normal_stencil_row(const Geom& g, const HostCSR& s, const HostCSR& sdag, const double* dk,
+                        int64_t j, double* out);
+tomo_status build_normal_values(const Geom& g, const HostCSR& s, const HostCSR& sdag,
+                                const double* dk, int stride, std::vector<double>* w);
 
 // ---------------------------------------------------------------------------------
 // device state
@@ -142,6 +147,14 @@ struct DevEll {
   int W2 = 0;
   int32_t* col = nullptr;
   void* val[3] = {nullptr, nullptr, nullptr};   // indexed by tomo_value_type
+};
+
+// W = S diag(D) S^dagger for the normal operator as a fixed stencil: values [G*G][stride] per
+// filter and value type, slot (d1 + R)(2R + 1) + (d2 + R) for the FFT-ordered offset (d1, d2),
+// R = kw - 1, stride = (2R+1)^2 rounded up to 8 (zero padded).  Built on first use per filter.
+struct DevNormal {
+  int R = 0, stride = 0;
+  void* val[4][3] = {};   // [tomo_filter][tomo_value_type]
 };
 
 struct DevAdj {
@@ -180,7 +193,7 @@ struct FFTPlans {
 
 struct SolverBuffers {
   int B = 0;
-  float *p = nullptr, *s = nullptr, *d = nullptr;      // image-sized [B][n][n]
+  float *p = nullptr, *s = nullptr, *d = nullptr, *t = nullptr;   // image-sized [B][n][n]
   float *r = nullptr, *q = nullptr, *rb = nullptr;     // sinogram-sized [B][nt][np]
   double* scal = nullptr;                              // per-slice scalars [16][B]
   double* partial = nullptr;                           // dot partial sums [B][kDotBlocks]
@@ -217,6 +230,8 @@ struct tomo_op {
   bool tiles_ready = false;
   std::map<int, tomo::FFTPlans> plans;   // keyed by channel count C
   tomo::SolverBuffers sb;
+  double* tv_partial = nullptr;   // [max_batch][kDotBlocks] TV partial sums (first use)
+  tomo::DevNormal nrm;            // normal-operator stencils (first use per filter)
 };
 
 namespace tomo {
@@ -264,6 +279,20 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
 tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_solve_opts* o,
                       hipStream_t st);
 void free_solver(tomo_op* op);
+
+// Smoothed isotropic TV of `B` n x n images: grad (nullable) = weight * dTV/dx, value
+// (nullable, device [B] float64) = weight * TV per slice.
+tomo_status launch_tv(tomo_op* op, const float* x, int B, double eps, double weight, float* grad,
+                      double* value, hipStream_t st);
+void free_tv(tomo_op* op);
+
+// Normal operator on the channel-slowest Cartesian grid: Out[c][j] = sum over the stencil of
+// W[j][o] In[c][j + offset(o)] (offsets wrap mod G), W for `filter` in value type vt.
+tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
+                         hipStream_t st);
+tomo_status normal_supported(const tomo_op* op);
+tomo_status launch_normal_stencil(const tomo_op* op, const float2* in, float2* out, int C, int vt,
+                                  int filter, hipStream_t st);
 
 // elementwise / reduction launchers used by the solver
 tomo_status launch_dot(const float* a, const float* b, int64_t len, int B, double* partial,

@@ -161,7 +161,7 @@ tomo_status ensure_solver(tomo_op* op) {
   const size_t img = B * g.n * g.n * sizeof(float);
   const size_t sino = B * g.nt * g.np * sizeof(float);
   struct Req { void** p; size_t bytes; } req[] = {
-      {(void**)&b.p, img},  {(void**)&b.s, img},  {(void**)&b.d, img},
+      {(void**)&b.p, img},  {(void**)&b.s, img},  {(void**)&b.d, img},  {(void**)&b.t, img},
       {(void**)&b.r, sino}, {(void**)&b.q, sino}, {(void**)&b.rb, sino},
       {(void**)&b.scal, kSlots * B * sizeof(double)},
       {(void**)&b.partial, B * kDotBlocks * sizeof(double)}};
@@ -222,16 +222,52 @@ tomo_status cgls(const Ctx& c, const float* b, float* x, int vt, int iters, bool
   return TOMO_OK;
 }
 
+// Conjugate gradients on the normal equations A^T A x = A^T b with A^T A applied through the
+// normal-operator stencil (no 1D FFTs; equal to CGLS in exact arithmetic).
+tomo_status cgnr(const Ctx& c, const float* b, float* x, int vt, int iters, bool use_x0) {
+  SolverBuffers& w = c.op->sb;
+  TOMO_TRY(apply_backproject(c.op, b, w.s, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));   // r = A^T b
+  if (use_x0) {
+    TOMO_TRY(apply_normal(c.op, x, w.t, c.B, vt, TOMO_FILTER_NONE, c.st));
+    TOMO_TRY(c.lin(w.s, w.s, w.t, nullptr, nullptr, 1.0, -1.0, c.img));      // r -= A^T A x
+  } else {
+    TOMO_TRY(launch_fill(x, 0.f, c.img * c.B, c.st));
+  }
+  TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));     // p = r
+  int cur = kGamma0, nxt = kGamma1;
+  TOMO_TRY(c.dot(w.s, w.s, c.img, cur));                                      // gamma = |r|^2
+  for (int it = 0; it < iters; ++it) {
+    TOMO_TRY(apply_normal(c.op, w.p, w.t, c.B, vt, TOMO_FILTER_NONE, c.st));  // q = A^T A p
+    TOMO_TRY(c.dot(w.p, w.t, c.img, kDelta));                                 // delta = p.q
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
+    TOMO_HIP(hipGetLastError());
+    TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));      // x += alpha p
+    TOMO_TRY(c.lin(w.s, w.s, w.t, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img)); // r -= alpha q
+    TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));                                    // gamma' = |r|^2
+    hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
+    TOMO_HIP(hipGetLastError());
+    TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));   // p = r + beta p
+    std::swap(cur, nxt);
+  }
+  return TOMO_OK;
+}
+
 // SIRT with the ramp/Hamming preconditioner D in the polar Fourier domain and BB steps:
 // g = A^T_D (A x - b), x0 = 0, gradients carried by the recurrence g -= alpha A^T_D A g.
-tomo_status sirt_bb(const Ctx& c, const float* b, float* x, int vt, int iters, int filter) {
+// With `normal`, h = A^T_D A g is applied through the normal-operator stencil of D.
+tomo_status sirt_bb(const Ctx& c, const float* b, float* x, int vt, int iters, int filter,
+                    bool normal) {
   SolverBuffers& w = c.op->sb;
   TOMO_TRY(launch_fill(x, 0.f, c.img * c.B, c.st));
   TOMO_TRY(apply_backproject(c.op, b, w.s, c.B, vt, filter, 1.0f, c.st));   // s = A^T_D b
   TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, -1.0, 0.0, c.img));  // g = -A^T_D b
   for (int it = 0; it < iters; ++it) {
-    TOMO_TRY(apply_project(c.op, w.p, w.q, c.B, vt, c.st));                // q = A g
-    TOMO_TRY(apply_backproject(c.op, w.q, w.s, c.B, vt, filter, 1.0f, c.st));   // h = A^T_D A g
+    if (normal) {
+      TOMO_TRY(apply_normal(c.op, w.p, w.s, c.B, vt, filter, c.st));       // h = A^T_D A g
+    } else {
+      TOMO_TRY(apply_project(c.op, w.p, w.q, c.B, vt, c.st));              // q = A g
+      TOMO_TRY(apply_backproject(c.op, w.q, w.s, c.B, vt, filter, 1.0f, c.st));   // h = A^T_D A g
+    }
     TOMO_TRY(c.dot(w.p, w.p, c.img, kNum));
     TOMO_TRY(c.dot(w.p, w.s, c.img, kDen));
     hipLaunchKernelGGL(k_sirt_step, dim3(1), dim3(256), 0, c.st, c.sc(kNum), c.sc(kDen), c.sc(kPNum),
@@ -251,11 +287,16 @@ tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_s
   TOMO_TRY(ensure_solver(op));
   Ctx c{op, B, st, (int64_t)op->g.n * op->g.n, (int64_t)op->g.nt * op->g.np};
   SolverBuffers& w = op->sb;
-  if (o->method == TOMO_SOLVE_SIRT_BB) {
+  const bool cg_normal = o->method == TOMO_SOLVE_CGNR;
+  if (o->method == TOMO_SOLVE_SIRT_BB || o->method == TOMO_SOLVE_SIRT_BB_NORMAL) {
     const int filter = o->filter == TOMO_FILTER_NONE ? TOMO_FILTER_HAMMING : o->filter;
-    TOMO_TRY(sirt_bb(c, b, x, o->values, o->iters, filter));
+    TOMO_TRY(sirt_bb(c, b, x, o->values, o->iters, filter,
+                     o->method == TOMO_SOLVE_SIRT_BB_NORMAL));
   } else if (o->refine_outer == 1) {
-    TOMO_TRY(cgls(c, b, x, o->values, o->iters, o->use_x0 != 0));
+    if (cg_normal)
+      TOMO_TRY(cgnr(c, b, x, o->values, o->iters, o->use_x0 != 0));
+    else
+      TOMO_TRY(cgls(c, b, x, o->values, o->iters, o->use_x0 != 0));
   } else {
     // iterative refinement: residual with float32 values, correction with `values`
     for (int outer = 0; outer < o->refine_outer; ++outer) {
@@ -266,7 +307,10 @@ tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_s
       } else {
         TOMO_TRY(c.lin(w.rb, b, nullptr, nullptr, nullptr, 1.0, 0.0, c.sino));
       }
-      TOMO_TRY(cgls(c, w.rb, w.d, o->values, o->iters, false));
+      if (cg_normal)
+        TOMO_TRY(cgnr(c, w.rb, w.d, o->values, o->iters, false));
+      else
+        TOMO_TRY(cgls(c, w.rb, w.d, o->values, o->iters, false));
       if (have_x)
         TOMO_TRY(c.lin(x, x, w.d, nullptr, nullptr, 1.0, 1.0, c.img));       // x += d
       else

@@ -131,6 +131,54 @@ __device__ __forceinline__ void gather_round(const int32_t* __restrict__ col,
     for (int i = 0; i < 2 * CPL; ++i) acc.v[i] += w[u] * (ok[u] ? x[u].v[i] : 0.f);
 }
 
+// The same round with the metadata loaded once per lane group instead of once per lane, for
+// groups of at least 8 lanes: lane t fetches the column and value of entries s*8 + (t & 7) of the
+// round (slot s), applies the padding test and the filter, and every lane then reads entry u
+// from lane (u & 7) of its group with a cross-lane permute.  All lanes of the group must be
+// active (lanes beyond the channel count still load metadata and gather an in-bounds vector).
+template <int CPL, int U, typename V, bool FILT>
+__device__ __forceinline__ void gather_round_bcast(const int32_t* __restrict__ col,
+                                                   const V* __restrict__ val, int base,
+                                                   int stride, int count,
+                                                   const float2* __restrict__ src, int C, int cb,
+                                                   const float* __restrict__ dscale,
+                                                   double inv_nt, int gbase4, int t8,
+                                                   Vec<CPL>& acc) {
+  constexpr int S = (U + 7) / 8;
+  int cl[S];
+  uint32_t rl[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int u = s * 8 + t8;
+    const int e = (u < count) ? base + u * stride : base;
+    cl[s] = col[e];
+    rl[s] = ldraw(val, e);
+  }
+  float wl[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const bool ok = (s * 8 + t8 < count) && (cl[s] >= 0);
+    wl[s] = cvt(val, rl[s]);
+    if constexpr (FILT) wl[s] *= dscale[ok ? (int)(((double)cl[s] + 0.5) * inv_nt) : 0];
+    cl[s] = ok ? cl[s] : -1;
+  }
+  int c[U];
+  float w[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int addr = gbase4 + ((u & 7) << 2);
+    c[u] = __builtin_amdgcn_ds_bpermute(addr, cl[u >> 3]);
+    w[u] = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(wl[u >> 3])));
+  }
+  Vec<CPL> x[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) x[u] = load_vec<CPL>(src + (int64_t)(c[u] >= 0 ? c[u] : 0) * C + cb);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int i = 0; i < 2 * CPL; ++i) acc.v[i] += w[u] * (c[u] >= 0 ? x[u].v[i] : 0.f);
+}
+
 // ------------------------------------------------------------------------------------------
 // forward: Y = S^dagger X with a constant row stride W2
 // ------------------------------------------------------------------------------------------
@@ -142,18 +190,33 @@ __global__ __launch_bounds__(kBlock) void k_fwd_ell(const int32_t* __restrict__ 
                                                     int logT, int w2_runtime) {
   const int g = threadIdx.x >> logT, t = threadIdx.x & ((1 << logT) - 1);
   const int64_t row = xcd_remap(blockIdx.x, gridDim.x) * (kBlock >> logT) + g;
-  const int cb = t * CPL;
-  if (row >= nrows || cb >= C) return;
+  if (row >= nrows) return;                 // whole lane groups leave together
+  const bool store = t * CPL < C;
+  const int cb = store ? t * CPL : 0;       // idle channel lanes gather an in-bounds vector
   Vec<CPL> acc;
   vzero(acc);
-  if constexpr (W2 > 0) {
-    gather_round<CPL, W2, V, false>(col, val, (int)row * W2, 1, W2, X, C, cb, nullptr, 0.0, acc);
+  if (logT >= 3) {
+    const int gbase4 = (int)((threadIdx.x & 63) & ~((1 << logT) - 1)) << 2;
+    const int t8 = t & 7;
+    if constexpr (W2 > 0) {
+      gather_round_bcast<CPL, W2, V, false>(col, val, (int)row * W2, 1, W2, X, C, cb, nullptr,
+                                            0.0, gbase4, t8, acc);
+    } else {
+      for (int e = 0; e < w2_runtime; e += kRound)
+        gather_round_bcast<CPL, kRound, V, false>(col, val, (int)row * w2_runtime + e, 1,
+                                                  min(kRound, w2_runtime - e), X, C, cb, nullptr,
+                                                  0.0, gbase4, t8, acc);
+    }
   } else {
-    for (int e = 0; e < w2_runtime; e += kRound)
-      gather_round<CPL, kRound, V, false>(col, val, (int)row * w2_runtime + e, 1,
-                                          min(kRound, w2_runtime - e), X, C, cb, nullptr, 0.0, acc);
+    if constexpr (W2 > 0) {
+      gather_round<CPL, W2, V, false>(col, val, (int)row * W2, 1, W2, X, C, cb, nullptr, 0.0, acc);
+    } else {
+      for (int e = 0; e < w2_runtime; e += kRound)
+        gather_round<CPL, kRound, V, false>(col, val, (int)row * w2_runtime + e, 1,
+                                            min(kRound, w2_runtime - e), X, C, cb, nullptr, 0.0, acc);
+    }
   }
-  store_vec(Y + row * C + cb, acc);
+  if (store) store_vec(Y + row * C + cb, acc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -191,21 +254,30 @@ __device__ __forceinline__ void wave_reduce_groups(Vec<CPL>& acc, int T) {
 template <int CPL, typename V, bool FILT>
 __global__ __launch_bounds__(kBlock) void k_adj_sell(AdjArgs a, const V* __restrict__ val) {
   const int g = threadIdx.x >> a.logT, t = threadIdx.x & ((1 << a.logT) - 1);
-  const int cb = t * CPL;
   const int64_t gid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock >> a.logT) + g;
   const int64_t slice = gid / kSliceRows;
   const int j = (int)(gid % kSliceRows);
-  if (slice >= a.n_slices || cb >= a.C) return;
+  if (slice >= a.n_slices) return;          // whole lane groups leave together
+  const bool store = t * CPL < a.C;
+  const int cb = store ? t * CPL : 0;
   const int32_t e0 = a.slice_ptr[slice];
   const int len = (a.slice_ptr[slice + 1] - e0) / kSliceRows;
   const int32_t row = a.slice_rows[gid];
   Vec<CPL> acc;
   vzero(acc);
-  for (int e = 0; e < len; e += kRound)
-    gather_round<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j,
-                                       kSliceRows, min(kRound, len - e), a.Y, a.C, cb, a.dscale,
-                                       a.inv_nt, acc);
-  if (row >= 0) store_vec(a.X + (int64_t)row * a.C + cb, acc);
+  if (a.logT >= 3) {
+    const int gbase4 = (int)((threadIdx.x & 63) & ~((1 << a.logT) - 1)) << 2;
+    for (int e = 0; e < len; e += kRound)
+      gather_round_bcast<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j, kSliceRows,
+                                               min(kRound, len - e), a.Y, a.C, cb, a.dscale,
+                                               a.inv_nt, gbase4, t & 7, acc);
+  } else {
+    for (int e = 0; e < len; e += kRound)
+      gather_round<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j, kSliceRows,
+                                         min(kRound, len - e), a.Y, a.C, cb, a.dscale, a.inv_nt,
+                                         acc);
+  }
+  if (row >= 0 && store) store_vec(a.X + (int64_t)row * a.C + cb, acc);
 }
 
 // one wavefront per medium row; lane groups stride the row's entries
@@ -214,23 +286,29 @@ __global__ __launch_bounds__(kBlock) void k_adj_medium(AdjArgs a, const V* __res
   const int T = 1 << a.logT;
   const int GPW = 64 >> a.logT;
   const int t = threadIdx.x & (T - 1);
-  const int cb = t * CPL;
-  const bool active = cb < a.C;
+  const bool store = t * CPL < a.C;
+  const int cb = store ? t * CPL : 0;
   const int wave = threadIdx.x >> 6;
   const int gw = (threadIdx.x & 63) >> a.logT;
-  const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+  const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
   if (i >= a.n_medium) return;                       // the whole wavefront leaves together
   const int e1 = a.tail_ptr[i + 1];
   Vec<CPL> acc;
   vzero(acc);
-  if (active) {
+  if (a.logT >= 3) {
+    const int gbase4 = (int)((threadIdx.x & 63) & ~(T - 1)) << 2;
+    for (int e = a.tail_ptr[i] + gw; e < e1; e += kRound * GPW)
+      gather_round_bcast<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, GPW,
+                                               min(kRound, (e1 - e + GPW - 1) / GPW), a.Y, a.C,
+                                               cb, a.dscale, a.inv_nt, gbase4, t & 7, acc);
+  } else {
     for (int e = a.tail_ptr[i] + gw; e < e1; e += kRound * GPW)
       gather_round<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, GPW,
-                                         min(kRound, (e1 - e + GPW - 1) / GPW), a.Y,
-                                         a.C, cb, a.dscale, a.inv_nt, acc);
+                                         min(kRound, (e1 - e + GPW - 1) / GPW), a.Y, a.C, cb,
+                                         a.dscale, a.inv_nt, acc);
   }
   wave_reduce_groups(acc, T);
-  if (gw == 0 && active) store_vec(a.X + (int64_t)a.tail_rows[i] * a.C + cb, acc);
+  if (gw == 0 && store) store_vec(a.X + (int64_t)a.tail_rows[i] * a.C + cb, acc);
 }
 
 // one block per chunk of a long row: partial sums to the scratch buffer
@@ -239,18 +317,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_chunk(AdjArgs a, const V* __rest
   const int T = 1 << a.logT;
   const int RPB = kBlock >> a.logT;
   const int g = threadIdx.x >> a.logT, t = threadIdx.x & (T - 1);
-  const int cb = t * CPL;
-  const bool active = cb < a.C;
-  const int64_t bid = blockIdx.x;
-  __shared__ float red[(kBlock / 64) * 256];
+  const bool active = t * CPL < a.C;
+  const int cb = active ? t * CPL : 0;
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);   // chunks of one row share an L2
+  __shared__ float red[(kBlock / 64) * 256];              // T * 2 * CPL <= 256 since C <= 128
   const int e1 = a.chunk_end[bid];
   Vec<CPL> acc;
   vzero(acc);
-  if (active) {
+  if (a.logT >= 3) {
+    const int gbase4 = (int)((threadIdx.x & 63) & ~(T - 1)) << 2;
+    for (int e = a.chunk_beg[bid] + g; e < e1; e += kRound * RPB)
+      gather_round_bcast<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, RPB,
+                                               min(kRound, (e1 - e + RPB - 1) / RPB), a.Y, a.C,
+                                               cb, a.dscale, a.inv_nt, gbase4, t & 7, acc);
+  } else {
     for (int e = a.chunk_beg[bid] + g; e < e1; e += kRound * RPB)
       gather_round<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, RPB,
-                                         min(kRound, (e1 - e + RPB - 1) / RPB), a.Y,
-                                         a.C, cb, a.dscale, a.inv_nt, acc);
+                                         min(kRound, (e1 - e + RPB - 1) / RPB), a.Y, a.C, cb,
+                                         a.dscale, a.inv_nt, acc);
   }
   wave_reduce_groups(acc, T);
   const int wave = threadIdx.x >> 6;

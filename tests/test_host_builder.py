@@ -166,3 +166,45 @@ def test_kernel_layouts_replay_the_csr_products(d, tuning):
     err = op.check_layouts()
     assert err < 1e-14                     # NaN (an unwritten row) fails too
     op.close()
+
+
+NORMAL_GEOMS = [g for g in GEOMS if g["n_det"] == g.get("grid", g["n_det"])
+                and g["n"] < 512 and "center" not in g]
+
+
+@pytest.mark.parametrize("d", NORMAL_GEOMS, ids=lambda d: "_".join(f"{k}{v}" for k, v in d.items()))
+@pytest.mark.parametrize("filt", ["none", "hamming"])
+def test_normal_stencil_matches_oracle_product(d, filt):
+    """W = S diag(D) S^dagger from the host builder (float64 stencil rows) against the oracle's
+    sparse product, entry by entry after re-indexing to the oracle's ordering."""
+    op = tomo.Operator(device=-1, max_batch=2, **d)
+    g = _oracle_geom(d)
+    ref = Operator(g)
+    D = np.ones(g.L) if filt == "none" else ramp_filter(g, filt)      # per centred k
+    dcol = np.tile(D, g.n_theta)                                          # oracle column a*L + k
+    W = (ref.S @ sp.diags(dcol) @ ref.S_dag).tocoo()
+    w = op.export_normal(filt)
+    G, R = g.G, g.kw - 1
+    S = 2 * R + 1
+    oG = G // 2
+    # oracle centred index -> FFT-ordered index
+    def fft_index(o):
+        j1, j2 = o // G - oG, o % G - oG
+        return (j1 % G) * G + (j2 % G)
+    r, c = fft_index(W.row), fft_index(W.col)
+    d1 = c // G - r // G
+    d2 = c % G - r % G
+    d1 = np.where(2 * d1 >= G, d1 - G, np.where(2 * d1 < -G, d1 + G, d1))
+    d2 = np.where(2 * d2 >= G, d2 - G, np.where(2 * d2 < -G, d2 + G, d2))
+    assert np.abs(d1).max() <= R and np.abs(d2).max() <= R
+    dense = np.zeros((G * G, S * S))
+    np.add.at(dense, (r, (d1 + R) * S + (d2 + R)), W.data)
+    assert np.abs(w - dense).max() <= 1e-13 * np.abs(dense).max()
+    op.close()
+
+
+def test_normal_operator_needs_full_detector():
+    op = tomo.Operator(12, 10, 16, grid=20, device=-1, max_batch=2)
+    with pytest.raises(tomo.TomoError, match="EUNSUPPORTED"):
+        op.export_normal()
+    op.close()
