@@ -28,7 +28,7 @@ N_IMG, N_ANG, N_DET, BATCH = 2048, 1501, 2048, 32
 WORKLOAD = "parallel-beam 2048x2048, 1501 angles in [0,pi), 2048 bins, batch 32 slices"
 COUNTERS = os.path.join(ROOT, "profiles", "spmm_2048_1501_b32_counters.json")
 SPMM_SOURCES = [os.path.join(ROOT, "paper_2003_12677_amd", "csrc", f)
-                for f in ("spmm.hip", "tiles.hip", "internal.h", "builder.cpp")]
+                for f in ("spmm.hip", "tiles.hip")]
 
 
 def parse():
@@ -83,15 +83,18 @@ def step_percentiles(torch, fn, iters: int):
     return {"p10": q(0.1), "p50": q(0.5), "p90": q(0.9)}
 
 
-def source_digest() -> str:
+def source_digest(tuning: dict) -> str:
+    """Identity of the SpMM kernels a counter summary was taken from: their sources and the
+    operator's layout tuning."""
     h = hashlib.sha256()
     for f in SPMM_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
+    h.update(json.dumps(tuning, sort_keys=True).encode())
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, tuning: dict):
     """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by the copy-kernel calibration), or None when the summary is missing or
     was taken from different kernel sources."""
@@ -100,7 +103,7 @@ def measured_traffic(kernel: str):
             c = json.load(fh)
     except (OSError, ValueError):
         return None
-    if c.get("source_sha256") != source_digest() or kernel not in c.get("kernels", {}):
+    if c.get("source_sha256") != source_digest(tuning) or kernel not in c.get("kernels", {}):
         return None
     k = c["kernels"][kernel]
     return {"read_bytes": k["read_bytes"], "write_bytes": k["write_bytes"],
@@ -249,7 +252,7 @@ def main():
         "step_ms_percentiles": pct,
         "roofline": {"bound": "hbm", "kernel": f"spmm_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"spmm_{dom}_bf16"),
+                     "traffic": measured_traffic(f"spmm_{dom}_bf16", op.get_tuning()),
                      "algorithmic_bytes": m[f"{dom}_bytes"], "frac_of_copy": achieved / copy_gbs},
         "copy_GBs": {"value": copy_gbs, "what": "torch copy_ of 1 GiB (read + write bytes / time)"},
         "kernels": res,

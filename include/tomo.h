@@ -140,6 +140,10 @@ typedef struct {
                                      split into partial sums (1..64)                           */
   int32_t normal_tiled;           /* normal operator: 1 stages each channel's grid tile (+ halo)
                                      in LDS; 0 reads every stencil tap through L1/L2           */
+  int32_t adj_sell_xcd_rows;      /* sliced-ELL adjoint kernel: its blocks go to the 8 XCDs in runs
+                                     covering this many consecutive rows (0 = one contiguous
+                                     range per XCD; 1 = dispatch order); 0..2^24                */
+  int32_t adj_medium_xcd_rows;    /* the same for the one-wavefront-per-row kernel           */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */

@@ -104,11 +104,11 @@ def reconstruct_tv(op: Operator, b: torch.Tensor, *, mu: float = 1e-3, eps: floa
         os.makedirs(checkpoint_dir, exist_ok=True)
         path = _checkpoint_path(checkpoint_dir)
         if resume and os.path.exists(path):
-            state = torch.load(path, map_location=b.device, weights_only=True)
+            state = torch.load(path, map_location="cpu", weights_only=True)
             with torch.no_grad():
                 x.copy_(state["x"])
-            opt.load_state_dict(state["adam"])
-            history = [h for h in state["history"]]
+            opt.load_state_dict(state["adam"])          # moves the moments to x's device
+            history = list(state["history"])
             start = int(state["step"])
     for k in range(start, steps):
         opt.zero_grad(set_to_none=False)

@@ -587,6 +587,8 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->tile_points = op->tune.tile_points;
   out->tile_chunks = op->tune.tile_chunks;
   out->normal_tiled = op->tune.normal_tiled;
+  out->adj_sell_xcd_rows = op->tune.sell_xcd_rows;
+  out->adj_medium_xcd_rows = op->tune.medium_xcd_rows;
   return TOMO_OK;
 }
 
@@ -606,6 +608,8 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.tile_points = in->tile_points;
   t.tile_chunks = in->tile_chunks;
   t.normal_tiled = in->normal_tiled;
+  t.sell_xcd_rows = in->adj_sell_xcd_rows;
+  t.medium_xcd_rows = in->adj_medium_xcd_rows;
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;

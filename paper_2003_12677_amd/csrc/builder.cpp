@@ -236,6 +236,9 @@ tomo_status check_tuning(const Tuning& t) {
     return fail(TOMO_EINVAL, "tile_points must be 32, 64, 96 or 128");
   if (t.tile_chunks < 1 || t.tile_chunks > 64) return fail(TOMO_EINVAL, "tile_chunks must be in [1, 64]");
   if (t.normal_tiled != 0 && t.normal_tiled != 1) return fail(TOMO_EINVAL, "normal_tiled must be 0 or 1");
+  if (t.sell_xcd_rows < 0 || t.sell_xcd_rows > (1 << 24) || t.medium_xcd_rows < 0 ||
+      t.medium_xcd_rows > (1 << 24))
+    return fail(TOMO_EINVAL, "XCD interleave rows must be in [0, 2^24]");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
     return fail(TOMO_EINVAL, "channels per lane must be 1, 2 or 4 (got %d, %d)", t.fwd_cpl, t.adj_cpl);
   if (t.sell_max < 0 || t.sell_max > 1024) return fail(TOMO_EINVAL, "sell_max %d not in [0, 1024]", t.sell_max);

@@ -68,6 +68,8 @@ struct Tuning {
   int tile_points = 128;  // forward: samples per block; adjoint: polar rows staged per chunk
   int tile_chunks = 1;    // adjoint: chunks one block accumulates before writing
   int normal_tiled = 1;   // normal operator: LDS-staged grid tiles (1) or direct taps (0)
+  int sell_xcd_rows = 8192;   // sliced-ELL adjoint: rows per XCD interleave run (0 = contiguous)
+  int medium_xcd_rows = 1024; // wave-per-row adjoint: rows per XCD interleave run
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout

@@ -41,6 +41,19 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
+// Blocks interleaved over the XCDs in runs of `chunk`: XCD x takes runs x, x+8, x+16, ... of
+// `chunk` consecutive logical blocks, so neighbouring rows still share an L2 while every XCD
+// gets a share of each part of the row range (the adjoint's row lengths vary with radius).
+// chunk 0 = one contiguous range per XCD (xcd_remap), chunk 1 = the dispatch order itself.
+__device__ __forceinline__ int64_t xcd_chunk_remap(int64_t bid, int64_t nblocks, int chunk) {
+  if (chunk <= 0) return xcd_remap(bid, nblocks);
+  const int64_t span = 8LL * chunk;
+  const int64_t full = nblocks / span * span;
+  if (bid >= full) return bid;
+  const int64_t x = bid & 7, local = bid >> 3;
+  return ((local / chunk) * 8 + x) * chunk + (local % chunk);
+}
+
 // CPL consecutive complex channels of one lane
 template <int CPL>
 struct Vec {
@@ -238,6 +251,7 @@ struct AdjArgs {
   const float2* Y;
   float2* X;
   int C, logT;
+  int sell_chunk, medium_chunk;   // block runs of the XCD interleave (xcd_chunk_remap)
   const float* dscale;        // per FFT-ordered radial index, or null
   double inv_nt;              // 1 / n_theta: radial index of polar column c is floor(c / nt)
 };
@@ -254,30 +268,20 @@ __device__ __forceinline__ void wave_reduce_groups(Vec<CPL>& acc, int T) {
 template <int CPL, typename V, bool FILT>
 __global__ __launch_bounds__(kBlock) void k_adj_sell(AdjArgs a, const V* __restrict__ val) {
   const int g = threadIdx.x >> a.logT, t = threadIdx.x & ((1 << a.logT) - 1);
-  const int64_t gid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock >> a.logT) + g;
+  const int64_t gid = xcd_chunk_remap(blockIdx.x, gridDim.x, a.sell_chunk) * (kBlock >> a.logT) + g;
   const int64_t slice = gid / kSliceRows;
   const int j = (int)(gid % kSliceRows);
-  if (slice >= a.n_slices) return;          // whole lane groups leave together
-  const bool store = t * CPL < a.C;
-  const int cb = store ? t * CPL : 0;
+  const int cb = t * CPL;
+  if (slice >= a.n_slices || cb >= a.C) return;
   const int32_t e0 = a.slice_ptr[slice];
   const int len = (a.slice_ptr[slice + 1] - e0) / kSliceRows;
   const int32_t row = a.slice_rows[gid];
   Vec<CPL> acc;
   vzero(acc);
-  if (a.logT >= 3) {
-    const int gbase4 = (int)((threadIdx.x & 63) & ~((1 << a.logT) - 1)) << 2;
-    for (int e = 0; e < len; e += kRound)
-      gather_round_bcast<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j, kSliceRows,
-                                               min(kRound, len - e), a.Y, a.C, cb, a.dscale,
-                                               a.inv_nt, gbase4, t & 7, acc);
-  } else {
-    for (int e = 0; e < len; e += kRound)
-      gather_round<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j, kSliceRows,
-                                         min(kRound, len - e), a.Y, a.C, cb, a.dscale, a.inv_nt,
-                                         acc);
-  }
-  if (row >= 0 && store) store_vec(a.X + (int64_t)row * a.C + cb, acc);
+  for (int e = 0; e < len; e += kRound)
+    gather_round<CPL, kRound, V, FILT>(a.col, val, e0 + e * kSliceRows + j, kSliceRows,
+                                       min(kRound, len - e), a.Y, a.C, cb, a.dscale, a.inv_nt, acc);
+  if (row >= 0) store_vec(a.X + (int64_t)row * a.C + cb, acc);
 }
 
 // one wavefront per medium row; lane groups stride the row's entries
@@ -286,29 +290,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_medium(AdjArgs a, const V* __res
   const int T = 1 << a.logT;
   const int GPW = 64 >> a.logT;
   const int t = threadIdx.x & (T - 1);
-  const bool store = t * CPL < a.C;
-  const int cb = store ? t * CPL : 0;
+  const int cb = t * CPL;
+  const bool active = cb < a.C;
   const int wave = threadIdx.x >> 6;
   const int gw = (threadIdx.x & 63) >> a.logT;
-  const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
+  const int64_t i = xcd_chunk_remap(blockIdx.x, gridDim.x, a.medium_chunk) * (kBlock / 64) + wave;
   if (i >= a.n_medium) return;                       // the whole wavefront leaves together
   const int e1 = a.tail_ptr[i + 1];
   Vec<CPL> acc;
   vzero(acc);
-  if (a.logT >= 3) {
-    const int gbase4 = (int)((threadIdx.x & 63) & ~(T - 1)) << 2;
-    for (int e = a.tail_ptr[i] + gw; e < e1; e += kRound * GPW)
-      gather_round_bcast<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, GPW,
-                                               min(kRound, (e1 - e + GPW - 1) / GPW), a.Y, a.C,
-                                               cb, a.dscale, a.inv_nt, gbase4, t & 7, acc);
-  } else {
+  if (active) {
     for (int e = a.tail_ptr[i] + gw; e < e1; e += kRound * GPW)
       gather_round<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, GPW,
                                          min(kRound, (e1 - e + GPW - 1) / GPW), a.Y, a.C, cb,
                                          a.dscale, a.inv_nt, acc);
   }
   wave_reduce_groups(acc, T);
-  if (gw == 0 && store) store_vec(a.X + (int64_t)a.tail_rows[i] * a.C + cb, acc);
+  if (gw == 0 && active) store_vec(a.X + (int64_t)a.tail_rows[i] * a.C + cb, acc);
 }
 
 // one block per chunk of a long row: partial sums to the scratch buffer
@@ -317,20 +315,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_chunk(AdjArgs a, const V* __rest
   const int T = 1 << a.logT;
   const int RPB = kBlock >> a.logT;
   const int g = threadIdx.x >> a.logT, t = threadIdx.x & (T - 1);
-  const bool active = t * CPL < a.C;
-  const int cb = active ? t * CPL : 0;
-  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);   // chunks of one row share an L2
+  const int cb = t * CPL;
+  const bool active = cb < a.C;
+  const int64_t bid = blockIdx.x;
   __shared__ float red[(kBlock / 64) * 256];              // T * 2 * CPL <= 256 since C <= 128
   const int e1 = a.chunk_end[bid];
   Vec<CPL> acc;
   vzero(acc);
-  if (a.logT >= 3) {
-    const int gbase4 = (int)((threadIdx.x & 63) & ~(T - 1)) << 2;
-    for (int e = a.chunk_beg[bid] + g; e < e1; e += kRound * RPB)
-      gather_round_bcast<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, RPB,
-                                               min(kRound, (e1 - e + RPB - 1) / RPB), a.Y, a.C,
-                                               cb, a.dscale, a.inv_nt, gbase4, t & 7, acc);
-  } else {
+  if (active) {
     for (int e = a.chunk_beg[bid] + g; e < e1; e += kRound * RPB)
       gather_round<CPL, kRound, V, FILT>(a.tail_col, tail_val, e, RPB,
                                          min(kRound, (e1 - e + RPB - 1) / RPB), a.Y, a.C, cb,
@@ -436,6 +428,12 @@ tomo_status adj_impl(const tomo_op* op, int vt, const float2* Y, float2* X, int 
   a.C = C;
   a.dscale = dscale;
   a.inv_nt = 1.0 / (double)op->g.nt;
+  // XCD interleave runs in blocks from the row counts (0 stays "contiguous")
+  auto run_blocks = [](int rows, int64_t rows_per_block) {
+    return rows <= 0 ? 0 : (int)std::max<int64_t>(1, rows / rows_per_block);
+  };
+  a.sell_chunk = run_blocks(op->tune.sell_xcd_rows, rpb);
+  a.medium_chunk = run_blocks(op->tune.medium_xcd_rows, kBlock / 64);
   const V* v = (const V*)d.val[vt];
   const V* tv = (const V*)d.tail_val[vt];
 #define TOMO_ADJ_LAUNCH(KERNEL, NB, VALS)                                                     \

@@ -200,6 +200,8 @@ TUNINGS = [
     dict(tile=8, tile_points=32, tile_chunks=1),                  # staged, many split tiles
     dict(tile=32, tile_points=64, tile_chunks=2),
     dict(fwd_tiled=1, adj_tiled=0),
+    dict(ROW, adj_sell_xcd_rows=64, adj_medium_xcd_rows=8),       # short XCD interleave runs
+    dict(ROW, adj_sell_xcd_rows=0, adj_medium_xcd_rows=0),        # one contiguous range per XCD
 ]
 
 
