@@ -118,7 +118,7 @@ typedef struct {
 
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB, else the row kernels.
- * Defaults: 2, 2, 16, 4096, 256, 256, 0, 0, 8, 128, 1. */
+ * Defaults (in field order): 2, 2, 48, 4096, 128, 1024, 0, 0, 8, 128, 1, 1, 8192, 1024, 2. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -144,6 +144,8 @@ typedef struct {
                                      covering this many consecutive rows (0 = one contiguous
                                      range per XCD; 1 = dispatch order); 0..2^24                */
   int32_t adj_medium_xcd_rows;    /* the same for the one-wavefront-per-row kernel           */
+  int32_t fwd_rows_per_group;     /* forward SpMM (3x3 stencil, >= 8 lanes per row): rows one lane
+                                     group handles in a software pipeline (1, 2 or 4)           */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */

@@ -589,6 +589,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->normal_tiled = op->tune.normal_tiled;
   out->adj_sell_xcd_rows = op->tune.sell_xcd_rows;
   out->adj_medium_xcd_rows = op->tune.medium_xcd_rows;
+  out->fwd_rows_per_group = op->tune.fwd_rows_per_group;
   return TOMO_OK;
 }
 
@@ -610,6 +611,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.normal_tiled = in->normal_tiled;
   t.sell_xcd_rows = in->adj_sell_xcd_rows;
   t.medium_xcd_rows = in->adj_medium_xcd_rows;
+  t.fwd_rows_per_group = in->fwd_rows_per_group;
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;

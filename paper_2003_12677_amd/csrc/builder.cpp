@@ -239,6 +239,8 @@ tomo_status check_tuning(const Tuning& t) {
   if (t.sell_xcd_rows < 0 || t.sell_xcd_rows > (1 << 24) || t.medium_xcd_rows < 0 ||
       t.medium_xcd_rows > (1 << 24))
     return fail(TOMO_EINVAL, "XCD interleave rows must be in [0, 2^24]");
+  if (t.fwd_rows_per_group != 1 && t.fwd_rows_per_group != 2 && t.fwd_rows_per_group != 4)
+    return fail(TOMO_EINVAL, "fwd_rows_per_group must be 1, 2 or 4");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
     return fail(TOMO_EINVAL, "channels per lane must be 1, 2 or 4 (got %d, %d)", t.fwd_cpl, t.adj_cpl);
   if (t.sell_max < 0 || t.sell_max > 1024) return fail(TOMO_EINVAL, "sell_max %d not in [0, 1024]", t.sell_max);

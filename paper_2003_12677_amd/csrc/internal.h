@@ -58,10 +58,10 @@ struct HostCSR {
 struct Tuning {
   int fwd_cpl = 2;        // complex channels per lane in the forward kernel (1, 2 or 4)
   int adj_cpl = 2;        // complex channels per lane in the adjoint kernel (1, 2 or 4)
-  int sell_max = 16;      // S rows with <= sell_max entries: sliced ELL, 8 rows per slice
+  int sell_max = 48;      // S rows with <= sell_max entries: sliced ELL, 8 rows per slice
   int sell_sigma = 4096;  // rows are sorted by length within windows of sell_sigma rows
-  int medium_max = 256;   // longer rows up to medium_max entries: one wavefront per row
-  int chunk = 256;        // rows above medium_max: chunks of <= chunk entries, one block each
+  int medium_max = 128;   // longer rows up to medium_max entries: one wavefront per row
+  int chunk = 1024;       // rows above medium_max: chunks of <= chunk entries, one block each
   int fwd_tiled = 0;      // forward: 1 = LDS-staged Cartesian tiles, 0 = row kernel
   int adj_tiled = 0;      // adjoint: 1 = LDS-staged polar chunks per output tile, 0 = row kernels
   int tile = 8;           // Cartesian tile side of the staged kernels (8, 16 or 32)
@@ -70,6 +70,7 @@ struct Tuning {
   int normal_tiled = 1;   // normal operator: LDS-staged grid tiles (1) or direct taps (0)
   int sell_xcd_rows = 8192;   // sliced-ELL adjoint: rows per XCD interleave run (0 = contiguous)
   int medium_xcd_rows = 1024; // wave-per-row adjoint: rows per XCD interleave run
+  int fwd_rows_per_group = 2; // forward: rows per lane group in the pipelined kernel (1, 2, 4)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout

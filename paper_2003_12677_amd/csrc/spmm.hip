@@ -137,7 +137,12 @@ __device__ __forceinline__ void gather_round(const int32_t* __restrict__ col,
   }
   Vec<CPL> x[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = load_vec<CPL>(src + (int64_t)(ok[u] ? c[u] : 0) * C + cb);
+  for (int u = 0; u < U; ++u) {
+    if (u < count)   // uniform in a lane group: slots past the round's end issue no request
+      x[u] = load_vec<CPL>(src + (int64_t)(ok[u] ? c[u] : 0) * C + cb);
+    else
+      vzero(x[u]);
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -146,34 +151,40 @@ __device__ __forceinline__ void gather_round(const int32_t* __restrict__ col,
 
 // The same round with the metadata loaded once per lane group instead of once per lane, for
 // groups of at least 8 lanes: lane t fetches the column and value of entries s*8 + (t & 7) of the
-// round (slot s), applies the padding test and the filter, and every lane then reads entry u
-// from lane (u & 7) of its group with a cross-lane permute.  All lanes of the group must be
-// active (lanes beyond the channel count still load metadata and gather an in-bounds vector).
-template <int CPL, int U, typename V, bool FILT>
-__device__ __forceinline__ void gather_round_bcast(const int32_t* __restrict__ col,
-                                                   const V* __restrict__ val, int base,
-                                                   int stride, int count,
-                                                   const float2* __restrict__ src, int C, int cb,
-                                                   const float* __restrict__ dscale,
-                                                   double inv_nt, int gbase4, int t8,
-                                                   Vec<CPL>& acc) {
-  constexpr int S = (U + 7) / 8;
-  int cl[S];
-  uint32_t rl[S];
+// round (slot s); every lane then reads entry u from lane (u & 7) of its group with a cross-lane
+// permute.  All lanes of the group must be active (lanes beyond the channel count still load
+// metadata and gather an in-bounds vector).  Split in two phases so that a caller can issue the
+// next row's metadata loads before it uses the current row's.
+template <int U, typename V>
+__device__ __forceinline__ void bcast_meta_load(const int32_t* __restrict__ col,
+                                                const V* __restrict__ val, int base, int stride,
+                                                int count, int t8, int (&cl)[(U + 7) / 8],
+                                                uint32_t (&rl)[(U + 7) / 8]) {
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
+  for (int s = 0; s < (U + 7) / 8; ++s) {
     const int u = s * 8 + t8;
     const int e = (u < count) ? base + u * stride : base;
     cl[s] = col[e];
     rl[s] = ldraw(val, e);
   }
+}
+
+template <int CPL, int U, typename V, bool FILT>
+__device__ __forceinline__ void bcast_meta_use(const V* val, int count, int t8,
+                                               const int (&cl_in)[(U + 7) / 8],
+                                               const uint32_t (&rl)[(U + 7) / 8],
+                                               const float2* __restrict__ src, int C, int cb,
+                                               const float* __restrict__ dscale, double inv_nt,
+                                               int gbase4, Vec<CPL>& acc) {
+  constexpr int S = (U + 7) / 8;
+  int cl[S];
   float wl[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const bool ok = (s * 8 + t8 < count) && (cl[s] >= 0);
+    const bool ok = (s * 8 + t8 < count) && (cl_in[s] >= 0);
     wl[s] = cvt(val, rl[s]);
-    if constexpr (FILT) wl[s] *= dscale[ok ? (int)(((double)cl[s] + 0.5) * inv_nt) : 0];
-    cl[s] = ok ? cl[s] : -1;
+    if constexpr (FILT) wl[s] *= dscale[ok ? (int)(((double)cl_in[s] + 0.5) * inv_nt) : 0];
+    cl[s] = ok ? cl_in[s] : -1;
   }
   int c[U];
   float w[U];
@@ -185,11 +196,30 @@ __device__ __forceinline__ void gather_round_bcast(const int32_t* __restrict__ c
   }
   Vec<CPL> x[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) x[u] = load_vec<CPL>(src + (int64_t)(c[u] >= 0 ? c[u] : 0) * C + cb);
+  for (int u = 0; u < U; ++u) {
+    if (u < count)
+      x[u] = load_vec<CPL>(src + (int64_t)(c[u] >= 0 ? c[u] : 0) * C + cb);
+    else
+      vzero(x[u]);
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int i = 0; i < 2 * CPL; ++i) acc.v[i] += w[u] * (c[u] >= 0 ? x[u].v[i] : 0.f);
+}
+
+template <int CPL, int U, typename V, bool FILT>
+__device__ __forceinline__ void gather_round_bcast(const int32_t* __restrict__ col,
+                                                   const V* __restrict__ val, int base,
+                                                   int stride, int count,
+                                                   const float2* __restrict__ src, int C, int cb,
+                                                   const float* __restrict__ dscale,
+                                                   double inv_nt, int gbase4, int t8,
+                                                   Vec<CPL>& acc) {
+  int cl[(U + 7) / 8];
+  uint32_t rl[(U + 7) / 8];
+  bcast_meta_load<U, V>(col, val, base, stride, count, t8, cl, rl);
+  bcast_meta_use<CPL, U, V, FILT>(val, count, t8, cl, rl, src, C, cb, dscale, inv_nt, gbase4, acc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -230,6 +260,44 @@ __global__ __launch_bounds__(kBlock) void k_fwd_ell(const int32_t* __restrict__ 
     }
   }
   if (store) store_vec(Y + row * C + cb, acc);
+}
+
+// Software-pipelined forward for the fixed 9-entry stencil and lane groups of >= 8 lanes: each
+// group handles RPG rows (at stride "groups per block", so a wavefront's groups work on
+// consecutive rows at every step) and issues the next row's metadata loads before it uses the
+// current row's, so the metadata round trip overlaps the previous row's gathers.
+template <int CPL, typename V, int RPG>
+__global__ __launch_bounds__(kBlock) void k_fwd_pipe(const int32_t* __restrict__ col,
+                                                     const V* __restrict__ val,
+                                                     const float2* __restrict__ X,
+                                                     float2* __restrict__ Y, int64_t nrows, int C,
+                                                     int logT) {
+  constexpr int W2 = 9, S = (W2 + 7) / 8;
+  const int GPB = kBlock >> logT;
+  const int g = threadIdx.x >> logT, t = threadIdx.x & ((1 << logT) - 1);
+  const int64_t first = xcd_remap(blockIdx.x, gridDim.x) * (int64_t)GPB * RPG + g;
+  if (first >= nrows) return;               // later rows of the group are beyond too
+  const bool store = t * CPL < C;
+  const int cb = store ? t * CPL : 0;
+  const int gbase4 = (int)((threadIdx.x & 63) & ~((1 << logT) - 1)) << 2;
+  const int t8 = t & 7;
+  int cl[2][S];
+  uint32_t rl[2][S];
+  bcast_meta_load<W2, V>(col, val, (int)first * W2, 1, W2, t8, cl[0], rl[0]);
+#pragma unroll
+  for (int i = 0; i < RPG; ++i) {
+    const int64_t row = first + (int64_t)i * GPB;
+    if (i + 1 < RPG) {
+      const int64_t nxt = min(row + GPB, nrows - 1);       // past the end: a valid row, unused
+      bcast_meta_load<W2, V>(col, val, (int)nxt * W2, 1, W2, t8, cl[(i + 1) & 1],
+                             rl[(i + 1) & 1]);
+    }
+    Vec<CPL> acc;
+    vzero(acc);
+    bcast_meta_use<CPL, W2, V, false>(val, W2, t8, cl[i & 1], rl[i & 1], X, C, cb, nullptr, 0.0,
+                                      gbase4, acc);
+    if (store && row < nrows) store_vec(Y + row * C + cb, acc);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -392,6 +460,18 @@ tomo_status fwd_impl(const tomo_op* op, const void* val, const float2* X, float2
   const int64_t rpb = kBlock >> logT;
   const int64_t nb = (rows + rpb - 1) / rpb;
   const int W2 = op->fwd.W2;
+  const int rpg = op->tune.fwd_rows_per_group;
+  if (W2 == 9 && logT >= 3 && rpg > 1) {
+    const int64_t nbp = (rows + rpb * rpg - 1) / (rpb * rpg);
+    if (rpg == 2)
+      hipLaunchKernelGGL((k_fwd_pipe<CPL, V, 2>), dim3((unsigned)nbp), dim3(kBlock), 0, st,
+                         op->fwd.col, (const V*)val, X, Y, rows, C, logT);
+    else
+      hipLaunchKernelGGL((k_fwd_pipe<CPL, V, 4>), dim3((unsigned)nbp), dim3(kBlock), 0, st,
+                         op->fwd.col, (const V*)val, X, Y, rows, C, logT);
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
   if (W2 == 9)
     hipLaunchKernelGGL((k_fwd_ell<CPL, V, 9>), dim3((unsigned)nb), dim3(kBlock), 0, st,
                        op->fwd.col, (const V*)val, X, Y, rows, C, logT, W2);

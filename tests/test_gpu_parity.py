@@ -202,6 +202,8 @@ TUNINGS = [
     dict(fwd_tiled=1, adj_tiled=0),
     dict(ROW, adj_sell_xcd_rows=64, adj_medium_xcd_rows=8),       # short XCD interleave runs
     dict(ROW, adj_sell_xcd_rows=0, adj_medium_xcd_rows=0),        # one contiguous range per XCD
+    dict(ROW, fwd_rows_per_group=2),                              # pipelined forward
+    dict(ROW, fwd_rows_per_group=4),
 ]
 
 
