@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=8.0,
                    help="budget of each oracle sample (one process, then all host cores)")
     p.add_argument("--extras", type=int, default=1, help="also time the full operator and CGLS")
+    p.add_argument("--accuracy", action="store_true",
+                   help="also compare float32 and mixed-precision CGLS-100 with the FP64 oracle on 4 "
+                        "noisy slices and time CGLS-100 on a 256-slice stack (several minutes)")
     return p.parse_args()
 
 
@@ -133,35 +136,118 @@ def _oracle_slices(budget_s: float, max_slices: int, seed: int):
 
 _ORACLE = {}
 
+ACC_SLICES, ACC_ITERS = 4, 100
 
-def cpu_baseline(budget_s: float):
-    """The FP64 oracle's forward and adjoint sparse products (S^dagger U, S V') per slice on the
-    host: one process, then one process per usable host core, each on its own slices (the
-    slice decomposition of Sec. 3.1).  Runs before anything touches the GPU, so the forked
-    workers hold no GPU state."""
+
+def _accuracy_inputs():
+    """Seeded noisy sinograms in pixel units: exact line integrals of 10 random ellipses per slice
+    with Poisson noise at I0 = 1e4, stored as float32 (what the GPU receives); and the phantoms
+    themselves rasterised with 2x2 supersampling (the ground truth)."""
+    import math
+
+    import numpy as np
+
+    from synth import (ellipse_params, ellipse_sinogram, poisson_log_sinogram,
+                       rasterize_ellipses, slice_rng)
+
+    th = np.arange(N_ANG) * math.pi / N_ANG
+    sinos, truth = [], []
+    for s in range(ACC_SLICES):
+        rng = slice_rng(3000 + s)
+        E = ellipse_params(rng, 10, contained=True)
+        P = poisson_log_sinogram(rng, ellipse_sinogram(E, th, N_DET, N_DET // 2, N_IMG), 1e4)
+        sinos.append((P / (2.0 / N_IMG)).astype(np.float32))
+        truth.append(rasterize_ellipses(E, N_IMG, 2))
+    return np.stack(sinos), truth
+
+
+def _progress(tag: str):
+    calls = [0]
+
+    def hook(v):                 # identity on the stored vectors; reports every 10 iterations
+        calls[0] += 1
+        if calls[0] % 50 == 0:
+            print(f"oracle {tag}: ~{calls[0] // 5} iterations", file=sys.stderr, flush=True)
+        return v
+
+    return hook
+
+
+def _oracle_solves(s: int):
+    """FP64 CGLS-100, and the FP64 form of the mixed-precision solve (4 outer steps with
+    float32-rounded values for the residual, 25 inner CGLS steps with bfloat16-rounded values)."""
+    from oracle import cgls, refine
+
+    hi, hi32, lo = _ORACLE["op"], _ORACLE["op32"], _ORACLE["op16"]
+    b = _ORACLE["b"][s].astype("float64")
+    x = cgls(hi.project, hi.backproject, b, ACC_ITERS, store=_progress(f"CGLS slice {s}"))
+    xr = refine(hi32.project, lo.project, lo.backproject, b, 4, ACC_ITERS // 4,
+                store=_progress(f"refinement slice {s}"))
+    return x, xr
+
+
+def accuracy_reference():
+    """The oracle's solves of each accuracy slice, one forked process per slice, before the GPU
+    is touched."""
     import multiprocessing as mp
 
-    from oracle import Geometry, Operator
+    from oracle import Geometry, Operator, round_values
 
+    b, truth = _accuracy_inputs()
+    op = Operator(Geometry(N_IMG, N_ANG, N_DET))
+    _ORACLE.update(op=op, op32=Operator(op.geom, S=round_values(op.S, "f32")),
+                   op16=Operator(op.geom, S=round_values(op.S, "bf16")), b=b)
     t0 = time.perf_counter()
-    _ORACLE["op"] = Operator(Geometry(N_IMG, N_ANG, N_DET))
-    build_s = time.perf_counter() - t0
-    one, el1 = _oracle_slices(budget_s, 64, 0)
-    cores = min(16, len(os.sched_getaffinity(0)))
-    ctx = mp.get_context("fork")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        parts = pool.starmap(_oracle_slices, [(budget_s, 64, 1 + i) for i in range(cores)])
-    wall = time.perf_counter() - t0
-    done = sum(p[0] for p in parts)
-    rate = sum(p[0] / p[1] for p in parts)      # concurrent processes, each over its own loop
+    with mp.get_context("fork").Pool(ACC_SLICES) as pool:
+        xs = pool.map(_oracle_solves, range(ACC_SLICES))
+    el = time.perf_counter() - t0
     _ORACLE.clear()
-    return {"value": rate, "unit": "slices/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} slices of S^dagger U + S V' (scipy CSR, complex128 vectors) in "
-                      f"{cores} concurrent processes, about {budget_s:.0f} s each ({wall:.1f} s "
-                      f"wall); operator build {build_s:.1f} s not timed",
-            "single_process": {"value": one / el1, "cores": 1,
-                               "sample": f"{one} slices in {el1:.1f} s"}}
+    return b, truth, xs, el
+
+
+def accuracy_leg(torch, tomo, op, ref):
+    """Errors of the GPU reconstructions against the oracle's (the same algorithm in float64) and
+    against the phantoms, and CGLS-100 wall time for a 256-slice stack (8 batches of 32)."""
+    import numpy as np
+
+    b_host, truth, x_ref, oracle_s = ref
+    dev = torch.device("cuda:0")
+    b = torch.from_numpy(b_host).to(dev)
+
+    def rel(a, r):
+        return float(np.linalg.norm(a - r) / np.linalg.norm(r))
+
+    forms = {"cgls_f32": dict(iters=ACC_ITERS),
+             "cgls_bf16": dict(iters=ACC_ITERS, values="bf16"),
+             "cgls_mixed_bf16_4x25": dict(iters=ACC_ITERS // 4, refine_outer=4, values="bf16"),
+             "cgnr_f32": dict(iters=ACC_ITERS, method="cgnr")}
+    res = {"slices": ACC_SLICES, "iterations": ACC_ITERS, "oracle_seconds": oracle_s,
+           "inputs": "exact ellipse line integrals with Poisson noise (I0 = 1e4), float32",
+           "oracle_cgls_vs_phantom": [rel(x_ref[s][0], truth[s]) for s in range(ACC_SLICES)]}
+    for name, kw in forms.items():
+        xh = op.solve(b, **kw).cpu().numpy().astype(np.float64)
+        same = 1 if "4x25" in name else 0        # the oracle solve of the same algorithm
+        res[name] = {"rel_l2_vs_oracle_same_algorithm":
+                     [rel(xh[s], x_ref[s][same]) for s in range(ACC_SLICES)],
+                     "rel_l2_vs_phantom": [rel(xh[s], truth[s]) for s in range(ACC_SLICES)]}
+    e32 = np.mean(res["cgls_f32"]["rel_l2_vs_phantom"])
+    res["mixed_over_f32_phantom_error"] = float(np.mean(res["cgls_mixed_bf16_4x25"]["rel_l2_vs_phantom"]) / e32)
+    res["bf16_over_f32_phantom_error"] = float(np.mean(res["cgls_bf16"]["rel_l2_vs_phantom"]) / e32)
+    # timing: 256 slices as 8 batches of 32 (inputs: projections of random images; speed does
+    # not depend on the values)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    stack = op.project(torch.rand((BATCH, N_IMG, N_IMG), generator=gen, device=dev))
+    xb = torch.empty((BATCH, N_IMG, N_IMG), device=dev)
+    for name, kw in forms.items():
+        op.solve(stack, xb, **dict(kw, iters=1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(256 // BATCH):
+            op.solve(stack, xb, **kw)
+        torch.cuda.synchronize()
+        res[name]["stack256_seconds"] = time.perf_counter() - t0
+    return res
 
 
 def main():
@@ -170,6 +256,7 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    acc_ref = accuracy_reference() if args.accuracy else None
     import torch
 
     import paper_2003_12677_amd as tomo
@@ -291,6 +378,8 @@ def main():
         ms_cn1 = time_loop(torch, lambda: op.solve(y, xb, iters=0, method="cgnr"), 2)
         out["cgls"] = {"ms_per_iteration_f32": (ms_cg - ms_cg1) / 10, "batch": BATCH,
                        "normal_form_ms_per_iteration_f32": (ms_cn - ms_cn1) / 10}
+    if acc_ref is not None:
+        out["accuracy"] = accuracy_leg(torch, tomo, op, acc_ref)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     op.close()
