@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=8.0,
                    help="budget of each oracle sample (one process, then all host cores)")
     p.add_argument("--extras", type=int, default=1, help="also time the full operator and CGLS")
+    p.add_argument("--uneven", action="store_true",
+                   help="also time a 200-slice stack of mixed sizes (256..2048, fp16 values) as "
+                        "eager launches and as one HIP graph, each operator autotuned")
     p.add_argument("--accuracy", action="store_true",
                    help="also compare float32 and mixed-precision CGLS-100 with the FP64 oracle on 4 "
                         "noisy slices and time CGLS-100 on a 256-slice stack (several minutes)")
@@ -250,6 +253,62 @@ def accuracy_leg(torch, tomo, op, ref):
     return res
 
 
+def uneven_leg(torch, tomo):
+    """200 slices with sizes drawn from {256, 512, 1024, 2048}^2 (seeded), 0.75 N angles,
+    round(N sqrt 2) bins, fp16 matrix values: one operator per size, autotuned for batches of
+    32; each operator's slices go in batches of <= 32 (the last one uneven).  One step = the
+    forward + adjoint SpMM of every batch; timed as eager launches and as one HIP graph."""
+    import math
+
+    import numpy as np
+
+    sizes = np.random.default_rng(2020).choice([256, 512, 1024, 2048], size=200)
+    dev = torch.device("cuda:0")
+    res = {"slices": 200, "values": "f16", "operators": []}
+    steps, eager = [], []
+    for n in (256, 512, 1024, 2048):
+        count = int((sizes == n).sum())
+        if count == 0:
+            continue
+        nt, npb = round(0.75 * n), round(n * math.sqrt(2))
+        op = tomo.Operator(n, nt, npb, max_batch=BATCH, values=("f16",), device=0)
+        tune = op.autotune(BATCH, values="f16")
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(n)
+        batches = [BATCH] * (count // BATCH) + ([count % BATCH] if count % BATCH else [])
+        bufs = {}
+        for b in sorted(set(batches)):            # one buffer set per batch width
+            Xc = torch.rand(op.cart_shape(b), generator=gen, device=dev)
+            bufs[b] = (Xc, torch.empty(op.polar_shape(b), device=dev), torch.empty_like(Xc))
+        for b in batches:
+            Xc, Yp, Xa = bufs[b]
+            steps.append(dict(op=op, kind="spmm_pair", batch=b, values="f16", inp=Xc, out=Yp, aux=Xa))
+            eager.append((op, b, Xc, Yp, Xa))
+        res["operators"].append({"n": n, "n_angles": nt, "n_det": npb, "slices": count,
+                                 "batches": batches, "nnz": op.info.nnz,
+                                 "tuned": {k: tune[k] for k in ("fwd_rows_per_group",
+                                           "fwd_channels_per_lane", "adj_channels_per_lane",
+                                           "adj_sell_max", "adj_medium_max",
+                                           "adj_sell_xcd_rows", "adj_medium_xcd_rows")},
+                                 "tuned_ms_b32": [tune["fwd_ms"], tune["adj_ms"]]})
+
+    def run_eager():
+        for op, b, Xc, Yp, Xa in eager:
+            op.slice_fwd(Xc, b, Yp=Yp, values="f16")
+            op.slice_adj(Yp, b, Xc=Xa, values="f16")
+
+    graph = tomo.Graph(steps)
+    for _ in range(3):
+        run_eager()
+        graph.launch()
+    ms_e = time_loop(torch, run_eager, 20)
+    ms_g = time_loop(torch, graph.launch, 20)
+    graph.close()
+    res.update(steps=len(steps), eager_ms=ms_e, graph_ms=ms_g,
+               eager_slices_per_s=200 / (ms_e * 1e-3), graph_slices_per_s=200 / (ms_g * 1e-3))
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -380,6 +439,8 @@ def main():
                        "normal_form_ms_per_iteration_f32": (ms_cn - ms_cn1) / 10}
     if acc_ref is not None:
         out["accuracy"] = accuracy_leg(torch, tomo, op, acc_ref)
+    if args.uneven:
+        out["uneven_stack"] = uneven_leg(torch, tomo)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     op.close()

@@ -277,6 +277,56 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out);
  * the operator is unchanged), TOMO_ENOMEM. */
 tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* t);
 
+/* Autotuner: search the SpMM layout parameters for `batch` slices with value type `values` by
+ * timing tomo_slice_fwd / tomo_slice_adj on the operator's own work buffers (hashed inputs;
+ * HIP events on a private stream), one parameter at a time over short candidate lists
+ * (forward rows per group and channels per lane; adjoint channels per lane, sliced-ELL and
+ * wave-per-row bounds, XCD interleave runs), `rounds` passes (1..8).  The fastest setting is
+ * applied to the operator and returned in *best (nullable), with its times in *fwd_ms /
+ * *adj_ms (nullable).  Synchronises the device; results of the operator do not depend on the
+ * tuning except through float32 summation order.  Overwrites the operator's work buffers, so
+ * it must not overlap other calls on the operator.  Errors: TOMO_EINVAL, TOMO_ESTATE,
+ * TOMO_ENOMEM, TOMO_EHIP. */
+tomo_status tomo_autotune(tomo_op* op, int32_t batch, int32_t values, int32_t rounds,
+                          tomo_tuning* best, double* fwd_ms, double* adj_ms);
+
+/* Several operators' work recorded as one HIP graph (stream capture), for stacks of slices of
+ * different sizes: each step is one operation of one operator on caller buffers.  Creating the
+ * graph runs every step once eagerly (creating FFT plans and normal-operator stencils on first
+ * use), then records the same launches; tomo_graph_launch replays them in order with one call.
+ * The graph holds the pointers given here: the buffers must stay allocated and the operators
+ * alive (and not re-tuned) while the graph is used; replays read the buffers' current
+ * contents.  Steps of one operator share its work buffers, so graph replays must not overlap
+ * other calls on those operators.  All operators must be on one device. */
+typedef enum {
+  TOMO_STEP_SPMM_PAIR = 0,     /* in = Xc (cart layout) -> out = Yp (polar) -> aux = Xc' (cart):
+                                  tomo_slice_fwd then tomo_slice_adj                          */
+  TOMO_STEP_PROJECT = 1,       /* in = x -> out = y (tomo_project)                           */
+  TOMO_STEP_BACKPROJECT = 2,   /* in = y -> out = x (tomo_backproject)                       */
+  TOMO_STEP_NORMAL = 3         /* in = x -> out = A^T A x (tomo_normal, no filter)            */
+} tomo_step_kind;
+
+typedef struct {
+  tomo_op* op;
+  int32_t kind;          /* tomo_step_kind                                                  */
+  int32_t batch;         /* slices (>= 1, <= the operator's max_batch)                     */
+  int32_t values;        /* tomo_value_type                                                 */
+  int32_t reserved;
+  const float* in;       /* device, 16-byte aligned                                         */
+  float* out;            /* device, 16-byte aligned                                         */
+  float* aux;            /* device, 16-byte aligned; TOMO_STEP_SPMM_PAIR only               */
+} tomo_step;
+
+typedef struct tomo_graph tomo_graph;
+
+/* Errors: TOMO_EINVAL (bad step, mixed devices), TOMO_ESTATE, TOMO_EUNSUPPORTED, TOMO_EHIP,
+ * TOMO_EFFT; *out is NULL on error. */
+tomo_status tomo_graph_create(const tomo_step* steps, int32_t n, tomo_graph** out);
+/* Replay on `stream` (a hipStream_t; NULL = the null stream).  Errors: TOMO_EINVAL, TOMO_EHIP. */
+tomo_status tomo_graph_launch(tomo_graph* g, void* stream);
+/* Free the graph (NULL is a no-op); does not synchronise. */
+void tomo_graph_destroy(tomo_graph* g);
+
 /* Host self-check (no device access): rebuild every kernel layout for the current tuning on
  * the host, apply each one in float64 following the kernels' traversal, and report the largest
  * relative difference from the CSR products in *max_rel_err (about 1e-16 when correct; NaN if

@@ -71,6 +71,13 @@ class tomo_solve_opts(ctypes.Structure):
 # name -> (restype, argtypes); every symbol declared in include/tomo.h
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
+class tomo_step(ctypes.Structure):
+    _fields_ = [("op", _P), ("kind", _I), ("batch", _I), ("values", _I), ("reserved", _I),
+                ("inp", _P), ("out", _P), ("aux", _P)]
+
+
+STEPS = {"spmm_pair": 0, "project": 1, "backproject": 2, "normal": 3}
+
 SIGNATURES = {
     "tomo_build_operator": (ctypes.c_int, [ctypes.POINTER(tomo_geometry), ctypes.c_int, ctypes.POINTER(_P)]),
     "tomo_project": (ctypes.c_int, [_P, _P, _P, _I, _I, _P]),
@@ -80,8 +87,13 @@ SIGNATURES = {
     "tomo_slice_adj": (ctypes.c_int, [_P, _P, _P, _I, _I, _I, _P]),
     "tomo_solve": (ctypes.c_int, [_P, _P, _P, _I, ctypes.POINTER(tomo_solve_opts), _P]),
     "tomo_normal": (ctypes.c_int, [_P, _P, _P, _I, _I, _I, _P]),
+    "tomo_autotune": (ctypes.c_int, [_P, _I, _I, _I, ctypes.POINTER(tomo_tuning),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "tomo_export_normal": (ctypes.c_int, [_P, _I, _P]),
     "tomo_tv": (ctypes.c_int, [_P, _P, _I, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "tomo_graph_create": (ctypes.c_int, [ctypes.POINTER(tomo_step), _I, ctypes.POINTER(_P)]),
+    "tomo_graph_launch": (ctypes.c_int, [_P, _P]),
+    "tomo_graph_destroy": (None, [_P]),
     "tomo_op_info_get": (ctypes.c_int, [_P, ctypes.POINTER(tomo_op_info)]),
     "tomo_export_csr": (ctypes.c_int, [_P, _I, _P, _P, _P]),
     "tomo_export_factors": (ctypes.c_int, [_P, _I, _P, _P]),
@@ -218,6 +230,18 @@ class Operator:
         self.info = self.op_info()
         return self.get_tuning()
 
+    def autotune(self, batch: int, values: str = "f32", rounds: int = 1) -> dict:
+        """``tomo_autotune``: search and apply the fastest SpMM tuning for ``batch`` slices;
+        returns the tuning with the measured ``fwd_ms`` / ``adj_ms``."""
+        t = tomo_tuning()
+        f, a = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.tomo_autotune(self._handle, batch, VALUES[values], rounds, ctypes.byref(t),
+                                  ctypes.byref(f), ctypes.byref(a)))
+        self.info = self.op_info()
+        out = {name: getattr(t, name) for name, _ in tomo_tuning._fields_}
+        out.update(fwd_ms=f.value, adj_ms=a.value)
+        return out
+
     def check_layouts(self) -> float:
         """``tomo_check_layouts``: host replay of every kernel layout against the CSR products."""
         err = ctypes.c_double()
@@ -341,6 +365,41 @@ class Operator:
         _check(_lib.tomo_tv(self._handle, _ptr(x), B, float(eps), float(weight), _ptr(g), _ptr(v),
                             _stream(self.device)))
         return v, g
+
+class Graph:
+    """``tomo_graph_create``: several operators' steps recorded as one HIP graph.
+
+    ``steps`` is a list of dicts with keys ``op`` (:class:`Operator`), ``kind`` (one of
+    ``STEPS``), ``batch``, ``values`` and the tensors ``inp``, ``out`` (and ``aux`` for
+    ``"spmm_pair"``).  The graph keeps references to the operators and tensors it records."""
+
+    def __init__(self, steps):
+        self._keep = list(steps)
+        arr = (tomo_step * len(steps))()
+        for k, st in enumerate(steps):
+            aux = st.get("aux")
+            arr[k] = tomo_step(st["op"]._handle, STEPS[st["kind"]], st["batch"],
+                               VALUES[st.get("values", "f32")], 0, _ptr(st["inp"]),
+                               _ptr(st["out"]), _ptr(aux))
+        h = ctypes.c_void_p()
+        _check(_lib.tomo_graph_create(arr, len(steps), ctypes.byref(h)))
+        self._handle = h
+        self.device = steps[0]["op"].device
+
+    def launch(self) -> None:
+        _check(_lib.tomo_graph_launch(self._handle, _stream(self.device)))
+
+    def close(self) -> None:
+        if self._handle is not None and _lib is not None:
+            _lib.tomo_graph_destroy(self._handle)
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 def build_operator(*args, **kwargs) -> Operator:
     """``tomo_build_operator``: see :class:`Operator`."""

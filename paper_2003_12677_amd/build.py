@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtomo.so")
-SOURCES = ["builder.cpp", "fft.cpp", "api.cpp", "spmm.hip", "tiles.hip", "layout.hip", "solver.hip", "tv.hip", "normal.hip"]
+SOURCES = ["builder.cpp", "fft.cpp", "api.cpp", "spmm.hip", "tiles.hip", "layout.hip", "solver.hip", "tv.hip", "normal.hip",
+           "autotune.cpp", "graph.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

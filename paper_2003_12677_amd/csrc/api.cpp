@@ -12,19 +12,6 @@ const char* last_error_cstr();
 
 namespace {
 
-struct DeviceGuard {
-  int prev = -1;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) err = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
 template <typename T>
 tomo_status upload(T** dst, const T* src, size_t count) {
   *dst = nullptr;
@@ -241,6 +228,8 @@ tomo_status upload_all(tomo_op* op) {
 
 bool misaligned(const void* p, size_t a) { return ((uintptr_t)p) % a != 0; }
 
+}  // namespace
+
 tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int32_t batch,
                         int32_t values) {
   if (!op) return fail(TOMO_EINVAL, "operator is NULL");
@@ -259,7 +248,6 @@ tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int3
   return TOMO_OK;
 }
 
-}  // namespace
 
 // project: embed + deapodise -> F2D -> S^dagger -> F1D^-1 -> crop (Eq. (2), first line)
 tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st) {
@@ -467,6 +455,25 @@ tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
   return run_solve(op, b, x, batch, opts, (hipStream_t)stream);
 }
 
+tomo_status tomo_autotune(tomo_op* op, int32_t batch, int32_t values, int32_t rounds,
+                          tomo_tuning* best, double* fwd_ms, double* adj_ms) {
+  clear_error();
+  if (!op) return fail(TOMO_EINVAL, "operator is NULL");
+  if (op->device < 0) return fail(TOMO_ESTATE, "operator was built without a device");
+  if (batch < 1 || batch > op->g.max_batch)
+    return fail(TOMO_EINVAL, "batch %d outside [1, max_batch=%d]", batch, op->g.max_batch);
+  if (values < 0 || values > 2 || !(op->values & (1u << values)))
+    return fail(TOMO_ESTATE, "value type %d was not built for this operator", values);
+  if (rounds < 1 || rounds > 8) return fail(TOMO_EINVAL, "rounds must be in [1, 8]");
+  {
+    DeviceGuard guard(op->device);
+    TOMO_HIP(hipDeviceSynchronize());
+    TOMO_TRY(autotune(op, batch, values, rounds, fwd_ms, adj_ms));
+  }
+  if (best) TOMO_TRY(tomo_get_tuning(op, best));
+  return TOMO_OK;
+}
+
 tomo_status tomo_normal(tomo_op* op, const float* x, float* out, int32_t batch, int32_t values,
                         int32_t filter, void* stream) {
   clear_error();
@@ -612,6 +619,13 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.sell_xcd_rows = in->adj_sell_xcd_rows;
   t.medium_xcd_rows = in->adj_medium_xcd_rows;
   t.fwd_rows_per_group = in->fwd_rows_per_group;
+  return apply_tuning(op, t);
+}
+
+}  // extern "C"
+
+namespace tomo {
+tomo_status apply_tuning(tomo_op* op, const Tuning& t) {
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
@@ -630,6 +644,9 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   TOMO_HIP(hipDeviceSynchronize());
   return TOMO_OK;
 }
+}  // namespace tomo
+
+extern "C" {
 
 void tomo_destroy_operator(tomo_op* op) {
   if (!op) return;

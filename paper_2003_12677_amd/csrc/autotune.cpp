@@ -1,0 +1,108 @@
+// Autotuner for the SpMM layout parameters (the tomo_tuning search space): times the forward and
+// adjoint SpMMs for one batch width and value type on the operator's own work buffers (filled
+// with hashed values), and walks the parameters one at a time (coordinate descent), keeping
+// whichever setting is fastest.  The adjoint's row-bin parameters change the host layout, so
+// each of their candidates costs a re-layout and upload; the search therefore visits a short
+// list per parameter.
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace tomo {
+namespace {
+
+struct Timer {
+  hipStream_t st = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+// average milliseconds of `reps` launches, best of three trials, after two warm-up launches
+template <typename F>
+tomo_status time_ms(Timer& tm, F launch, int reps, double* out) {
+  for (int w = 0; w < 2; ++w) TOMO_TRY(launch());
+  double best = 1e30;
+  for (int trial = 0; trial < 3; ++trial) {
+    TOMO_HIP(hipEventRecord(tm.a, tm.st));
+    for (int r = 0; r < reps; ++r) TOMO_TRY(launch());
+    TOMO_HIP(hipEventRecord(tm.b, tm.st));
+    TOMO_HIP(hipEventSynchronize(tm.b));
+    float ms = 0.f;
+    TOMO_HIP(hipEventElapsedTime(&ms, tm.a, tm.b));
+    best = std::min(best, (double)ms / reps);
+  }
+  *out = best;
+  return TOMO_OK;
+}
+
+}  // namespace
+
+tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms, double* adj_ms) {
+  const Geom& g = op->g;
+  const int C = (batch + 1) / 2;
+  Timer tm;
+  TOMO_HIP(hipStreamCreate(&tm.st));
+  TOMO_HIP(hipEventCreate(&tm.a));
+  TOMO_HIP(hipEventCreate(&tm.b));
+  TOMO_TRY(launch_fill_hash((float*)op->X, (int64_t)g.G * g.G * C * 2, 1u, tm.st));
+  TOMO_TRY(launch_fill_hash((float*)op->Y, (int64_t)g.L * g.nt * C * 2, 2u, tm.st));
+  const int reps = 10;
+  auto fwd = [&] { return launch_spmm_fwd(op, op->X, op->Y, C, vt, tm.st); };
+  auto adj = [&] { return launch_spmm_adj(op, op->Y, op->X, C, vt, nullptr, tm.st); };
+  // every candidate is timed from the same inputs: the forward reads X and writes Y, so time the
+  // adjoint (which reads Y) after refilling Y
+  auto measure_fwd = [&](double* ms) { return time_ms(tm, fwd, reps, ms); };
+  auto measure_adj = [&](double* ms) {
+    TOMO_TRY(launch_fill_hash((float*)op->Y, (int64_t)g.L * g.nt * C * 2, 2u, tm.st));
+    return time_ms(tm, adj, reps, ms);
+  };
+
+  Tuning best = op->tune;
+  double bf = 0, ba = 0;
+  TOMO_TRY(measure_fwd(&bf));
+  TOMO_TRY(measure_adj(&ba));
+  struct Param {
+    int Tuning::*field;
+    std::vector<int> values;
+    bool forward;
+  };
+  const std::vector<Param> params = {
+      {&Tuning::fwd_rows_per_group, {1, 2, 4}, true},
+      {&Tuning::fwd_cpl, {1, 2, 4}, true},
+      {&Tuning::adj_cpl, {1, 2, 4}, false},
+      {&Tuning::sell_max, {8, 16, 24, 32, 48, 64, 96}, false},
+      {&Tuning::medium_max, {64, 128, 256, 512}, false},
+      {&Tuning::sell_xcd_rows, {0, 1, 2048, 4096, 8192, 16384}, false},
+      {&Tuning::medium_xcd_rows, {1, 256, 1024, 4096}, false},
+  };
+  for (int round = 0; round < std::max(1, rounds); ++round) {
+    for (const Param& p : params) {
+      for (int v : p.values) {
+        Tuning t = best;
+        t.*(p.field) = v;
+        if (t.*(p.field) == best.*(p.field) || check_tuning(t) != TOMO_OK) continue;
+        TOMO_TRY(apply_tuning(op, t));
+        double ms = 0;
+        TOMO_TRY(p.forward ? measure_fwd(&ms) : measure_adj(&ms));
+        if (ms < (p.forward ? bf : ba)) {
+          best = t;
+          (p.forward ? bf : ba) = ms;
+        }
+      }
+      TOMO_TRY(apply_tuning(op, best));
+    }
+  }
+  clear_error();
+  TOMO_HIP(hipStreamSynchronize(tm.st));
+  if (fwd_ms) *fwd_ms = bf;
+  if (adj_ms) *adj_ms = ba;
+  return TOMO_OK;
+}
+
+}  // namespace tomo

@@ -239,6 +239,24 @@ struct tomo_op {
 
 namespace tomo {
 
+// Makes `dev` current for the scope and restores the previous device.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Argument checks shared by the apply entry points (operator, batch, pointers, value type).
+tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int32_t batch,
+                        int32_t values);
+
 constexpr int kDotBlocks = 256;   // blocks per slice in the FP64 reductions
 
 // FFT plans for C complex channels (created on first use).
@@ -304,5 +322,10 @@ tomo_status launch_lincomb(float* out, const float* a, const float* b, const dou
                            const double* cb, double sa, double sb, int64_t len, int B,
                            hipStream_t st);
 tomo_status launch_fill(float* out, float v, int64_t len, hipStream_t st);
+tomo_status launch_fill_hash(float* out, int64_t len, uint32_t seed, hipStream_t st);
+// Validate and apply a tuning (re-uploading the layouts it changes; synchronises the device).
+tomo_status apply_tuning(tomo_op* op, const Tuning& t);
+// Coordinate-descent search of the SpMM tuning for `batch` slices in value type vt.
+tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms, double* adj_ms);
 
 }  // namespace tomo

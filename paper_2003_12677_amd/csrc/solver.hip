@@ -133,6 +133,22 @@ tomo_status launch_lincomb(float* out, const float* a, const float* b, const dou
   return TOMO_OK;
 }
 
+// out[i] = a value in [-1, 1) from a 32-bit integer hash of (i, seed): timing inputs
+__global__ __launch_bounds__(256) void k_fill_hash(float* __restrict__ out, int64_t len,
+                                                   uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    uint32_t h = (uint32_t)i * 0x9E3779B9u ^ (uint32_t)(i >> 32) ^ seed;
+    h ^= h >> 16; h *= 0x7FEB352Du; h ^= h >> 15; h *= 0x846CA68Bu; h ^= h >> 16;
+    out[i] = (float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f;
+  }
+}
+
+tomo_status launch_fill_hash(float* out, int64_t len, uint32_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_hash, dim3(grid_for(len)), dim3(256), 0, st, out, len, seed);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
 tomo_status launch_fill(float* out, float v, int64_t len, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(grid_for(len)), dim3(256), 0, st, out, v, len);
   TOMO_HIP(hipGetLastError());
