@@ -176,6 +176,7 @@ void free_device(tomo_op* op) {
   for (auto& v : op->fwd.val) dfree(v);
   free_adj(op);
   dfree(op->kd_dev);
+  dfree(op->tw1);
   for (auto& f : op->filt_dev) dfree(f);
   dfree(op->X);
   dfree(op->Y);
@@ -203,6 +204,15 @@ tomo_status upload_all(tomo_op* op) {
     filter_diagonal(g, f, &d);
     std::vector<float> df(d.begin(), d.end());
     TOMO_TRY(upload(&op->filt_dev[f], df.data(), df.size()));
+  }
+  if (g.L >= 16 && g.L <= 4096 && (g.L & (g.L - 1)) == 0) {
+    // twiddles exp(-2 pi i j / L) of the fused detector transforms, from double
+    std::vector<float2> tw(g.L);
+    for (int j = 0; j < g.L; ++j) {
+      const double ang = -2.0 * M_PI * (double)j / (double)g.L;
+      tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    TOMO_TRY(upload(&op->tw1, tw.data(), tw.size()));
   }
   const size_t xb = (size_t)g.G * g.G * op->cmax * sizeof(float2);
   const size_t yb = (size_t)g.L * g.nt * op->cmax * sizeof(float2);
@@ -260,6 +270,8 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
   TOMO_TRY(launch_to_channel_fastest(op->Xs, op->X, (int64_t)g.G * g.G, C, st));
   TOMO_TRY(launch_spmm_fwd(op, op->X, op->Y, C, vt, st));
   TOMO_TRY(launch_polar_to_slowest(op->Y, op->Ys, g.L, g.nt, C, st));
+  if (op->tune.det_fft && det_fft_supported(op))
+    return launch_det_inverse_crop(op, op->Ys, y, B, 1.0f / (float)g.L, st);
   TOMO_TRY(fft_exec(p->inv1, p, op->Ys, st));
   TOMO_TRY(launch_crop_sino(op, op->Ys, y, B, 1.0f / (float)g.L, st));
   return TOMO_OK;
@@ -272,8 +284,12 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
-  TOMO_TRY(launch_pad_sino(op, y, op->Ys, B, st));
-  TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
+  if (op->tune.det_fft && det_fft_supported(op)) {
+    TOMO_TRY(launch_det_pad_forward(op, y, op->Ys, B, st));
+  } else {
+    TOMO_TRY(launch_pad_sino(op, y, op->Ys, B, st));
+    TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
+  }
   TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
   const float* ds = (filter == TOMO_FILTER_NONE) ? nullptr : op->filt_dev[filter];
   TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
@@ -597,6 +613,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->adj_sell_xcd_rows = op->tune.sell_xcd_rows;
   out->adj_medium_xcd_rows = op->tune.medium_xcd_rows;
   out->fwd_rows_per_group = op->tune.fwd_rows_per_group;
+  out->det_fft = op->tune.det_fft;
   return TOMO_OK;
 }
 
@@ -619,6 +636,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.sell_xcd_rows = in->adj_sell_xcd_rows;
   t.medium_xcd_rows = in->adj_medium_xcd_rows;
   t.fwd_rows_per_group = in->fwd_rows_per_group;
+  t.det_fft = in->det_fft;
   return apply_tuning(op, t);
 }
 

@@ -71,6 +71,7 @@ struct Tuning {
   int sell_xcd_rows = 8192;   // sliced-ELL adjoint: rows per XCD interleave run (0 = contiguous)
   int medium_xcd_rows = 1024; // wave-per-row adjoint: rows per XCD interleave run
   int fwd_rows_per_group = 2; // forward: rows per lane group in the pipelined kernel (1, 2, 4)
+  int det_fft = 1;            // detector transforms: fused hand-written (1, L = 2^m) or library (0)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
@@ -217,6 +218,7 @@ struct tomo_op {
   tomo::DevEll fwd;
   tomo::DevAdj adj;
   float* kd_dev = nullptr;        // [n]
+  float2* tw1 = nullptr;          // [L] exp(-2 pi i j / L) when L is a power of two (fused 1D DFTs)
   float* filt_dev[4] = {nullptr, nullptr, nullptr, nullptr};   // D per tomo_filter, [L]
   int cmax = 0;                   // complex channels the workspace holds
   float2* X = nullptr;            // [G*G][C]     channel-fastest Cartesian grid (SpMM side)
@@ -309,6 +311,12 @@ void free_tv(tomo_op* op);
 
 // Normal operator on the channel-slowest Cartesian grid: Out[c][j] = sum over the stencil of
 // W[j][o] In[c][j + offset(o)] (offsets wrap mod G), W for `filter` in value type vt.
+// Detector transforms fused with the layout steps (L a power of two in [16, 4096]).
+bool det_fft_supported(const tomo_op* op);
+tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Y, float* y, int B,
+                                    float scale, hipStream_t st);
+tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
+                                   hipStream_t st);
 tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
                          hipStream_t st);
 tomo_status normal_supported(const tomo_op* op);

@@ -114,6 +114,41 @@ def test_project_backproject_irradon(tomo, shape, batch):
     op.close()
 
 
+POW2_SHAPES = [
+    (16, 12, 16, {}),
+    (32, 24, 64, {}),
+    (24, 20, 32, {"center": 10.0}),
+    (12, 10, 16, {"grid": 32}),            # zero-padded detector: crop / pad of L to n_p
+    (40, 30, 64, {"kw": 5}),
+    (100, 60, 256, {}),
+    (64, 6, 4096, {}),                     # two channels per block
+]
+
+
+@pytest.mark.parametrize("shape", POW2_SHAPES, ids=_ids)
+@pytest.mark.parametrize("det_fft", [1, 0])
+@pytest.mark.parametrize("batch", [1, 5])
+def test_detector_transform_paths(tomo, shape, det_fft, batch):
+    """The fused detector transform (gather + radix-4 DFT in LDS + crop / pad) and the rocFFT
+    path both give the oracle's operators for power-of-two L."""
+    n, nt, npb, extra = shape
+    op = _gpu_op(tomo, n, nt, npb, extra)
+    op.set_tuning(det_fft=det_fft)
+    ref = _oracle(n, nt, npb, extra)
+    x = _rand((batch, n, n), 700 + batch)
+    y = _rand((batch, nt, npb), 800 + batch)
+    yg = _host(op.project(_dev(x)))
+    xg = _host(op.backproject(_dev(y)))
+    xf = _host(op.irradon(_dev(y), filter="ramlak"))
+    for s in range(batch):
+        xs = x[s].astype(np.float32).astype(np.float64)
+        ys = y[s].astype(np.float32).astype(np.float64)
+        assert rel_l2(yg[s], ref.project(xs)) < TOL, s
+        assert rel_l2(xg[s], ref.backproject(ys)) < TOL, s
+        assert rel_l2(xf[s], ref.irradon(ys, "ramlak")) < TOL, s
+    op.close()
+
+
 def test_phantom_stack_configuration_1_shape(tomo):
     """Random-ellipse phantoms at 64^2, 90 angles, 91 bins, through the paired path."""
     x = phantom_stack(64, 5, seed_base=1000)
