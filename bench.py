@@ -139,6 +139,36 @@ def _oracle_slices(budget_s: float, max_slices: int, seed: int):
 
 _ORACLE = {}
 
+def cpu_baseline(budget_s: float):
+    """The FP64 oracle's forward and adjoint sparse products (S^dagger U, S V') per slice on the
+    host: one process, then one process per usable host core, each on its own slices (the
+    slice decomposition of Sec. 3.1).  Runs before anything touches the GPU, so the forked
+    workers hold no GPU state."""
+    import multiprocessing as mp
+
+    from oracle import Geometry, Operator
+
+    t0 = time.perf_counter()
+    _ORACLE["op"] = Operator(Geometry(N_IMG, N_ANG, N_DET))
+    build_s = time.perf_counter() - t0
+    one, el1 = _oracle_slices(budget_s, 64, 0)
+    cores = min(16, len(os.sched_getaffinity(0)))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        parts = pool.starmap(_oracle_slices, [(budget_s, 64, 1 + i) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    done = sum(p[0] for p in parts)
+    rate = sum(p[0] / p[1] for p in parts)      # concurrent processes, each over its own loop
+    _ORACLE.clear()
+    return {"value": rate, "unit": "slices/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} slices of S^dagger U + S V' (scipy CSR, complex128 vectors) in "
+                      f"{cores} concurrent processes, about {budget_s:.0f} s each ({wall:.1f} s "
+                      f"wall); operator build {build_s:.1f} s not timed",
+            "single_process": {"value": one / el1, "cores": 1,
+                               "sample": f"{one} slices in {el1:.1f} s"}}
+
+
 ACC_SLICES, ACC_ITERS = 4, 100
 
 

@@ -118,7 +118,7 @@ typedef struct {
 
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB, else the row kernels.
- * Defaults (in field order): 2, 2, 48, 4096, 128, 1024, 0, 0, 8, 128, 1, 1, 8192, 1024, 2, 1. */
+ * Defaults (in field order): 2, 2, 48, 4096, 128, 1024, 0, 0, 8, 128, 1, 1, 8192, 1024, 2, 1, 1. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -149,6 +149,9 @@ typedef struct {
   int32_t det_fft;                /* detector-direction DFTs of project / backproject: 1 = one
                                      fused kernel (layout + radix-4 DFT in LDS + crop / pad)
                                      when L is a power of two in [16, 4096]; 0 = rocFFT        */
+  int32_t grid_fft;               /* Cartesian 2D DFTs: 1 = hand-written row and column kernels
+                                     fused with the embed / crop steps when the grid side is a
+                                     power of two in [16, 4096]; 0 = rocFFT                    */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */

@@ -177,6 +177,7 @@ void free_device(tomo_op* op) {
   free_adj(op);
   dfree(op->kd_dev);
   dfree(op->tw1);
+  dfree(op->tw2);
   for (auto& f : op->filt_dev) dfree(f);
   dfree(op->X);
   dfree(op->Y);
@@ -205,15 +206,19 @@ tomo_status upload_all(tomo_op* op) {
     std::vector<float> df(d.begin(), d.end());
     TOMO_TRY(upload(&op->filt_dev[f], df.data(), df.size()));
   }
-  if (g.L >= 16 && g.L <= 4096 && (g.L & (g.L - 1)) == 0) {
-    // twiddles exp(-2 pi i j / L) of the fused detector transforms, from double
-    std::vector<float2> tw(g.L);
-    for (int j = 0; j < g.L; ++j) {
-      const double ang = -2.0 * M_PI * (double)j / (double)g.L;
+  // twiddles exp(-2 pi i j / m) of the hand-written transforms (m = L detector, m = G grid),
+  // from double, for power-of-two sizes
+  auto twiddles = [](int m, float2** dst) -> tomo_status {
+    if (m < 16 || m > 4096 || (m & (m - 1)) != 0) return TOMO_OK;
+    std::vector<float2> tw(m);
+    for (int j = 0; j < m; ++j) {
+      const double ang = -2.0 * M_PI * (double)j / (double)m;
       tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
     }
-    TOMO_TRY(upload(&op->tw1, tw.data(), tw.size()));
-  }
+    return upload(dst, tw.data(), tw.size());
+  };
+  TOMO_TRY(twiddles(g.L, &op->tw1));
+  TOMO_TRY(twiddles(g.G, &op->tw2));
   const size_t xb = (size_t)g.G * g.G * op->cmax * sizeof(float2);
   const size_t yb = (size_t)g.L * g.nt * op->cmax * sizeof(float2);
   if (hipMalloc((void**)&op->X, xb) != hipSuccess) {
@@ -265,8 +270,12 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
-  TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
-  TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  if (op->tune.grid_fft && grid_fft_supported(op)) {
+    TOMO_TRY(launch_grid_forward(op, x, op->Xs, B, st));
+  } else {
+    TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
+    TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  }
   TOMO_TRY(launch_to_channel_fastest(op->Xs, op->X, (int64_t)g.G * g.G, C, st));
   TOMO_TRY(launch_spmm_fwd(op, op->X, op->Y, C, vt, st));
   TOMO_TRY(launch_polar_to_slowest(op->Y, op->Ys, g.L, g.nt, C, st));
@@ -294,6 +303,8 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
   const float* ds = (filter == TOMO_FILTER_NONE) ? nullptr : op->filt_dev[filter];
   TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
   TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
+  if (op->tune.grid_fft && grid_fft_supported(op))
+    return launch_grid_inverse(op, op->Xs, x, B, extra_scale / (float)g.L, st);
   TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
   TOMO_TRY(launch_crop_image(op, op->Xs, x, B, extra_scale / (float)g.L, st));
   return TOMO_OK;
@@ -342,9 +353,15 @@ tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt,
   TOMO_TRY(ensure_normal(op, filter));
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
-  TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
-  TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  const bool hand = op->tune.grid_fft && grid_fft_supported(op);
+  if (hand) {
+    TOMO_TRY(launch_grid_forward(op, x, op->Xs, B, st));
+  } else {
+    TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
+    TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  }
   TOMO_TRY(launch_normal_stencil(op, op->Xs, op->X, C, vt, filter, st));
+  if (hand) return launch_grid_inverse(op, op->X, out, B, 1.0f / (float)g.L, st);
   TOMO_TRY(fft_exec(p->inv2, p, op->X, st));
   TOMO_TRY(launch_crop_image(op, op->X, out, B, 1.0f / (float)g.L, st));
   return TOMO_OK;
@@ -614,6 +631,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->adj_medium_xcd_rows = op->tune.medium_xcd_rows;
   out->fwd_rows_per_group = op->tune.fwd_rows_per_group;
   out->det_fft = op->tune.det_fft;
+  out->grid_fft = op->tune.grid_fft;
   return TOMO_OK;
 }
 
@@ -637,6 +655,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.medium_xcd_rows = in->adj_medium_xcd_rows;
   t.fwd_rows_per_group = in->fwd_rows_per_group;
   t.det_fft = in->det_fft;
+  t.grid_fft = in->grid_fft;
   return apply_tuning(op, t);
 }
 

@@ -240,6 +240,7 @@ tomo_status check_tuning(const Tuning& t) {
       t.medium_xcd_rows > (1 << 24))
     return fail(TOMO_EINVAL, "XCD interleave rows must be in [0, 2^24]");
   if (t.det_fft != 0 && t.det_fft != 1) return fail(TOMO_EINVAL, "det_fft must be 0 or 1");
+  if (t.grid_fft != 0 && t.grid_fft != 1) return fail(TOMO_EINVAL, "grid_fft must be 0 or 1");
   if (t.fwd_rows_per_group != 1 && t.fwd_rows_per_group != 2 && t.fwd_rows_per_group != 4)
     return fail(TOMO_EINVAL, "fwd_rows_per_group must be 1, 2 or 4");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))

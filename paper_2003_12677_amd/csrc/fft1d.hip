@@ -20,123 +20,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include "fft_lds.h"
 #include "internal.h"
 
 namespace tomo {
 namespace {
 
-constexpr int kFB = 512;
-
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// X_q = sum_r v_r exp(-/+ 2 pi i r q / R)
-template <bool INV>
-__device__ __forceinline__ void dft4(float2 (&v)[4]) {
-  const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
-  const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
-  const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
-  const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
-  // -i * d13 (forward) or +i * d13 (inverse)
-  const float2 rot = INV ? make_float2(-d13.y, d13.x) : make_float2(d13.y, -d13.x);
-  v[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
-  v[2] = make_float2(s02.x - s13.x, s02.y - s13.y);
-  v[1] = make_float2(d02.x + rot.x, d02.y + rot.y);
-  v[3] = make_float2(d02.x - rot.x, d02.y - rot.y);
-}
-
-// radix 8 from two radix-4 transforms of the even and odd inputs and the eighth roots of unity
-template <bool INV>
-__device__ __forceinline__ void dft8(float2 (&v)[8]) {
-  float2 e[4] = {v[0], v[2], v[4], v[6]};
-  float2 o[4] = {v[1], v[3], v[5], v[7]};
-  dft4<INV>(e);
-  dft4<INV>(o);
-  constexpr float h = 0.70710678118654752f;
-  // t_q = w8^q o_q, w8 = exp(-/+ 2 pi i / 8)
-  const float2 t0 = o[0];
-  const float2 t1 = INV ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
-                        : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
-  const float2 t2 = INV ? make_float2(-o[2].y, o[2].x) : make_float2(o[2].y, -o[2].x);
-  const float2 t3 = INV ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
-                        : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
-  const float2 t[4] = {t0, t1, t2, t3};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    v[q] = make_float2(e[q].x + t[q].x, e[q].y + t[q].y);
-    v[q + 4] = make_float2(e[q].x - t[q].x, e[q].y - t[q].y);
-  }
-}
-
-template <bool INV>
-__device__ __forceinline__ void dft2(float2 (&v)[2]) {
-  const float2 a = v[0], b = v[1];
-  v[0] = make_float2(a.x + b.x, a.y + b.y);
-  v[1] = make_float2(a.x - b.x, a.y - b.y);
-}
-
-// One Stockham pass of radix R on CH transforms of length L stored back to back in `buf`,
-// after which sub-transforms of length Ns*R are complete (Ns = 1 << logNs).
-template <int L, int CH, int R, bool INV>
-__device__ __forceinline__ void stockham_pass(float2* buf, int logNs, const float2* __restrict__ tw) {
-  constexpr int NJ = L / R;
-  constexpr int TOTAL = CH * NJ;
-  constexpr int IT = (TOTAL + kFB - 1) / kFB;
-  const int Ns = 1 << logNs;
-  const int tstep = L / (R * Ns);
-  float2 v[IT][R];
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int w = threadIdx.x + it * kFB;
-    if (w < TOTAL) {
-      const int ch = w / NJ, j = w % NJ;
-      const int k = j & (Ns - 1);
-      const float2* src = buf + ch * L + j;
-      // w = exp(-/+ 2 pi i k / (R Ns)) from the table, its powers by multiplication
-      float2 w = tw[k * tstep];
-      if (INV) w.y = -w.y;
-      float2 wr = w;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        float2 a = src[r * NJ];
-        if (r > 0) {
-          a = cmul(a, wr);
-          wr = cmul(wr, w);
-        }
-        v[it][r] = a;
-      }
-      if constexpr (R == 8) dft8<INV>(v[it]);
-      else if constexpr (R == 4) dft4<INV>(v[it]);
-      else dft2<INV>(v[it]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int w = threadIdx.x + it * kFB;
-    if (w < TOTAL) {
-      const int ch = w / NJ, j = w % NJ;
-      const int idx = ((j >> logNs) << logNs) * R + (j & (Ns - 1));
-      float2* dst = buf + ch * L + idx;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[it][r];
-    }
-  }
-  __syncthreads();
-}
-
-// radix-8 passes, then one radix-4 or radix-2 pass for the remaining factor
-template <int L, int CH, bool INV>
-__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw) {
-  int logNs = 0;
-  while ((8 << logNs) <= L) {
-    stockham_pass<L, CH, 8, INV>(buf, logNs, tw);
-    logNs += 3;
-  }
-  if ((4 << logNs) <= L) stockham_pass<L, CH, 4, INV>(buf, logNs, tw);
-  else if ((2 << logNs) <= L) stockham_pass<L, CH, 2, INV>(buf, logNs, tw);
-}
+using namespace fftk;
 
 // Ys[C][nt][L] (channel-slowest rows after the polar transpose) -> inverse DFT of each row ->
 // axis shift, scale, crop, slices 2c / 2c+1.  One block per (channel, AG consecutive angles):
@@ -146,20 +36,20 @@ __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restri
                                                           float* __restrict__ y,
                                                           const float2* __restrict__ tw, int B,
                                                           int nt, int np, int cdet, float scale) {
-  __shared__ float2 buf[AG * L];
+  __shared__ float2 buf[lds_size<AG * L>()];
   const int agroups = (nt + AG - 1) / AG;
   const int c = blockIdx.x / agroups, a0 = (blockIdx.x % agroups) * AG;
   const int na = min(AG, nt - a0);
   const float2* src = Ys + ((int64_t)c * nt + a0) * L;
   for (int i = threadIdx.x; i < AG * L; i += kFB)
-    buf[i] = (i < na * L) ? src[i] : make_float2(0.f, 0.f);
+    buf[lds(i)] = (i < na * L) ? src[i] : make_float2(0.f, 0.f);
   __syncthreads();
   fft_lds<L, AG, true>(buf, tw);
   const int64_t plane = (int64_t)nt * np;
   const bool odd = 2 * c + 1 < B;
   for (int i = threadIdx.x; i < na * np; i += kFB) {
     const int q = i / np, b = i % np;
-    const float2 v = buf[q * L + ((b - cdet) & (L - 1))];
+    const float2 v = buf[lds(q * L + ((b - cdet) & (L - 1)))];
     const int64_t off = (int64_t)(a0 + q) * np + b;
     y[(int64_t)(2 * c) * plane + off] = v.x * scale;
     if (odd) y[(int64_t)(2 * c + 1) * plane + off] = v.y * scale;
@@ -173,7 +63,7 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
                                                          float2* __restrict__ Ys,
                                                          const float2* __restrict__ tw, int B,
                                                          int nt, int np, int cdet) {
-  __shared__ float2 buf[AG * L];
+  __shared__ float2 buf[lds_size<AG * L>()];
   const int agroups = (nt + AG - 1) / AG;
   const int c = blockIdx.x / agroups, a0 = (blockIdx.x % agroups) * AG;
   const int na = min(AG, nt - a0);
@@ -188,18 +78,19 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
       v.x = y[(int64_t)(2 * c) * plane + off];
       if (odd) v.y = y[(int64_t)(2 * c + 1) * plane + off];
     }
-    buf[i] = v;
+    buf[lds(i)] = v;
   }
   __syncthreads();
   fft_lds<L, AG, false>(buf, tw);
   float2* dst = Ys + ((int64_t)c * nt + a0) * L;
-  for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[i];
+  for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[lds(i)];
 }
 
 template <int L>
 tomo_status det_launch(bool inverse, const tomo_op* op, const float2* Ysin, float2* Ysout,
                        const float* yin, float* yout, int B, float scale, hipStream_t st) {
-  constexpr int AG = L >= 4096 ? 2 : (L >= 2048 ? 4 : 8192 / L > 16 ? 16 : 8192 / L);
+  // about 32 KB of LDS per block, so that four blocks share a CU
+  constexpr int AG = L >= 2048 ? 2 : (4096 / L > 16 ? 16 : 4096 / L);
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   const dim3 grid((unsigned)(C * ((g.nt + AG - 1) / AG)));

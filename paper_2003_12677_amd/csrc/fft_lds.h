@@ -1,0 +1,133 @@
+// Radix-8/4/2 Stockham DFTs of several length-L vectors held in LDS, for power-of-two L: the
+// shared core of the hand-written transforms (detector rows and Cartesian rows / columns).
+// Every pass reads each butterfly's inputs into registers, synchronises the block, then writes
+// its outputs back, so the transform is in place in one buffer.  Forward: exp(-2 pi i jk / L);
+// inverse: exp(+2 pi i jk / L), unnormalised.  Twiddle table tw[j] = exp(-2 pi i j / L).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tomo {
+namespace fftk {
+
+constexpr int kFB = 512;   // threads per block of every kernel that uses these passes
+
+// LDS index of element i: one padding element after every 32 (256 bytes, one row of banks), so
+// the stride-R writes of the early passes spread over the banks instead of colliding.
+__device__ __forceinline__ int lds(int i) { return i + (i >> 5); }
+template <int N>
+constexpr int lds_size() { return N + N / 32 + 1; }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// X_q = sum_r v_r exp(-/+ 2 pi i r q / R)
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 (&v)[4]) {
+  const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+  const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+  const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+  const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+  // -i * d13 (forward) or +i * d13 (inverse)
+  const float2 rot = INV ? make_float2(-d13.y, d13.x) : make_float2(d13.y, -d13.x);
+  v[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
+  v[2] = make_float2(s02.x - s13.x, s02.y - s13.y);
+  v[1] = make_float2(d02.x + rot.x, d02.y + rot.y);
+  v[3] = make_float2(d02.x - rot.x, d02.y - rot.y);
+}
+
+// radix 8 from two radix-4 transforms of the even and odd inputs and the eighth roots of unity
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  constexpr float h = 0.70710678118654752f;
+  // t_q = w8^q o_q, w8 = exp(-/+ 2 pi i / 8)
+  const float2 t0 = o[0];
+  const float2 t1 = INV ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                        : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+  const float2 t2 = INV ? make_float2(-o[2].y, o[2].x) : make_float2(o[2].y, -o[2].x);
+  const float2 t3 = INV ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                        : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+  const float2 t[4] = {t0, t1, t2, t3};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = make_float2(e[q].x + t[q].x, e[q].y + t[q].y);
+    v[q + 4] = make_float2(e[q].x - t[q].x, e[q].y - t[q].y);
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2 (&v)[2]) {
+  const float2 a = v[0], b = v[1];
+  v[0] = make_float2(a.x + b.x, a.y + b.y);
+  v[1] = make_float2(a.x - b.x, a.y - b.y);
+}
+
+// One Stockham pass of radix R on CH transforms of length L stored back to back in `buf`,
+// after which sub-transforms of length Ns*R are complete (Ns = 1 << logNs).
+template <int L, int CH, int R, bool INV>
+__device__ __forceinline__ void stockham_pass(float2* buf, int logNs, const float2* __restrict__ tw) {
+  constexpr int NJ = L / R;
+  constexpr int TOTAL = CH * NJ;
+  constexpr int IT = (TOTAL + kFB - 1) / kFB;
+  const int Ns = 1 << logNs;
+  const int tstep = L / (R * Ns);
+  float2 v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = threadIdx.x + it * kFB;
+    if (w < TOTAL) {
+      const int ch = w / NJ, j = w % NJ;
+      const int k = j & (Ns - 1);
+      const int src = ch * L + j;
+      // w = exp(-/+ 2 pi i k / (R Ns)) from the table, its powers by multiplication
+      float2 w = tw[k * tstep];
+      if (INV) w.y = -w.y;
+      float2 wr = w;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 a = buf[lds(src + r * NJ)];
+        if (r > 0) {
+          a = cmul(a, wr);
+          wr = cmul(wr, w);
+        }
+        v[it][r] = a;
+      }
+      if constexpr (R == 8) dft8<INV>(v[it]);
+      else if constexpr (R == 4) dft4<INV>(v[it]);
+      else dft2<INV>(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = threadIdx.x + it * kFB;
+    if (w < TOTAL) {
+      const int ch = w / NJ, j = w % NJ;
+      const int idx = ((j >> logNs) << logNs) * R + (j & (Ns - 1));
+      const int dst = ch * L + idx;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds(dst + r * Ns)] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+// radix-8 passes, then one radix-4 or radix-2 pass for the remaining factor
+template <int L, int CH, bool INV>
+__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw) {
+  int logNs = 0;
+  while ((8 << logNs) <= L) {
+    stockham_pass<L, CH, 8, INV>(buf, logNs, tw);
+    logNs += 3;
+  }
+  if ((4 << logNs) <= L) stockham_pass<L, CH, 4, INV>(buf, logNs, tw);
+  else if ((2 << logNs) <= L) stockham_pass<L, CH, 2, INV>(buf, logNs, tw);
+}
+
+}  // namespace fftk
+}  // namespace tomo

@@ -72,6 +72,7 @@ struct Tuning {
   int medium_xcd_rows = 1024; // wave-per-row adjoint: rows per XCD interleave run
   int fwd_rows_per_group = 2; // forward: rows per lane group in the pipelined kernel (1, 2, 4)
   int det_fft = 1;            // detector transforms: fused hand-written (1, L = 2^m) or library (0)
+  int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1, G = 2^m) or library (0)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
@@ -219,6 +220,7 @@ struct tomo_op {
   tomo::DevAdj adj;
   float* kd_dev = nullptr;        // [n]
   float2* tw1 = nullptr;          // [L] exp(-2 pi i j / L) when L is a power of two (fused 1D DFTs)
+  float2* tw2 = nullptr;          // [G] exp(-2 pi i j / G) when G is a power of two (fused 2D DFTs)
   float* filt_dev[4] = {nullptr, nullptr, nullptr, nullptr};   // D per tomo_filter, [L]
   int cmax = 0;                   // complex channels the workspace holds
   float2* X = nullptr;            // [G*G][C]     channel-fastest Cartesian grid (SpMM side)
@@ -317,6 +319,13 @@ tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Y, float* y
                                     float scale, hipStream_t st);
 tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
                                    hipStream_t st);
+// Cartesian 2D DFT fused with embed (forward) and crop (inverse), G a power of two in [16, 4096]:
+// forward x -> Xs (channel-slowest), inverse Xs (overwritten) -> x.
+bool grid_fft_supported(const tomo_op* op);
+tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
+                                hipStream_t st);
+tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
+                                hipStream_t st);
 tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
                          hipStream_t st);
 tomo_status normal_supported(const tomo_op* op);

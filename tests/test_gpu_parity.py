@@ -126,14 +126,15 @@ POW2_SHAPES = [
 
 
 @pytest.mark.parametrize("shape", POW2_SHAPES, ids=_ids)
-@pytest.mark.parametrize("det_fft", [1, 0])
+@pytest.mark.parametrize("fft", [(1, 1), (0, 0), (1, 0), (0, 1)], ids=lambda f: f"det{f[0]}_grid{f[1]}")
 @pytest.mark.parametrize("batch", [1, 5])
-def test_detector_transform_paths(tomo, shape, det_fft, batch):
-    """The fused detector transform (gather + radix-4 DFT in LDS + crop / pad) and the rocFFT
-    path both give the oracle's operators for power-of-two L."""
+def test_hand_written_transform_paths(tomo, shape, fft, batch):
+    """The hand-written transforms (detector rows with crop / pad; Cartesian rows with embed /
+    crop and columns) and the rocFFT paths all give the oracle's operators for power-of-two
+    sizes."""
     n, nt, npb, extra = shape
     op = _gpu_op(tomo, n, nt, npb, extra)
-    op.set_tuning(det_fft=det_fft)
+    op.set_tuning(det_fft=fft[0], grid_fft=fft[1])
     ref = _oracle(n, nt, npb, extra)
     x = _rand((batch, n, n), 700 + batch)
     y = _rand((batch, nt, npb), 800 + batch)
