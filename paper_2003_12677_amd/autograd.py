@@ -17,6 +17,7 @@ element-wise residual and the optimiser.
 from __future__ import annotations
 
 import os
+import threading
 
 import torch
 
@@ -92,8 +93,9 @@ def reconstruct_tv(op: Operator, b: torch.Tensor, *, mu: float = 1e-3, eps: floa
 
     Returns ``(x, history)`` where history[k] is the per-slice loss (float64 [B], on the host)
     before step k.  With ``checkpoint_dir`` the state after every ``checkpoint_every`` steps is
-    written atomically, and with ``resume`` a run restarts from the newest checkpoint there
-    (same inputs and settings continue the run bit for bit)."""
+    copied to host memory and written by a background thread (atomically, through a rename;
+    the run returns only after the last write), and with ``resume`` a run restarts from the
+    newest checkpoint there (same inputs and settings continue the run bit for bit)."""
     B = b.shape[0]
     x = (torch.zeros((B, op.n, op.n), dtype=torch.float32, device=b.device) if x0 is None
          else x0.detach().clone()).requires_grad_(True)
@@ -110,15 +112,39 @@ def reconstruct_tv(op: Operator, b: torch.Tensor, *, mu: float = 1e-3, eps: floa
             opt.load_state_dict(state["adam"])          # moves the moments to x's device
             history = list(state["history"])
             start = int(state["step"])
-    for k in range(start, steps):
-        opt.zero_grad(set_to_none=False)
-        loss = model_loss(x, b, op, mu, eps, values)
-        loss.sum().backward()
-        history.append(loss.detach().cpu())
-        opt.step()
-        if checkpoint_dir is not None and ((k + 1) % checkpoint_every == 0 or k + 1 == steps):
-            tmp = _checkpoint_path(checkpoint_dir) + ".tmp"
-            torch.save({"step": k + 1, "x": x.detach(), "adam": opt.state_dict(),
-                        "history": history}, tmp)
-            os.replace(tmp, _checkpoint_path(checkpoint_dir))
+    writer = None
+
+    def write(state, path):
+        tmp = path + ".tmp"
+        torch.save(state, tmp)
+        os.replace(tmp, path)
+
+    def host_copy(obj):
+        if isinstance(obj, torch.Tensor):
+            return obj.detach().to("cpu", copy=True)
+        if isinstance(obj, dict):
+            return {k: host_copy(v) for k, v in obj.items()}
+        if isinstance(obj, list):
+            return [host_copy(v) for v in obj]
+        return obj
+
+    try:
+        for k in range(start, steps):
+            opt.zero_grad(set_to_none=False)
+            loss = model_loss(x, b, op, mu, eps, values)
+            loss.sum().backward()
+            history.append(loss.detach().cpu())
+            opt.step()
+            if checkpoint_dir is not None and ((k + 1) % checkpoint_every == 0 or k + 1 == steps):
+                # snapshot to host memory now, write to disk while the device keeps going (at most
+                # one write in flight; each write is atomic through a rename)
+                state = host_copy({"step": k + 1, "x": x, "adam": opt.state_dict(),
+                                   "history": history})
+                if writer is not None:
+                    writer.join()
+                writer = threading.Thread(target=write, args=(state, _checkpoint_path(checkpoint_dir)))
+                writer.start()
+    finally:
+        if writer is not None:
+            writer.join()
     return x.detach(), history

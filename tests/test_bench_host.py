@@ -12,7 +12,7 @@ def test_default_run_entry_points_exist(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
     assert a.gpus == 1 and a.steps > 0 and a.warmup >= 0
-    for name in ("cpu_baseline", "accuracy_reference", "accuracy_leg", "uneven_leg",
+    for name in ("cpu_baseline", "accuracy_reference", "accuracy_leg", "uneven_leg", "tv_leg",
                  "measured_traffic", "step_percentiles", "time_loop", "main"):
         assert callable(getattr(bench, name)), name
 
