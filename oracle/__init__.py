@@ -30,4 +30,5 @@ from .fubini_radon import (  # noqa: F401
 from .lowprec import round_to_bf16, round_to_f16, round_values  # noqa: F401
 from .solvers import cgls, refine, sirt_bb  # noqa: F401
 from .normal import cg_normal, interpolation_product, normal, normal_factored  # noqa: F401
-from .tv import differences, differences_adjoint, objective, objective_grad, tv_grad, tv_value  # noqa: F401,E501
+from .tv import (chambolle_rof, differences, differences_adjoint, objective,  # noqa: F401
+                 objective_grad, shrink, split_bregman, tv_grad, tv_value)

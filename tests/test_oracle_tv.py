@@ -114,3 +114,56 @@ def test_pins_reject_planted_mistakes():
     assert np.abs(wrong - fd).max() > 1e-2
     w = rng.standard_normal((12, 12))
     assert abs(_tv_value_one_axis_twice(w, EPS) - _tv_value_one_axis_twice(w.T, EPS)) > 1e-3
+
+
+# ---- split-Bregman TV (Sec. 3.1) -------------------------------------------------------------
+
+def _identity(v):
+    return v
+
+
+def test_split_bregman_denoising_matches_chambolle():
+    """A = I: the split-Bregman iterates reach the minimiser that Chambolle's dual algorithm
+    (an independent method) finds for the same ROF problem."""
+    from oracle import chambolle_rof, split_bregman
+    rng = np.random.default_rng(31)
+    f = np.zeros((24, 24))
+    f[6:18, 8:20] = 1.0
+    f += 0.1 * rng.standard_normal(f.shape)
+    mu = 8.0
+    u_sb = split_bregman(_identity, _identity, f, mu=mu, lam=4.0, outer=400, inner=4)
+    u_ch = chambolle_rof(f, mu=mu, iters=6000)
+    assert np.abs(u_sb - u_ch).max() < 2e-3
+    # the minimiser removes noise: closer to the clean image than the data
+    clean = np.zeros_like(f)
+    clean[6:18, 8:20] = 1.0
+    assert np.linalg.norm(u_sb - clean) < 0.6 * np.linalg.norm(f - clean)
+
+
+def test_split_bregman_constant_data_is_a_fixed_point():
+    from oracle import split_bregman
+    f = np.full((10, 10), 2.5)
+    u = split_bregman(_identity, _identity, f, mu=3.0, lam=2.0, outer=5, inner=5)
+    np.testing.assert_allclose(u, f, rtol=1e-12)
+
+
+def test_split_bregman_small_tv_weight_gives_least_squares():
+    """With the data term weighted 1e12 times the TV term the minimiser is the least-squares
+    solution (here of a well-determined tomography problem; at 1e8 the TV term still moves the
+    minimiser by ~2e-5 along the operator's weakest directions, condition number ~440)."""
+    from oracle import split_bregman
+    op = Operator(Geometry(8, 12, 13))
+    rng = np.random.default_rng(32)
+    x_true = rng.uniform(0, 1, (8, 8))
+    f = op.project(x_true)
+    u = split_bregman(op.project, op.backproject, f, mu=1e12, lam=1.0, outer=3, inner=60)
+    assert np.linalg.norm(u - x_true) < 1e-6 * np.linalg.norm(x_true)
+
+
+def test_shrink_closed_form():
+    from oracle import shrink
+    s1 = np.array([3.0, 0.0, 0.3, 0.0])
+    s2 = np.array([4.0, 0.0, 0.4, -2.0])
+    d1, d2 = shrink(s1, s2, 1.0)
+    np.testing.assert_allclose(d1, [2.4, 0.0, 0.0, 0.0])
+    np.testing.assert_allclose(d2, [3.2, 0.0, 0.0, -1.0])
