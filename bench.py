@@ -518,6 +518,12 @@ def main():
         ms_cn1 = time_loop(torch, lambda: op.solve(y, xb, iters=0, method="cgnr"), 2)
         out["cgls"] = {"ms_per_iteration_f32": (ms_cg - ms_cg1) / 10, "batch": BATCH,
                        "normal_form_ms_per_iteration_f32": (ms_cn - ms_cn1) / 10}
+        sb = dict(method="tv_split_bregman", iters=5, tv_mu=0.5, tv_lambda=2.0)
+        op.solve(y, xb, refine_outer=1, **sb)
+        ms_sb3 = time_loop(torch, lambda: op.solve(y, xb, refine_outer=3, **sb), 2)
+        ms_sb1 = time_loop(torch, lambda: op.solve(y, xb, refine_outer=1, **sb), 2)
+        out["tv_split_bregman"] = {"ms_per_bregman_step_f32": (ms_sb3 - ms_sb1) / 2,
+                                   "cg_steps_per_bregman_step": 5, "batch": BATCH}
     if acc_ref is not None:
         out["accuracy"] = accuracy_leg(torch, tomo, op, acc_ref)
     if args.uneven:

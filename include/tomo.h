@@ -160,7 +160,13 @@ typedef enum {
   TOMO_SOLVE_SIRT_BB = 1,        /* SIRT, preconditioner D, Barzilai-Borwein steps (Sec. 3.1)  */
   TOMO_SOLVE_CGNR = 2,           /* CG on A^T A x = A^T b with A^T A from tomo_normal (Sec. 4,
                                     Toeplitz approach); needs n_det == grid                   */
-  TOMO_SOLVE_SIRT_BB_NORMAL = 3  /* SIRT_BB with A^T_D A from tomo_normal; needs n_det == grid */
+  TOMO_SOLVE_SIRT_BB_NORMAL = 3, /* SIRT_BB with A^T_D A from tomo_normal; needs n_det == grid */
+  TOMO_SOLVE_TV_SPLIT_BREGMAN = 4 /* min (tv_mu/2)|A x - b|^2 + sum |D x| (isotropic TV, forward
+                                    differences) by split Bregman (Sec. 3.1): refine_outer
+                                    Bregman steps of `iters` CG steps each on
+                                    (mu A^T A + lambda D^T D) x = mu A^T b + lambda D^T (d - e),
+                                    then d = shrink(D x + e, 1/lambda), e = D x + e - d;
+                                    A^T A from tomo_normal when n_det == grid              */
 } tomo_solver;
 
 typedef struct {
@@ -173,6 +179,8 @@ typedef struct {
   int32_t filter;         /* tomo_filter preconditioner D for SIRT_BB (NONE -> HAMMING)     */
   int32_t use_x0;         /* CGLS only: start from the contents of x instead of zero        */
   double* out_resnorm;    /* device [batch] float64 or NULL: |b - A x|_2 per slice at exit   */
+  double tv_mu;           /* TV_SPLIT_BREGMAN: data weight mu > 0                            */
+  double tv_lambda;       /* TV_SPLIT_BREGMAN: splitting penalty lambda > 0                  */
 } tomo_solve_opts;
 
 /* Build the operator for geometry `g` (Sec. 3.1 setup stage): the CSR matrices S^dagger

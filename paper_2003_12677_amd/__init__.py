@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libtomo.so")
 VALUES = {"f32": 0, "bf16": 1, "f16": 2}
 VALUE_MASK = {"f32": 1, "bf16": 2, "f16": 4}
 FILTERS = {"none": 0, "ramlak": 1, "shepp": 2, "hamming": 3}
-SOLVERS = {"cgls": 0, "sirt_bb": 1, "cgnr": 2, "sirt_bb_normal": 3}
+SOLVERS = {"cgls": 0, "sirt_bb": 1, "cgnr": 2, "sirt_bb_normal": 3, "tv_split_bregman": 4}
 STATUS = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EHIP", -4: "TOMO_EFFT",
           -5: "TOMO_ESTATE", -6: "TOMO_EUNSUPPORTED"}
 
@@ -66,7 +66,8 @@ class tomo_solve_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("refine_outer", ctypes.c_int32), ("values", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("use_x0", ctypes.c_int32),
-                ("out_resnorm", ctypes.c_void_p)]
+                ("out_resnorm", ctypes.c_void_p), ("tv_mu", ctypes.c_double),
+                ("tv_lambda", ctypes.c_double)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/tomo.h
@@ -322,7 +323,10 @@ class Operator:
 
     def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, *, method: str = "cgls",
               iters: int = 10, refine_outer: int = 1, values: str = "f32", filter: str = "none",
-              use_x0: bool = False, resnorm: torch.Tensor | None = None) -> torch.Tensor:
+              use_x0: bool = False, resnorm: torch.Tensor | None = None, tv_mu: float = 0.0,
+              tv_lambda: float = 0.0) -> torch.Tensor:
+        """``tomo_solve``.  For ``method="tv_split_bregman"``, ``refine_outer`` is the number of
+        Bregman steps, ``iters`` the CG steps in each, ``tv_mu`` / ``tv_lambda`` the weights."""
         B = b.shape[0]
         _need(b, self._sino_shape(B), self.device, "b")
         if x is None:
@@ -332,7 +336,7 @@ class Operator:
             if resnorm.dtype != torch.float64 or not resnorm.is_cuda or resnorm.numel() < B:
                 raise ValueError("resnorm must be a float64 device tensor with >= batch entries")
         o = tomo_solve_opts(SOLVERS[method], iters, refine_outer, VALUES[values], FILTERS[filter],
-                            1 if use_x0 else 0, _ptr(resnorm))
+                            1 if use_x0 else 0, _ptr(resnorm), float(tv_mu), float(tv_lambda))
         _check(_lib.tomo_solve(self._handle, _ptr(b), _ptr(x), B, ctypes.byref(o), _stream(self.device)))
         return x
 

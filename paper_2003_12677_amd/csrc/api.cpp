@@ -472,7 +472,7 @@ tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
   clear_error();
   if (!opts) return fail(TOMO_EINVAL, "opts is NULL");
   TOMO_TRY(check_apply(op, b, x, batch, opts->values));
-  if (opts->method < TOMO_SOLVE_CGLS || opts->method > TOMO_SOLVE_SIRT_BB_NORMAL)
+  if (opts->method < TOMO_SOLVE_CGLS || opts->method > TOMO_SOLVE_TV_SPLIT_BREGMAN)
     return fail(TOMO_EINVAL, "unknown solver %d", opts->method);
   if (opts->method == TOMO_SOLVE_CGNR || opts->method == TOMO_SOLVE_SIRT_BB_NORMAL)
     TOMO_TRY(normal_supported(op));
@@ -480,6 +480,10 @@ tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
     return fail(TOMO_EINVAL, "iters must be >= 0 and refine_outer >= 1");
   if (opts->filter < TOMO_FILTER_NONE || opts->filter > TOMO_FILTER_HAMMING)
     return fail(TOMO_EINVAL, "unknown filter %d", opts->filter);
+  if (opts->method == TOMO_SOLVE_TV_SPLIT_BREGMAN &&
+      (!(opts->tv_mu > 0) || !(opts->tv_lambda > 0) || !std::isfinite(opts->tv_mu) ||
+       !std::isfinite(opts->tv_lambda) || opts->use_x0))
+    return fail(TOMO_EINVAL, "split Bregman needs finite tv_mu > 0, tv_lambda > 0 and x0 = 0");
   if ((opts->method == TOMO_SOLVE_SIRT_BB || opts->method == TOMO_SOLVE_SIRT_BB_NORMAL) &&
       (opts->refine_outer != 1 || opts->use_x0))
     return fail(TOMO_EUNSUPPORTED, "SIRT-BB runs from zero without refinement");

@@ -202,6 +202,7 @@ struct SolverBuffers {
   float *r = nullptr, *q = nullptr, *rb = nullptr;     // sinogram-sized [B][nt][np]
   double* scal = nullptr;                              // per-slice scalars [16][B]
   double* partial = nullptr;                           // dot partial sums [B][kDotBlocks]
+  float* tvb = nullptr;                                // split-Bregman fields [6][B][n][n]
 };
 
 }  // namespace tomo

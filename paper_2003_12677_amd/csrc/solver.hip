@@ -133,6 +133,80 @@ tomo_status launch_lincomb(float* out, const float* a, const float* b, const dou
   return TOMO_OK;
 }
 
+// ---- split-Bregman TV: forward differences D (zero past the last row / column) and D^T -----
+// (D1 u)(i1,i2) = u(i1+1,i2) - u(i1,i2) for i1 < n-1, else 0; (D2 u) likewise along i2.
+// (D^T p)(i) = -p1(i) - p2(i) + p1(i1-1,i2) + p2(i1,i2-1), p1 taken as 0 on the last row and
+// p2 on the last column.
+
+__device__ __forceinline__ float tv_dt(const float* __restrict__ p1, const float* __restrict__ p2,
+                                       int n, int i1, int i2, int64_t i) {
+  const float a = (i1 < n - 1) ? p1[i] : 0.f;
+  const float b = (i2 < n - 1) ? p2[i] : 0.f;
+  float v = -a - b;
+  if (i1 > 0) v += p1[i - n];          // p1(i1-1, i2); i1-1 < n-1 always
+  if (i2 > 0) v += p2[i - 1];          // p2(i1, i2-1)
+  return v;
+}
+
+// rhs = mu ATf + lam D^T (d - b), per slice of n x n (tv buffers: d1, d2, b1, b2)
+__global__ __launch_bounds__(256) void k_sb_rhs(const float* __restrict__ ATf,
+                                                const float* __restrict__ d1,
+                                                const float* __restrict__ d2,
+                                                const float* __restrict__ b1,
+                                                const float* __restrict__ b2,
+                                                float* __restrict__ rhs, float mu, float lam, int n,
+                                                int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int64_t pix = i % ((int64_t)n * n);
+    const int i1 = (int)(pix / n), i2 = (int)(pix % n);
+    // D^T of (d - b): evaluate the two fields at the three points the operator touches
+    const float a = (i1 < n - 1) ? d1[i] - b1[i] : 0.f;
+    const float c = (i2 < n - 1) ? d2[i] - b2[i] : 0.f;
+    float v = -a - c;
+    if (i1 > 0) v += d1[i - n] - b1[i - n];
+    if (i2 > 0) v += d2[i - 1] - b2[i - 1];
+    rhs[i] = mu * ATf[i] + lam * v;
+  }
+}
+
+// q = mu q + lam D^T D p   (q holds A^T A p on entry)
+__global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, float* __restrict__ q,
+                                                   float mu, float lam, int n, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int64_t pix = i % ((int64_t)n * n);
+    const int i1 = (int)(pix / n), i2 = (int)(pix % n);
+    const float c = p[i];
+    // D p at (i1, i2), (i1-1, i2) [component 1] and (i1, i2-1) [component 2]
+    const float g1 = (i1 < n - 1) ? p[i + n] - c : 0.f;
+    const float g2 = (i2 < n - 1) ? p[i + 1] - c : 0.f;
+    float v = -g1 - g2;
+    if (i1 > 0) v += c - p[i - n];
+    if (i2 > 0) v += c - p[i - 1];
+    q[i] = mu * q[i] + lam * v;
+  }
+}
+
+// s = D u + b; d = shrink(s, 1/lam) (isotropic); b = s - d
+__global__ __launch_bounds__(256) void k_sb_shrink(const float* __restrict__ u, float* __restrict__ d1,
+                                                   float* __restrict__ d2, float* __restrict__ b1,
+                                                   float* __restrict__ b2, float thr, int n,
+                                                   int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int64_t pix = i % ((int64_t)n * n);
+    const int i1 = (int)(pix / n), i2 = (int)(pix % n);
+    const float c = u[i];
+    const float s1 = ((i1 < n - 1) ? u[i + n] - c : 0.f) + b1[i];
+    const float s2 = ((i2 < n - 1) ? u[i + 1] - c : 0.f) + b2[i];
+    const float mag = sqrtf(s1 * s1 + s2 * s2);
+    const float sc = mag > thr ? (mag - thr) / mag : 0.f;
+    const float e1 = sc * s1, e2 = sc * s2;
+    d1[i] = e1;
+    d2[i] = e2;
+    b1[i] = s1 - e1;
+    b2[i] = s2 - e2;
+  }
+}
+
 // out[i] = a value in [-1, 1) from a 32-bit integer hash of (i, seed): timing inputs
 __global__ __launch_bounds__(256) void k_fill_hash(float* __restrict__ out, int64_t len,
                                                    uint32_t seed) {
@@ -157,7 +231,7 @@ tomo_status launch_fill(float* out, float v, int64_t len, hipStream_t st) {
 
 void free_solver(tomo_op* op) {
   SolverBuffers& b = op->sb;
-  for (float** p : {&b.p, &b.s, &b.d, &b.r, &b.q, &b.rb}) {
+  for (float** p : {&b.p, &b.s, &b.d, &b.t, &b.r, &b.q, &b.rb, &b.tvb}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
@@ -178,6 +252,7 @@ tomo_status ensure_solver(tomo_op* op) {
   const size_t sino = B * g.nt * g.np * sizeof(float);
   struct Req { void** p; size_t bytes; } req[] = {
       {(void**)&b.p, img},  {(void**)&b.s, img},  {(void**)&b.d, img},  {(void**)&b.t, img},
+      {(void**)&b.tvb, 6 * img},
       {(void**)&b.r, sino}, {(void**)&b.q, sino}, {(void**)&b.rb, sino},
       {(void**)&b.scal, kSlots * B * sizeof(double)},
       {(void**)&b.partial, B * kDotBlocks * sizeof(double)}};
@@ -268,6 +343,70 @@ tomo_status cgnr(const Ctx& c, const float* b, float* x, int vt, int iters, bool
   return TOMO_OK;
 }
 
+// Split-Bregman TV (Sec. 3.1, the paper's TV algorithm): min (mu/2)||A x - b||^2 + sum |D x|.
+// Each outer step solves (mu A^T A + lam D^T D) x = mu A^T b + lam D^T (d - e) by `inner` CG
+// steps from the current x (A^T A through the normal-operator stencil when the geometry allows
+// it), then shrinks s = D x + e into d and sets e = s - d.  x0 = 0; d = e = 0.
+tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int outer, int inner,
+                             double mu, double lam) {
+  SolverBuffers& w = c.op->sb;
+  const int64_t tot = c.img * c.B;
+  float* ATf = w.tvb;
+  float* d1 = w.tvb + tot;
+  float* d2 = w.tvb + 2 * tot;
+  float* e1 = w.tvb + 3 * tot;
+  float* e2 = w.tvb + 4 * tot;
+  float* rhs = w.tvb + 5 * tot;
+  const bool nrm = normal_supported(c.op) == TOMO_OK;
+  clear_error();
+  const int n = c.op->g.n;
+  const unsigned grid = grid_for(tot);
+  // q = mu A^T A v + lam D^T D v
+  auto apply_M = [&](const float* v, float* q) -> tomo_status {
+    if (nrm) {
+      TOMO_TRY(apply_normal(c.op, v, q, c.B, vt, TOMO_FILTER_NONE, c.st));
+    } else {
+      TOMO_TRY(apply_project(c.op, v, w.q, c.B, vt, c.st));
+      TOMO_TRY(apply_backproject(c.op, w.q, q, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
+    }
+    hipLaunchKernelGGL(k_sb_addlap, dim3(grid), dim3(256), 0, c.st, v, q, (float)mu, (float)lam, n,
+                       tot);
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  };
+  TOMO_TRY(apply_backproject(c.op, b, ATf, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
+  TOMO_TRY(launch_fill(x, 0.f, tot, c.st));
+  TOMO_TRY(launch_fill(d1, 0.f, 4 * tot, c.st));                              // d1, d2, e1, e2
+  for (int k = 0; k < outer; ++k) {
+    hipLaunchKernelGGL(k_sb_rhs, dim3(grid), dim3(256), 0, c.st, ATf, d1, d2, e1, e2, rhs,
+                       (float)mu, (float)lam, n, tot);
+    TOMO_HIP(hipGetLastError());
+    // CG on M x = rhs from the current x: r = rhs - M x, p = r
+    TOMO_TRY(apply_M(x, w.t));
+    TOMO_TRY(c.lin(w.s, rhs, w.t, nullptr, nullptr, 1.0, -1.0, c.img));
+    TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));
+    int cur = kGamma0, nxt = kGamma1;
+    TOMO_TRY(c.dot(w.s, w.s, c.img, cur));
+    for (int it = 0; it < inner; ++it) {
+      TOMO_TRY(apply_M(w.p, w.t));                                             // q = M p
+      TOMO_TRY(c.dot(w.p, w.t, c.img, kDelta));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
+      TOMO_HIP(hipGetLastError());
+      TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));
+      TOMO_TRY(c.lin(w.s, w.s, w.t, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img));
+      TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
+      TOMO_HIP(hipGetLastError());
+      TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));
+      std::swap(cur, nxt);
+    }
+    hipLaunchKernelGGL(k_sb_shrink, dim3(grid), dim3(256), 0, c.st, x, d1, d2, e1, e2,
+                       (float)(1.0 / lam), n, tot);
+    TOMO_HIP(hipGetLastError());
+  }
+  return TOMO_OK;
+}
+
 // SIRT with the ramp/Hamming preconditioner D in the polar Fourier domain and BB steps:
 // g = A^T_D (A x - b), x0 = 0, gradients carried by the recurrence g -= alpha A^T_D A g.
 // With `normal`, h = A^T_D A g is applied through the normal-operator stencil of D.
@@ -304,7 +443,9 @@ tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_s
   Ctx c{op, B, st, (int64_t)op->g.n * op->g.n, (int64_t)op->g.nt * op->g.np};
   SolverBuffers& w = op->sb;
   const bool cg_normal = o->method == TOMO_SOLVE_CGNR;
-  if (o->method == TOMO_SOLVE_SIRT_BB || o->method == TOMO_SOLVE_SIRT_BB_NORMAL) {
+  if (o->method == TOMO_SOLVE_TV_SPLIT_BREGMAN) {
+    TOMO_TRY(tv_split_bregman(c, b, x, o->values, o->refine_outer, o->iters, o->tv_mu, o->tv_lambda));
+  } else if (o->method == TOMO_SOLVE_SIRT_BB || o->method == TOMO_SOLVE_SIRT_BB_NORMAL) {
     const int filter = o->filter == TOMO_FILTER_NONE ? TOMO_FILTER_HAMMING : o->filter;
     TOMO_TRY(sirt_bb(c, b, x, o->values, o->iters, filter,
                      o->method == TOMO_SOLVE_SIRT_BB_NORMAL));
