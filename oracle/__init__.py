@@ -27,7 +27,7 @@ from .fubini_radon import (  # noqa: F401
     ramp_filter,
     sdag_dense_direct,
 )
-from .density import backproject_weighted, density_target, density_weights, irradon_density  # noqa: F401,E501
+from .density import backproject_weighted, density_target, density_weights, mirror_average, irradon_density  # noqa: F401,E501
 from .lowprec import round_to_bf16, round_to_f16, round_values  # noqa: F401
 from .solvers import cgls, refine, sirt_bb  # noqa: F401
 from .normal import cg_normal, interpolation_product, normal, normal_factored  # noqa: F401
