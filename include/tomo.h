@@ -75,7 +75,9 @@ typedef enum {
   TOMO_FILTER_NONE = 0,
   TOMO_FILTER_RAMLAK = 1,
   TOMO_FILTER_SHEPP = 2,
-  TOMO_FILTER_HAMMING = 3
+  TOMO_FILTER_HAMMING = 3,
+  TOMO_FILTER_DENSITY = 4   /* tomo_irradon only: per-polar-sample weights from
+                               tomo_density_filter (Sec. 3 density filter)                    */
 } tomo_filter;
 
 /* Experimental parameters of the setup stage (Sec. 3.1: number of pixels, angles,
@@ -206,7 +208,9 @@ tomo_status tomo_backproject(tomo_op* op, const float* y, float* x, int32_t batc
                              int32_t values, void* stream);
 
 /* iRadon / filtered back-projection (Eq. (2), second line), scaled as
- * x = (pi / n_theta) A^T_D y with D = `filter` (TOMO_FILTER_NONE is rejected). */
+ * x = (pi / n_theta) A^T_D y with D = `filter` (TOMO_FILTER_NONE is rejected); with
+ * TOMO_FILTER_DENSITY, x = (L / G^2) A^T Diag(D_v) y with the weights of tomo_density_filter
+ * (TOMO_ESTATE if they were not computed). */
 tomo_status tomo_irradon(tomo_op* op, const float* y, float* x, int32_t batch,
                          int32_t values, int32_t filter, void* stream);
 
@@ -340,6 +344,19 @@ tomo_status tomo_graph_create(const tomo_step* steps, int32_t n, tomo_graph** ou
 tomo_status tomo_graph_launch(tomo_graph* g, void* stream);
 /* Free the graph (NULL is a no-op); does not synchronise. */
 void tomo_graph_destroy(tomo_graph* g);
+
+/* Density filter (Sec. 3): per-polar-sample weights D_v ~ arg min ||S D_v - c 1|| over the
+ * Cartesian grid, c = kappa(0)^2 the mass of the separable gridding kernel, among weights even
+ * in the frequency (D_v(k, a) = D_v(-k, a), which keeps the filtered back projection of a real
+ * sinogram real), by `iters` CGLS steps from zero (float32 vectors, float64 dots; the
+ * least-squares problem is rank deficient, so the weights are defined by this iteration).  Kept in the operator for
+ * TOMO_FILTER_DENSITY; *resid (nullable) receives ||S D_v - c 1||_2.  Synchronises the device
+ * and uses temporary device memory.  Errors: TOMO_EINVAL, TOMO_ESTATE, TOMO_ENOMEM, TOMO_EHIP. */
+tomo_status tomo_density_filter(tomo_op* op, int32_t iters, double* resid);
+
+/* Host copy of the density weights: w [L * n_theta] float32, FFT-ordered polar rows
+ * (k_fft * n_theta + a).  TOMO_ESTATE if they were not computed. */
+tomo_status tomo_export_density(const tomo_op* op, float* w);
 
 /* Host self-check (no device access): rebuild every kernel layout for the current tuning on
  * the host, apply each one in float64 following the kernels' traversal, and report the largest

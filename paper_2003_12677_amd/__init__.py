@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtomo.so")
 
 VALUES = {"f32": 0, "bf16": 1, "f16": 2}
 VALUE_MASK = {"f32": 1, "bf16": 2, "f16": 4}
-FILTERS = {"none": 0, "ramlak": 1, "shepp": 2, "hamming": 3}
+FILTERS = {"none": 0, "ramlak": 1, "shepp": 2, "hamming": 3, "density": 4}
 SOLVERS = {"cgls": 0, "sirt_bb": 1, "cgnr": 2, "sirt_bb_normal": 3, "tv_split_bregman": 4}
 STATUS = {0: "TOMO_OK", -1: "TOMO_EINVAL", -2: "TOMO_ENOMEM", -3: "TOMO_EHIP", -4: "TOMO_EFFT",
           -5: "TOMO_ESTATE", -6: "TOMO_EUNSUPPORTED"}
@@ -93,6 +93,8 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "tomo_export_normal": (ctypes.c_int, [_P, _I, _P]),
     "tomo_tv": (ctypes.c_int, [_P, _P, _I, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "tomo_density_filter": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_double)]),
+    "tomo_export_density": (ctypes.c_int, [_P, _P]),
     "tomo_graph_create": (ctypes.c_int, [ctypes.POINTER(tomo_step), _I, ctypes.POINTER(_P)]),
     "tomo_graph_launch": (ctypes.c_int, [_P, _P]),
     "tomo_graph_destroy": (None, [_P]),
@@ -243,6 +245,20 @@ class Operator:
         out = {name: getattr(t, name) for name, _ in tomo_tuning._fields_}
         out.update(fwd_ms=f.value, adj_ms=a.value)
         return out
+
+    def density_filter(self, iters: int = 100) -> float:
+        """``tomo_density_filter``: compute the density weights (kept for filter="density");
+        returns ||S D_v - kappa(0)^2 1||."""
+        r = ctypes.c_double()
+        _check(_lib.tomo_density_filter(self._handle, iters, ctypes.byref(r)))
+        return r.value
+
+    def export_density(self):
+        """Density weights on the host: float32 [L * n_angles], FFT-ordered polar rows."""
+        import numpy as np
+        w = np.empty(self.grid * self.n_angles, dtype=np.float32)
+        _check(_lib.tomo_export_density(self._handle, w.ctypes.data))
+        return w
 
     def check_layouts(self) -> float:
         """``tomo_check_layouts``: host replay of every kernel layout against the CSR products."""

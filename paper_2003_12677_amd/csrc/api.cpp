@@ -178,6 +178,7 @@ void free_device(tomo_op* op) {
   dfree(op->kd_dev);
   dfree(op->tw1);
   dfree(op->tw2);
+  dfree(op->dens);
   for (auto& f : op->filt_dev) dfree(f);
   dfree(op->X);
   dfree(op->Y);
@@ -300,7 +301,11 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
     TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
   }
   TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
-  const float* ds = (filter == TOMO_FILTER_NONE) ? nullptr : op->filt_dev[filter];
+  const float* ds = nullptr;
+  if (filter == TOMO_FILTER_DENSITY)
+    TOMO_TRY(launch_scale_rows(op->Y, op->dens, (int64_t)g.L * g.nt, C, st));
+  else if (filter != TOMO_FILTER_NONE)
+    ds = op->filt_dev[filter];
   TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
   TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
   if (op->tune.grid_fft && grid_fft_supported(op))
@@ -436,12 +441,16 @@ tomo_status tomo_irradon(tomo_op* op, const float* y, float* x, int32_t batch, i
                          int32_t filter, void* stream) {
   clear_error();
   TOMO_TRY(check_apply(op, y, x, batch, values));
-  if (filter < TOMO_FILTER_RAMLAK || filter > TOMO_FILTER_HAMMING)
+  if (filter < TOMO_FILTER_RAMLAK || filter > TOMO_FILTER_DENSITY)
     return fail(TOMO_EINVAL, "irradon needs a filter (got %d)", filter);
+  if (filter == TOMO_FILTER_DENSITY && !op->dens)
+    return fail(TOMO_ESTATE, "density weights not computed (tomo_density_filter)");
   if (batch == 0) return TOMO_OK;
   DeviceGuard guard(op->device);
-  return apply_backproject(op, y, x, batch, values, filter, (float)(M_PI / op->g.nt),
-                           (hipStream_t)stream);
+  const float scale = filter == TOMO_FILTER_DENSITY
+                          ? (float)((double)op->g.L / ((double)op->g.G * op->g.G))
+                          : (float)(M_PI / op->g.nt);
+  return apply_backproject(op, y, x, batch, values, filter, scale, (hipStream_t)stream);
 }
 
 tomo_status tomo_slice_fwd(tomo_op* op, const float* Xc, float* Yp, int32_t batch, int32_t values,
@@ -490,6 +499,28 @@ tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
   if (batch == 0) return TOMO_OK;
   DeviceGuard guard(op->device);
   return run_solve(op, b, x, batch, opts, (hipStream_t)stream);
+}
+
+tomo_status tomo_density_filter(tomo_op* op, int32_t iters, double* resid) {
+  clear_error();
+  if (!op) return fail(TOMO_EINVAL, "operator is NULL");
+  if (op->device < 0) return fail(TOMO_ESTATE, "operator was built without a device");
+  if (iters < 1 || iters > 100000) return fail(TOMO_EINVAL, "iters must be in [1, 100000]");
+  if (!(op->values & TOMO_VALUES_F32)) return fail(TOMO_ESTATE, "needs float32 values");
+  DeviceGuard guard(op->device);
+  TOMO_HIP(hipDeviceSynchronize());
+  TOMO_TRY(run_density(op, iters, resid, nullptr));
+  TOMO_HIP(hipDeviceSynchronize());
+  return TOMO_OK;
+}
+
+tomo_status tomo_export_density(const tomo_op* op, float* w) {
+  clear_error();
+  if (!op || !w) return fail(TOMO_EINVAL, "NULL argument");
+  if (!op->dens) return fail(TOMO_ESTATE, "density weights not computed (tomo_density_filter)");
+  DeviceGuard guard(op->device);
+  TOMO_HIP(hipMemcpy(w, op->dens, (size_t)op->g.L * op->g.nt * sizeof(float), hipMemcpyDeviceToHost));
+  return TOMO_OK;
 }
 
 tomo_status tomo_autotune(tomo_op* op, int32_t batch, int32_t values, int32_t rounds,

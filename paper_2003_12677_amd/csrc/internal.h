@@ -222,6 +222,7 @@ struct tomo_op {
   float* kd_dev = nullptr;        // [n]
   float2* tw1 = nullptr;          // [L] exp(-2 pi i j / L) when L is a power of two (fused 1D DFTs)
   float2* tw2 = nullptr;          // [G] exp(-2 pi i j / G) when G is a power of two (fused 2D DFTs)
+  float* dens = nullptr;          // [L*nt] density-filter weights (tomo_density_filter)
   float* filt_dev[4] = {nullptr, nullptr, nullptr, nullptr};   // D per tomo_filter, [L]
   int cmax = 0;                   // complex channels the workspace holds
   float2* X = nullptr;            // [G*G][C]     channel-fastest Cartesian grid (SpMM side)
@@ -341,6 +342,10 @@ tomo_status launch_lincomb(float* out, const float* a, const float* b, const dou
                            hipStream_t st);
 tomo_status launch_fill(float* out, float v, int64_t len, hipStream_t st);
 tomo_status launch_fill_hash(float* out, int64_t len, uint32_t seed, hipStream_t st);
+// Density-filter weights by CGLS on S (one complex channel); stores op->dens.
+tomo_status run_density(tomo_op* op, int iters, double* resid, hipStream_t st);
+// Y[p][c] *= w[p] for P rows of C complex channels.
+tomo_status launch_scale_rows(float2* Y, const float* w, int64_t P, int C, hipStream_t st);
 // Validate and apply a tuning (re-uploading the layouts it changes; synchronises the device).
 tomo_status apply_tuning(tomo_op* op, const Tuning& t);
 // Coordinate-descent search of the SpMM tuning for `batch` slices in value type vt.

@@ -86,6 +86,16 @@ __global__ __launch_bounds__(256) void k_pad_sino(const float* __restrict__ y, f
   Ys[((int64_t)c * nt + a) * L + m] = v;
 }
 
+// Y[p][c] *= w[p] (a per-row diagonal on a channel-fastest buffer)
+__global__ __launch_bounds__(256) void k_scale_rows(float2* __restrict__ Y, const float* __restrict__ w,
+                                                    int64_t total, int C) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const float s = w[i / C];
+    const float2 v = Y[i];
+    Y[i] = make_float2(v.x * s, v.y * s);
+  }
+}
+
 // a[C][P] -> b[P][C], tiles of 64 points x 16 channels through LDS
 __global__ __launch_bounds__(256) void k_to_fastest(const float2* __restrict__ a, float2* __restrict__ b,
                                                     int64_t P, int C) {
@@ -161,6 +171,14 @@ __global__ __launch_bounds__(256) void k_polar_to_fastest(const float2* __restri
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
+
+tomo_status launch_scale_rows(float2* Y, const float* w, int64_t P, int C, hipStream_t st) {
+  const int64_t total = P * C;
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65535)),
+                     dim3(256), 0, st, Y, w, total, C);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
 
 tomo_status launch_embed(const tomo_op* op, const float* x, float2* Xs, int B, hipStream_t st) {
   const Geom& g = op->g;

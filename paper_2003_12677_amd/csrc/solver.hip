@@ -436,6 +436,114 @@ tomo_status sirt_bb(const Ctx& c, const float* b, float* x, int vt, int iters, i
 
 }  // namespace
 
+// out[i] = re if i even, 0 if odd (a real vector as one complex channel); dst[i] = src[2 i]
+__global__ __launch_bounds__(256) void k_fill_real(float* __restrict__ out, float v, int64_t n2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (int64_t)gridDim.x * 256)
+    out[i] = (i & 1) ? 0.f : v;
+}
+__global__ __launch_bounds__(256) void k_real_part(const float* __restrict__ src, float* __restrict__ dst,
+                                                   int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[2 * i];
+}
+
+// v(kf, a) and v(L - kf, a) (frequencies k and -k at one angle, FFT-ordered rows kf * nt + a)
+// both set to their mean; kf = 0 and, for even L, kf = L/2 have no mirror and stay.
+__global__ __launch_bounds__(256) void k_mirror_average(float2* __restrict__ v, int L, int nt) {
+  const int64_t pairs = (int64_t)((L - 1) / 2) * nt;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * 256) {
+    const int kf = 1 + (int)(i / nt), a = (int)(i % nt);
+    const int64_t p = (int64_t)kf * nt + a, q = (int64_t)(L - kf) * nt + a;
+    const float2 x = v[p], y = v[q];
+    const float2 m = make_float2(0.5f * (x.x + y.x), 0.5f * (x.y + y.y));
+    v[p] = m;
+    v[q] = m;
+  }
+}
+
+// Density filter (Sec. 3): CGLS from zero on S Pi D_v = c 1 over weights even in the frequency
+// (Pi the mirror average; see k_mirror_average), c = kappa(0)^2 = 1 / k*(origin), with the
+// forward / adjoint SpMMs on one complex channel whose imaginary parts stay zero.  Even weights
+// keep the filtered back projection of a real sinogram real, which the pairing of two slices in
+// one complex channel needs.
+tomo_status run_density(tomo_op* op, int iters, double* resid, hipStream_t st) {
+  const Geom& g = op->g;
+  const int64_t N = (int64_t)g.L * g.nt, M = (int64_t)g.G * g.G;
+  const double kd0 = op->kd[g.on];
+  const float target = (float)(1.0 / (kd0 * kd0));
+  float *v = nullptr, *s = nullptr, *p = nullptr, *r = nullptr, *q = nullptr;
+  double *scal = nullptr, *partial = nullptr;
+  struct Req { void** p; size_t bytes; } req[] = {
+      {(void**)&v, (size_t)N * 8}, {(void**)&s, (size_t)N * 8}, {(void**)&p, (size_t)N * 8},
+      {(void**)&r, (size_t)M * 8}, {(void**)&q, (size_t)M * 8},
+      {(void**)&scal, kSlots * sizeof(double)}, {(void**)&partial, kDotBlocks * sizeof(double)}};
+  tomo_status status = TOMO_OK;
+  for (auto& rq : req)
+    if (status == TOMO_OK && hipMalloc(rq.p, rq.bytes) != hipSuccess) {
+      *rq.p = nullptr;
+      status = fail(TOMO_ENOMEM, "density filter workspace (%zu B)", rq.bytes);
+    }
+  auto sc = [&](int slot) { return scal + slot; };
+  auto dot = [&](const float* a, const float* b, int64_t len, int slot) {
+    return launch_dot(a, b, len, 1, partial, sc(slot), st);
+  };
+  auto lin = [&](float* out, const float* a, const float* b, const double* ca, const double* cb,
+                 double sa, double sb, int64_t len) {
+    return launch_lincomb(out, a, b, ca, cb, sa, sb, len, 1, st);
+  };
+  auto body = [&]() -> tomo_status {
+    hipLaunchKernelGGL(k_fill_real, dim3(grid_for(2 * M)), dim3(256), 0, st, r, target, 2 * M);
+    TOMO_HIP(hipGetLastError());
+    TOMO_TRY(launch_fill(v, 0.f, 2 * N, st));
+    auto grad = [&]() -> tomo_status {   // s = Pi S^T r
+      TOMO_TRY(launch_spmm_fwd(op, (const float2*)r, (float2*)s, 1, TOMO_VAL_F32, st));
+      hipLaunchKernelGGL(k_mirror_average, dim3(grid_for((int64_t)((g.L - 1) / 2) * g.nt)), dim3(256),
+                         0, st, (float2*)s, g.L, g.nt);
+      TOMO_HIP(hipGetLastError());
+      return TOMO_OK;
+    };
+    TOMO_TRY(grad());
+    TOMO_TRY(lin(p, s, nullptr, nullptr, nullptr, 1.0, 0.0, 2 * N));
+    int cur = kGamma0, nxt = kGamma1;
+    TOMO_TRY(dot(s, s, 2 * N, cur));
+    for (int it = 0; it < iters; ++it) {
+      TOMO_TRY(launch_spmm_adj(op, (const float2*)p, (float2*)q, 1, TOMO_VAL_F32, nullptr, st));
+      TOMO_TRY(dot(q, q, 2 * M, kDelta));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, st, sc(cur), sc(kDelta), sc(kAlpha), 1);
+      TOMO_HIP(hipGetLastError());
+      TOMO_TRY(lin(v, v, p, nullptr, sc(kAlpha), 1.0, 1.0, 2 * N));
+      TOMO_TRY(lin(r, r, q, nullptr, sc(kAlpha), 1.0, -1.0, 2 * M));
+      TOMO_TRY(grad());
+      TOMO_TRY(dot(s, s, 2 * N, nxt));
+      hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, st, sc(nxt), sc(cur), sc(kBeta), 1);
+      TOMO_HIP(hipGetLastError());
+      TOMO_TRY(lin(p, s, p, nullptr, sc(kBeta), 1.0, 1.0, 2 * N));
+      std::swap(cur, nxt);
+    }
+    if (!op->dens) {
+      if (hipMalloc((void**)&op->dens, (size_t)N * sizeof(float)) != hipSuccess) {
+        op->dens = nullptr;
+        return fail(TOMO_ENOMEM, "density weights (%lld floats)", (long long)N);
+      }
+    }
+    hipLaunchKernelGGL(k_real_part, dim3(grid_for(N)), dim3(256), 0, st, v, op->dens, N);
+    TOMO_HIP(hipGetLastError());
+    if (resid) {
+      TOMO_TRY(dot(r, r, 2 * M, kTmp));
+      double rr = 0;
+      TOMO_HIP(hipMemcpyAsync(&rr, sc(kTmp), sizeof(double), hipMemcpyDeviceToHost, st));
+      TOMO_HIP(hipStreamSynchronize(st));
+      *resid = std::sqrt(rr);
+    }
+    return TOMO_OK;
+  };
+  if (status == TOMO_OK) status = body();
+  (void)hipStreamSynchronize(st);
+  for (auto& rq : req)
+    if (*rq.p) (void)hipFree(*rq.p);
+  return status;
+}
+
 tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_solve_opts* o,
                       hipStream_t st) {
   if (B > 256) return fail(TOMO_EINVAL, "batch too large for the scalar kernels");
