@@ -131,15 +131,18 @@ typedef struct {
                                      many rows (>= 1; 1 = natural order)                       */
   int32_t adj_medium_max;         /* longer rows up to this many entries: one wavefront each  */
   int32_t adj_chunk;              /* rows above that: chunks of this many entries (8..8192)   */
-  int32_t fwd_tiled;              /* 1: forward SpMM stages Cartesian tiles (+ halo) in LDS;
-                                     0: one lane group per row with every tap gathered from L2 */
-  int32_t adj_tiled;              /* 1: adjoint SpMM stages each output tile's polar rows in LDS
-                                     in chunks; 0: the row-binned layouts above                */
-  int32_t tile;                   /* Cartesian tile side of the staged kernels: 8, 16 or 32   */
-  int32_t tile_points;            /* forward: samples per block; adjoint: polar rows staged per
-                                     chunk (32, 64, 96 or 128)                                 */
-  int32_t tile_chunks;            /* adjoint: chunks one block accumulates before a tile is
-                                     split into partial sums (1..64)                           */
+  int32_t fwd_tiled;              /* value-type bit mask (1 f32, 2 bf16, 4 f16): forward SpMM
+                                     stages Cartesian tiles (+ halo) and the tile's sample
+                                     records in LDS; clear bit: one lane group per row with
+                                     every tap gathered from L2                                */
+  int32_t adj_tiled;              /* value-type bit mask: adjoint SpMM stages, per output tile,
+                                     the polar samples whose windows reach it in LDS, and runs
+                                     the row kernels on the cells of tiles with too many
+                                     samples; clear bit: the row-binned layouts for every cell */
+  int32_t tile;                   /* Cartesian tile side of the staged kernels: 8 or 16        */
+  int32_t tile_points;            /* forward: samples per block (32, 64, 96 or 128)            */
+  int32_t adj_tile_points;        /* adjoint: most samples a staged tile may hold (multiple of
+                                     32 in [32, 256]); denser tiles go to the row kernels     */
   int32_t normal_tiled;           /* normal operator: 1 stages each channel's grid tile (+ halo)
                                      in LDS; 0 reads every stencil tap through L1/L2           */
   int32_t adj_sell_xcd_rows;      /* sliced-ELL adjoint kernel: its blocks go to the 8 XCDs in runs

@@ -56,7 +56,7 @@ class tomo_tuning(ctypes.Structure):
                 ("adj_sell_max", ctypes.c_int32), ("adj_sell_sigma", ctypes.c_int32),
                 ("adj_medium_max", ctypes.c_int32), ("adj_chunk", ctypes.c_int32),
                 ("fwd_tiled", ctypes.c_int32), ("adj_tiled", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("tile_points", ctypes.c_int32), ("tile_chunks", ctypes.c_int32),
+                ("tile_points", ctypes.c_int32), ("adj_tile_points", ctypes.c_int32),
                 ("normal_tiled", ctypes.c_int32), ("adj_sell_xcd_rows", ctypes.c_int32),
                 ("adj_medium_xcd_rows", ctypes.c_int32), ("fwd_rows_per_group", ctypes.c_int32),
                 ("det_fft", ctypes.c_int32), ("grid_fft", ctypes.c_int32)]

@@ -49,8 +49,7 @@ tomo_status upload_values(const std::vector<double>& v, uint32_t values, void* d
   return TOMO_OK;
 }
 
-void free_adj(tomo_op* op) {
-  DevAdj& d = op->adj;
+void free_adj_layout(DevAdj& d) {
   dfree(d.slice_ptr);
   dfree(d.slice_rows);
   dfree(d.col);
@@ -63,8 +62,33 @@ void free_adj(tomo_op* op) {
   dfree(d.chunk_end);
   dfree(d.long_chunk_ptr);
   d = DevAdj();
+}
+
+void free_adj(tomo_op* op) {
+  free_adj_layout(op->adj);
   dfree(op->partials);
   op->partials_cap = 0;
+}
+
+tomo_status upload_adj_layout(const HostAdj& h, uint32_t values, DevAdj& d) {
+  if (h.col.size() >= (size_t)INT32_MAX)
+    return fail(TOMO_EINVAL, "sliced-ELL layout exceeds 32-bit entry indices; lower adj_sell_max");
+  d.n_slices = (int64_t)h.slice_ptr.size() - 1;
+  d.n_medium = h.n_medium;
+  d.n_long = h.n_long;
+  d.n_chunks = (int64_t)h.chunk_beg.size();
+  TOMO_TRY(upload(&d.slice_ptr, h.slice_ptr.data(), h.slice_ptr.size()));
+  TOMO_TRY(upload(&d.slice_rows, h.slice_rows.data(), h.slice_rows.size()));
+  TOMO_TRY(upload(&d.col, h.col.data(), h.col.size()));
+  TOMO_TRY(upload_values(h.val, values, d.val));
+  TOMO_TRY(upload(&d.tail_rows, h.tail_rows.data(), h.tail_rows.size()));
+  TOMO_TRY(upload(&d.tail_ptr, h.tail_ptr.data(), h.tail_ptr.size()));
+  TOMO_TRY(upload(&d.tail_col, h.tail_col.data(), h.tail_col.size()));
+  TOMO_TRY(upload_values(h.tail_val, values, d.tail_val));
+  TOMO_TRY(upload(&d.chunk_beg, h.chunk_beg.data(), h.chunk_beg.size()));
+  TOMO_TRY(upload(&d.chunk_end, h.chunk_end.data(), h.chunk_end.size()));
+  TOMO_TRY(upload(&d.long_chunk_ptr, h.long_chunk_ptr.data(), h.long_chunk_ptr.size()));
+  return TOMO_OK;
 }
 
 // (Re)build the adjoint layout for op->tune on the host and upload it.
@@ -73,24 +97,8 @@ tomo_status upload_adj(tomo_op* op) {
   free_adj(op);
   build_adj_layout(op->s, op->tune, &op->hadj);
   const HostAdj& h = op->hadj;
-  if (h.col.size() >= (size_t)INT32_MAX)
-    return fail(TOMO_EINVAL, "sliced-ELL layout exceeds 32-bit entry indices; lower adj_sell_max");
   DevAdj& d = op->adj;
-  d.n_slices = (int64_t)h.slice_ptr.size() - 1;
-  d.n_medium = h.n_medium;
-  d.n_long = h.n_long;
-  d.n_chunks = (int64_t)h.chunk_beg.size();
-  TOMO_TRY(upload(&d.slice_ptr, h.slice_ptr.data(), h.slice_ptr.size()));
-  TOMO_TRY(upload(&d.slice_rows, h.slice_rows.data(), h.slice_rows.size()));
-  TOMO_TRY(upload(&d.col, h.col.data(), h.col.size()));
-  TOMO_TRY(upload_values(h.val, op->g.values, d.val));
-  TOMO_TRY(upload(&d.tail_rows, h.tail_rows.data(), h.tail_rows.size()));
-  TOMO_TRY(upload(&d.tail_ptr, h.tail_ptr.data(), h.tail_ptr.size()));
-  TOMO_TRY(upload(&d.tail_col, h.tail_col.data(), h.tail_col.size()));
-  TOMO_TRY(upload_values(h.tail_val, op->g.values, d.tail_val));
-  TOMO_TRY(upload(&d.chunk_beg, h.chunk_beg.data(), h.chunk_beg.size()));
-  TOMO_TRY(upload(&d.chunk_end, h.chunk_end.data(), h.chunk_end.size()));
-  TOMO_TRY(upload(&d.long_chunk_ptr, h.long_chunk_ptr.data(), h.long_chunk_ptr.size()));
+  TOMO_TRY(upload_adj_layout(h, op->g.values, d));
   if (d.n_chunks > 0) {
     const size_t pb = (size_t)d.n_chunks * op->cmax * sizeof(float2);
     if (hipMalloc((void**)&op->partials, pb) != hipSuccess) {
@@ -105,16 +113,14 @@ tomo_status upload_adj(tomo_op* op) {
 
 void free_tiles(tomo_op* op) {
   DevFwdTiles& f = op->ftile;
-  dfree(f.wi_tile); dfree(f.wi_beg); dfree(f.pt_row); dfree(f.pt_slot);
+  dfree(f.wi_tile); dfree(f.wi_beg); dfree(f.pt_row); dfree(f.pt_base);
   for (auto& v : f.val) dfree(v);
   f = DevFwdTiles();
-  DevAdjTiles& a = op->atile;
-  dfree(a.wi_tile); dfree(a.wi_cb); dfree(a.wi_ce); dfree(a.wi_out);
-  dfree(a.ch_pt_beg); dfree(a.ch_pts); dfree(a.ch_row_off); dfree(a.en_slot);
-  for (auto& v : a.en_val) dfree(v);
-  dfree(a.red_tile); dfree(a.red_beg); dfree(a.red_cnt);
-  a = DevAdjTiles();
-  dfree(op->tile_partials);
+  DevAdjWin& a = op->awin;
+  dfree(a.wi_tile); dfree(a.wi_q); dfree(a.wi_boff); dfree(a.q_row);
+  for (auto& v : a.q_val) dfree(v);
+  a = DevAdjWin();
+  free_adj_layout(op->adj_dense);
 }
 
 // (Re)build the LDS-staged layouts for op->tune on the host and upload them.
@@ -126,40 +132,31 @@ tomo_status upload_tiles(tomo_op* op) {
     TOMO_TRY(build_fwd_tiles(op->g, op->sdag, op->centres, op->tune, &h));
     DevFwdTiles& d = op->ftile;
     d.n_wi = (int64_t)h.wi_tile.size();
-    d.TS = h.TS; d.PS = h.PS; d.NT = h.NT; d.WS = h.WS;
+    d.TS = h.TS; d.PS = h.PS; d.NT = h.NT; d.KW = h.KW;
     TOMO_TRY(upload(&d.wi_tile, h.wi_tile.data(), h.wi_tile.size()));
     TOMO_TRY(upload(&d.wi_beg, h.wi_beg.data(), h.wi_beg.size()));
     TOMO_TRY(upload(&d.pt_row, h.pt_row.data(), h.pt_row.size()));
-    TOMO_TRY(upload(&d.pt_slot, h.pt_slot.data(), h.pt_slot.size()));
+    TOMO_TRY(upload(&d.pt_base, h.pt_base.data(), h.pt_base.size()));
     TOMO_TRY(upload_values(h.pt_val, op->g.values, d.val));
   }
   {
-    HostAdjTiles h;
-    TOMO_TRY(build_adj_tiles(op->g, op->s, op->tune, &h));
-    DevAdjTiles& d = op->atile;
+    HostAdjWin h;
+    TOMO_TRY(build_adj_win(op->g, op->sdag, op->centres, op->tune, &h));
+    DevAdjWin& d = op->awin;
     d.n_wi = (int64_t)h.wi_tile.size();
-    d.n_red = (int64_t)h.red_tile.size();
-    d.n_pslots = h.n_pslots;
-    d.TS = h.TS; d.NT = h.NT; d.qmax = op->tune.tile_points; d.emax = std::max(1, h.emax);
+    d.TS = h.TS; d.RS = h.RS; d.NT = h.NT; d.KW = h.KW; d.QMAX = h.QMAX;
     TOMO_TRY(upload(&d.wi_tile, h.wi_tile.data(), h.wi_tile.size()));
-    TOMO_TRY(upload(&d.wi_cb, h.wi_chunk_beg.data(), h.wi_chunk_beg.size()));
-    TOMO_TRY(upload(&d.wi_ce, h.wi_chunk_end.data(), h.wi_chunk_end.size()));
-    TOMO_TRY(upload(&d.wi_out, h.wi_out.data(), h.wi_out.size()));
-    TOMO_TRY(upload(&d.ch_pt_beg, h.ch_pt_beg.data(), h.ch_pt_beg.size()));
-    TOMO_TRY(upload(&d.ch_pts, h.ch_pts.data(), h.ch_pts.size()));
-    TOMO_TRY(upload(&d.ch_row_off, h.ch_row_off.data(), h.ch_row_off.size()));
-    TOMO_TRY(upload(&d.en_slot, h.en_slot.data(), h.en_slot.size()));
-    TOMO_TRY(upload_values(h.en_val, op->g.values, d.en_val));
-    TOMO_TRY(upload(&d.red_tile, h.red_tile.data(), h.red_tile.size()));
-    TOMO_TRY(upload(&d.red_beg, h.red_beg.data(), h.red_beg.size()));
-    TOMO_TRY(upload(&d.red_cnt, h.red_cnt.data(), h.red_cnt.size()));
-    if (d.n_pslots > 0) {
-      const size_t pb = (size_t)d.n_pslots * d.TS * d.TS * op->cmax * sizeof(float2);
-      if (hipMalloc((void**)&op->tile_partials, pb) != hipSuccess) {
-        op->tile_partials = nullptr;
-        return fail(TOMO_ENOMEM, "tile partial sums (%zu B)", pb);
-      }
-    }
+    TOMO_TRY(upload(&d.wi_q, h.wi_q.data(), h.wi_q.size()));
+    TOMO_TRY(upload(&d.wi_boff, h.wi_boff.data(), h.wi_boff.size()));
+    TOMO_TRY(upload(&d.q_row, h.q_row.data(), h.q_row.size()));
+    TOMO_TRY(upload_values(h.q_val, op->g.values, d.q_val));
+    // dense cells: the row kernels' layout over those cells (its long rows are a subset of the
+    // full layout's, so the long-row partial-sum buffer already fits them)
+    HostAdj hd;
+    build_adj_layout(op->s, op->tune, &hd, &h.dense_cell);
+    if ((size_t)hd.chunk_beg.size() > op->partials_cap)
+      return fail(TOMO_EINVAL, "internal: dense-cell layout has more long-row chunks than the full one");
+    TOMO_TRY(upload_adj_layout(hd, op->g.values, op->adj_dense));
   }
   op->tiles_ready = true;
   return TOMO_OK;
@@ -189,6 +186,7 @@ void free_device(tomo_op* op) {
 tomo_status upload_all(tomo_op* op) {
   const Geom& g = op->g;
   op->cmax = (g.max_batch + 1) / 2;
+  TOMO_HIP(hipDeviceGetAttribute(&op->n_cu, hipDeviceAttributeMultiprocessorCount, op->device));
   {
     HostEll ell;
     build_ell(op->sdag, g.kw * g.kw, &ell);
@@ -660,7 +658,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->adj_tiled = op->tune.adj_tiled;
   out->tile = op->tune.tile;
   out->tile_points = op->tune.tile_points;
-  out->tile_chunks = op->tune.tile_chunks;
+  out->adj_tile_points = op->tune.adj_tile_points;
   out->normal_tiled = op->tune.normal_tiled;
   out->adj_sell_xcd_rows = op->tune.sell_xcd_rows;
   out->adj_medium_xcd_rows = op->tune.medium_xcd_rows;
@@ -684,7 +682,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.adj_tiled = in->adj_tiled;
   t.tile = in->tile;
   t.tile_points = in->tile_points;
-  t.tile_chunks = in->tile_chunks;
+  t.adj_tile_points = in->adj_tile_points;
   t.normal_tiled = in->normal_tiled;
   t.sell_xcd_rows = in->adj_sell_xcd_rows;
   t.medium_xcd_rows = in->adj_medium_xcd_rows;
@@ -701,8 +699,9 @@ tomo_status apply_tuning(tomo_op* op, const Tuning& t) {
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
-  const bool retile = t.tile != op->tune.tile || t.tile_points != op->tune.tile_points ||
-                      t.tile_chunks != op->tune.tile_chunks;
+  // the staged adjoint's dense cells use a row layout with the same bins, so it is rebuilt too
+  const bool retile = relayout || t.tile != op->tune.tile || t.tile_points != op->tune.tile_points ||
+                      t.adj_tile_points != op->tune.adj_tile_points;
   op->tune = t;
   if (op->device < 0) {
     if (relayout) build_adj_layout(op->s, op->tune, &op->hadj);

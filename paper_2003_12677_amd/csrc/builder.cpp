@@ -229,12 +229,13 @@ void build_ell(const HostCSR& a, int W2, HostEll* out) {
 
 tomo_status check_tuning(const Tuning& t) {
   auto cpl_ok = [](int c) { return c == 1 || c == 2 || c == 4; };
-  if ((t.fwd_tiled != 0 && t.fwd_tiled != 1) || (t.adj_tiled != 0 && t.adj_tiled != 1))
-    return fail(TOMO_EINVAL, "fwd_tiled / adj_tiled must be 0 or 1");
-  if (t.tile != 8 && t.tile != 16 && t.tile != 32) return fail(TOMO_EINVAL, "tile must be 8, 16 or 32");
+  if (t.fwd_tiled < 0 || t.fwd_tiled > 7 || t.adj_tiled < 0 || t.adj_tiled > 7)
+    return fail(TOMO_EINVAL, "fwd_tiled / adj_tiled are value-type bit masks in [0, 7]");
+  if (t.tile != 8 && t.tile != 16) return fail(TOMO_EINVAL, "tile must be 8 or 16");
   if (t.tile_points < 32 || t.tile_points > 128 || t.tile_points % 32 != 0)
     return fail(TOMO_EINVAL, "tile_points must be 32, 64, 96 or 128");
-  if (t.tile_chunks < 1 || t.tile_chunks > 64) return fail(TOMO_EINVAL, "tile_chunks must be in [1, 64]");
+  if (t.adj_tile_points < 32 || t.adj_tile_points > 256 || t.adj_tile_points % 32 != 0)
+    return fail(TOMO_EINVAL, "adj_tile_points must be a multiple of 32 in [32, 256]");
   if (t.normal_tiled != 0 && t.normal_tiled != 1) return fail(TOMO_EINVAL, "normal_tiled must be 0 or 1");
   if (t.sell_xcd_rows < 0 || t.sell_xcd_rows > (1 << 24) || t.medium_xcd_rows < 0 ||
       t.medium_xcd_rows > (1 << 24))
@@ -253,11 +254,12 @@ tomo_status check_tuning(const Tuning& t) {
   return TOMO_OK;
 }
 
-void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* o) {
+void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* o, const std::vector<char>* rows) {
   *o = HostAdj();
   std::vector<int32_t> sell, medium, lng;
   auto len = [&](int64_t r) { return s.rowptr[r + 1] - s.rowptr[r]; };
   for (int64_t r = 0; r < s.rows; ++r) {
+    if (rows && !(*rows)[(size_t)r]) continue;
     const int64_t l = len(r);
     if (l <= t.sell_max) sell.push_back((int32_t)r);
     else if (l <= t.medium_max) medium.push_back((int32_t)r);
@@ -332,13 +334,12 @@ inline int tile_of(int j, int oG, int TS) { return (j + oG) / TS; }
 tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
                             const Tuning& t, HostFwdTiles* o) {
   *o = HostFwdTiles();
-  const int G = g.G, oG = G / 2, TS = t.tile, h = g.h;
+  const int G = g.G, oG = G / 2, TS = t.tile, h = g.h, kw = g.kw;
   o->TS = TS;
-  o->PS = TS + 2 * h;
+  o->PS = TS + 2 * h + 1;
   o->NT = (G + TS - 1) / TS;
-  o->W2 = g.kw * g.kw;
-  o->WS = (o->W2 + 3) / 4 * 4;
-  if ((int64_t)o->PS * o->PS > 0xFFFF) return fail(TOMO_EINVAL, "tile patch too large for 16-bit slots");
+  o->KW = kw;
+  o->W2 = kw * kw;
   const int64_t N = sdag.rows;
   const int ntiles = o->NT * o->NT;
   const int origin_tile = tile_of(0, oG, TS) * o->NT + tile_of(0, oG, TS);
@@ -362,21 +363,29 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
     for (int64_t r = 0; r < N; ++r) order[next[tile_of_row[r]]++] = (int32_t)r;
   }
   o->pt_row = order;
-  o->pt_slot.assign((size_t)N * o->WS, 0xFFFF);
-  o->pt_val.assign((size_t)N * o->WS, 0.0);
+  o->pt_base.assign((size_t)N, 0);
+  o->pt_val.assign((size_t)N * o->W2, 0.0);
   o->wi_beg.push_back(0);
   for (int tl = 0; tl < ntiles; ++tl) {
     const int j01 = -oG + (tl / o->NT) * TS - h, j02 = -oG + (tl % o->NT) * TS - h;   // patch origin
     for (int64_t i = count[tl]; i < count[tl + 1]; ++i) {
       const int64_t r = order[i];
-      int s = 0;
-      for (int64_t e = sdag.rowptr[r]; e < sdag.rowptr[r + 1]; ++e, ++s) {
-        const int j1 = centred(sdag.col[e] / G, G, oG), j2 = centred(sdag.col[e] % G, G, oG);
-        const int p1 = j1 - j01, p2 = j2 - j02;
-        if (p1 < 0 || p1 >= o->PS || p2 < 0 || p2 >= o->PS)
-          return fail(TOMO_EINVAL, "internal: tap outside its tile patch (row %lld)", (long long)r);
-        o->pt_slot[(size_t)i * o->WS + s] = (uint16_t)(p1 * o->PS + p2);
-        o->pt_val[(size_t)i * o->WS + s] = sdag.val[e];
+      const int32_t c1 = centres[(size_t)r * 2], c2 = centres[(size_t)r * 2 + 1];
+      if (c1 == INT32_MIN) {
+        if (sdag.rowptr[r + 1] != sdag.rowptr[r])
+          return fail(TOMO_EINVAL, "internal: row %lld has entries but no window", (long long)r);
+        continue;   // base 0, all values zero
+      }
+      const int b1 = c1 - h - j01, b2 = c2 - h - j02;
+      if (b1 < 0 || b2 < 0 || b1 + kw > o->PS || b2 + kw > o->PS)
+        return fail(TOMO_EINVAL, "internal: window outside its tile patch (row %lld)", (long long)r);
+      o->pt_base[(size_t)i] = b1 * o->PS + b2;
+      for (int64_t e = sdag.rowptr[r]; e < sdag.rowptr[r + 1]; ++e) {
+        const int s1 = centred(sdag.col[e] / G, G, oG) - c1 + h;
+        const int s2 = centred(sdag.col[e] % G, G, oG) - c2 + h;
+        if (s1 < 0 || s1 >= kw || s2 < 0 || s2 >= kw)
+          return fail(TOMO_EINVAL, "internal: tap outside its window (row %lld)", (long long)r);
+        o->pt_val[(size_t)i * o->W2 + s1 * kw + s2] = sdag.val[e];
       }
     }
     for (int64_t b = count[tl]; b < count[tl + 1]; b += t.tile_points) {
@@ -387,73 +396,91 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
   return TOMO_OK;
 }
 
-tomo_status build_adj_tiles(const Geom& g, const HostCSR& s, const Tuning& t, HostAdjTiles* o) {
-  *o = HostAdjTiles();
-  const int G = g.G, oG = G / 2, TS = t.tile;
+tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
+                          const Tuning& t, HostAdjWin* o) {
+  *o = HostAdjWin();
+  const int G = g.G, oG = G / 2, TS = t.tile, h = g.h, kw = g.kw;
   o->TS = TS;
+  o->RS = TS + 2 * h;
   o->NT = (G + TS - 1) / TS;
-  const int R = TS * TS;
-  std::vector<int32_t> cols;
-  std::vector<int64_t> rows(R);
-  o->ch_pt_beg.push_back(0);
-  for (int t1 = 0; t1 < o->NT; ++t1) {
-    for (int t2 = 0; t2 < o->NT; ++t2) {
-      const int tl = t1 * o->NT + t2;
-      // the tile's output rows (library row index, -1 outside the grid)
-      cols.clear();
-      for (int a = 0; a < TS; ++a)
-        for (int b = 0; b < TS; ++b) {
-          const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
-          int64_t m = -1;
-          if (j1 <= G - 1 - oG && j2 <= G - 1 - oG)
-            m = (int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G);
-          rows[a * TS + b] = m;
-          if (m >= 0)
-            for (int64_t e = s.rowptr[m]; e < s.rowptr[m + 1]; ++e) cols.push_back(s.col[e]);
-        }
-      std::sort(cols.begin(), cols.end());
-      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-      const int nch = (int)((cols.size() + t.tile_points - 1) / t.tile_points);
-      const int first_chunk = (int)o->ch_pt_beg.size() - 1;
-      for (int c = 0; c < nch; ++c) {
-        const size_t q0 = (size_t)c * t.tile_points;
-        const size_t q1 = std::min(cols.size(), q0 + (size_t)t.tile_points);
-        o->ch_pts.insert(o->ch_pts.end(), cols.begin() + q0, cols.begin() + q1);
-        o->ch_pt_beg.push_back((int32_t)o->ch_pts.size());
-        const int32_t lo = cols[q0], hi = cols[q1 - 1];
-        for (int rr = 0; rr < R; ++rr) {
-          o->ch_row_off.push_back((int32_t)o->en_slot.size());
-          const int64_t m = rows[rr];
-          if (m < 0) continue;
-          // the row's columns are sorted, so its entries inside [lo, hi] are one run
-          const int32_t* cb = s.col.data() + s.rowptr[m];
-          const int32_t* ce = s.col.data() + s.rowptr[m + 1];
-          const int32_t* it = std::lower_bound(cb, ce, lo);
-          for (; it != ce && *it <= hi; ++it) {
-            const size_t q = (size_t)(std::lower_bound(cols.begin() + q0, cols.begin() + q1, *it) - cols.begin());
-            o->en_slot.push_back((uint16_t)(q - q0));
-            o->en_val.push_back(s.val[s.rowptr[m] + (it - cb)]);
-          }
-        }
-        o->ch_row_off.push_back((int32_t)o->en_slot.size());
-        o->emax = std::max(o->emax, (int)(o->en_slot.size() - o->ch_row_off[o->ch_row_off.size() - R - 1]));
-      }
-      // work items: runs of <= kch chunks; a tile needing several writes partial sums
-      const int nwi = std::max(1, (nch + t.tile_chunks - 1) / t.tile_chunks);
-      if (nwi > 1) {
-        o->red_tile.push_back(tl);
-        o->red_beg.push_back((int32_t)o->n_pslots);
-        o->red_cnt.push_back(nwi);
-      }
-      for (int w = 0; w < nwi; ++w) {
-        o->wi_tile.push_back(tl);
-        o->wi_chunk_beg.push_back(first_chunk + std::min(nch, w * t.tile_chunks));
-        o->wi_chunk_end.push_back(first_chunk + std::min(nch, (w + 1) * t.tile_chunks));
-        o->wi_out.push_back(nwi > 1 ? (int32_t)(o->n_pslots++) : -1);
-      }
+  o->KW = kw;
+  o->W2 = kw * kw;
+  o->QMAX = t.adj_tile_points;
+  const int RS = o->RS, NT = o->NT, W2 = o->W2;
+  const int64_t N = sdag.rows;
+  // window-ordered values of every polar row, and the rows bucketed by centre cell on the grid
+  // extended by h (+1 above: a centre may round onto the grid's upper edge)
+  const int E = G + 2 * h + 1;
+  std::vector<double> wv((size_t)N * W2, 0.0);
+  std::vector<int64_t> cell_ptr((size_t)E * E + 1, 0);
+  auto ext = [&](int32_t c) { return (int64_t)c + oG + h; };
+  for (int64_t r = 0; r < N; ++r) {
+    const int32_t c1 = centres[(size_t)r * 2], c2 = centres[(size_t)r * 2 + 1];
+    if (c1 == INT32_MIN) continue;
+    if (ext(c1) < 0 || ext(c1) >= E || ext(c2) < 0 || ext(c2) >= E)
+      return fail(TOMO_EINVAL, "internal: window centre off the extended grid (row %lld)", (long long)r);
+    for (int64_t e = sdag.rowptr[r]; e < sdag.rowptr[r + 1]; ++e) {
+      const int s1 = centred(sdag.col[e] / G, G, oG) - c1 + h;
+      const int s2 = centred(sdag.col[e] % G, G, oG) - c2 + h;
+      if (s1 < 0 || s1 >= kw || s2 < 0 || s2 >= kw)
+        return fail(TOMO_EINVAL, "internal: tap outside its window (row %lld)", (long long)r);
+      wv[(size_t)r * W2 + s1 * kw + s2] = sdag.val[e];
+    }
+    cell_ptr[(size_t)(ext(c1) * E + ext(c2)) + 1]++;
+  }
+  for (size_t i = 1; i < cell_ptr.size(); ++i) cell_ptr[i] += cell_ptr[i - 1];
+  std::vector<int32_t> cell_rows((size_t)cell_ptr.back());
+  {
+    std::vector<int64_t> next(cell_ptr.begin(), cell_ptr.end() - 1);
+    for (int64_t r = 0; r < N; ++r) {
+      const int32_t c1 = centres[(size_t)r * 2], c2 = centres[(size_t)r * 2 + 1];
+      if (c1 != INT32_MIN) cell_rows[(size_t)next[(size_t)(ext(c1) * E + ext(c2))]++] = (int32_t)r;
     }
   }
-  if (o->en_slot.size() >= (size_t)INT32_MAX) return fail(TOMO_EINVAL, "tile layout too large");
+  o->dense_cell.assign((size_t)G * G, 0);
+  o->wi_q.push_back(0);
+  for (int t1 = 0; t1 < NT; ++t1)
+    for (int t2 = 0; t2 < NT; ++t2) {
+      // region cell (a, b) is extended-grid cell (t1*TS + a, t2*TS + b)
+      auto bucket = [&](int a, int b, int64_t* beg, int64_t* end) {
+        const int64_t e1 = (int64_t)t1 * TS + a, e2 = (int64_t)t2 * TS + b;
+        if (e1 >= E || e2 >= E) { *beg = *end = 0; return; }
+        *beg = cell_ptr[(size_t)(e1 * E + e2)];
+        *end = cell_ptr[(size_t)(e1 * E + e2) + 1];
+      };
+      int64_t nq = 0;
+      for (int a = 0; a < RS; ++a)
+        for (int b = 0; b < RS; ++b) {
+          int64_t bb, be;
+          bucket(a, b, &bb, &be);
+          nq += be - bb;
+        }
+      if (nq > o->QMAX) {
+        for (int a = 0; a < TS; ++a)
+          for (int b = 0; b < TS; ++b) {
+            const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
+            if (j1 <= G - 1 - oG && j2 <= G - 1 - oG)
+              o->dense_cell[(size_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = 1;
+          }
+        continue;
+      }
+      o->wi_tile.push_back(t1 * NT + t2);
+      int64_t k = 0;
+      for (int a = 0; a < RS; ++a)
+        for (int b = 0; b < RS; ++b) {
+          o->wi_boff.push_back((uint16_t)k);
+          int64_t bb, be;
+          bucket(a, b, &bb, &be);
+          for (int64_t i = bb; i < be; ++i, ++k) {
+            const int32_t r = cell_rows[(size_t)i];
+            o->q_row.push_back(r);
+            o->q_val.insert(o->q_val.end(), wv.begin() + (size_t)r * W2, wv.begin() + (size_t)(r + 1) * W2);
+          }
+        }
+      o->wi_boff.push_back((uint16_t)k);
+      o->wi_q.push_back((int32_t)o->q_row.size());
+    }
+  if (o->q_row.size() >= (size_t)INT32_MAX) return fail(TOMO_EINVAL, "staged adjoint layout too large");
   return TOMO_OK;
 }
 
@@ -490,10 +517,8 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
       }
     worst = std::max(worst, rel(out, yf));
   }
-  {  // row-binned adjoint
-    HostAdj h;
-    build_adj_layout(s, t, &h);
-    std::vector<double> out(M, std::nan(""));
+  // row-binned adjoint kernels over layout h: writes the rows h holds
+  auto replay_rows = [&](const HostAdj& h, std::vector<double>& out) {
     const int64_t ns = (int64_t)h.slice_ptr.size() - 1;
     for (int64_t i = 0; i < ns; ++i) {
       const int len = (h.slice_ptr[i + 1] - h.slice_ptr[i]) / kSliceRows;
@@ -512,6 +537,12 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
       for (int32_t e = h.tail_ptr[i]; e < h.tail_ptr[i + 1]; ++e) acc += h.tail_val[e] * y[h.tail_col[e]];
       out[h.tail_rows[i]] = acc;
     }
+  };
+  {  // row-binned adjoint
+    HostAdj h;
+    build_adj_layout(s, t, &h);
+    std::vector<double> out(M, std::nan(""));
+    replay_rows(h, out);
     worst = std::max(worst, rel(out, xa));
   }
   {  // staged forward
@@ -523,52 +554,46 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
       const int j01 = -oG + (tl / f.NT) * f.TS - g.h, j02 = -oG + (tl % f.NT) * f.TS - g.h;
       for (int32_t i = f.wi_beg[w]; i < f.wi_beg[w + 1]; ++i) {
         double acc = 0;
-        for (int k = 0; k < f.WS; ++k) {
-          const uint16_t sl = f.pt_slot[(size_t)i * f.WS + k];
-          if (sl == 0xFFFF) continue;
-          const int g1 = ((j01 + sl / f.PS) % G + G) % G, g2 = ((j02 + sl % f.PS) % G + G) % G;
-          acc += f.pt_val[(size_t)i * f.WS + k] * x[(int64_t)g1 * G + g2];
-        }
+        for (int s1 = 0; s1 < f.KW; ++s1)
+          for (int s2 = 0; s2 < f.KW; ++s2) {
+            const int sl = f.pt_base[i] + s1 * f.PS + s2;
+            if (sl < 0 || sl >= f.PS * f.PS) return fail(TOMO_EINVAL, "internal: tap slot outside the patch");
+            const int g1 = ((j01 + sl / f.PS) % G + G) % G, g2 = ((j02 + sl % f.PS) % G + G) % G;
+            acc += f.pt_val[(size_t)i * f.W2 + s1 * f.KW + s2] * x[(int64_t)g1 * G + g2];
+          }
         out[f.pt_row[i]] = acc;
       }
     }
     worst = std::max(worst, rel(out, yf));
   }
-  {  // staged adjoint
-    HostAdjTiles a;
-    TOMO_TRY(build_adj_tiles(g, s, t, &a));
-    const int R = a.TS * a.TS;
+  {  // staged adjoint (window form) and the row kernels on its dense cells
+    HostAdjWin a;
+    TOMO_TRY(build_adj_win(g, sdag, centres, t, &a));
+    const int RS = a.RS, h = g.h, kw = a.KW, NBO = RS * RS + 1;
     std::vector<double> out(M, std::nan(""));
-    std::vector<double> part((size_t)a.n_pslots * R, 0.0);
     for (size_t w = 0; w < a.wi_tile.size(); ++w) {
-      std::vector<double> acc(R, 0.0);
-      for (int ch = a.wi_chunk_beg[w]; ch < a.wi_chunk_end[w]; ++ch) {
-        const int32_t* off = a.ch_row_off.data() + (size_t)ch * (R + 1);
-        for (int rr = 0; rr < R; ++rr)
-          for (int32_t e = off[rr]; e < off[rr + 1]; ++e) {
-            if ((int)a.en_slot[e] >= a.ch_pt_beg[ch + 1] - a.ch_pt_beg[ch])
-              return fail(TOMO_EINVAL, "internal: entry slot beyond its chunk");
-            acc[rr] += a.en_val[e] * y[a.ch_pts[a.ch_pt_beg[ch] + a.en_slot[e]]];
-          }
-      }
-      const int tl = a.wi_tile[w];
-      for (int rr = 0; rr < R; ++rr) {
-        if (a.wi_out[w] >= 0) { part[(size_t)a.wi_out[w] * R + rr] = acc[rr]; continue; }
-        const int j1 = -oG + (tl / a.NT) * a.TS + rr / a.TS, j2 = -oG + (tl % a.NT) * a.TS + rr % a.TS;
-        if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
-        out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc[rr];
-      }
+      const int tl = a.wi_tile[w], t1 = tl / a.NT, t2 = tl % a.NT;
+      const int32_t q0 = a.wi_q[w];
+      const uint16_t* bo = a.wi_boff.data() + w * (size_t)NBO;
+      if (a.wi_q[w + 1] - q0 > a.QMAX || bo[NBO - 1] != a.wi_q[w + 1] - q0)
+        return fail(TOMO_EINVAL, "internal: staged tile sample count");
+      for (int m1 = 0; m1 < a.TS; ++m1)
+        for (int m2 = 0; m2 < a.TS; ++m2) {
+          const int j1 = -oG + t1 * a.TS + m1, j2 = -oG + t2 * a.TS + m2;
+          if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
+          double acc = 0;
+          for (int p1 = 0; p1 < kw; ++p1)
+            for (int p2 = 0; p2 < kw; ++p2) {
+              const int b = (m1 + 2 * h - p1) * RS + (m2 + 2 * h - p2);
+              for (int k = bo[b]; k < bo[b + 1]; ++k)
+                acc += a.q_val[(size_t)(q0 + k) * a.W2 + p1 * kw + p2] * y[a.q_row[(size_t)(q0 + k)]];
+            }
+          out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc;
+        }
     }
-    for (size_t i = 0; i < a.red_tile.size(); ++i) {
-      const int tl = a.red_tile[i];
-      for (int rr = 0; rr < R; ++rr) {
-        const int j1 = -oG + (tl / a.NT) * a.TS + rr / a.TS, j2 = -oG + (tl % a.NT) * a.TS + rr % a.TS;
-        if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
-        double acc = 0;
-        for (int k = 0; k < a.red_cnt[i]; ++k) acc += part[(size_t)(a.red_beg[i] + k) * R + rr];
-        out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc;
-      }
-    }
+    HostAdj hd;
+    build_adj_layout(s, t, &hd, &a.dense_cell);
+    replay_rows(hd, out);
     worst = std::max(worst, rel(out, xa));
   }
   *max_rel = worst;   // NaN if some output row was never written

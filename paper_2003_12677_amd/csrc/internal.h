@@ -62,11 +62,12 @@ struct Tuning {
   int sell_sigma = 4096;  // rows are sorted by length within windows of sell_sigma rows
   int medium_max = 128;   // longer rows up to medium_max entries: one wavefront per row
   int chunk = 1024;       // rows above medium_max: chunks of <= chunk entries, one block each
-  int fwd_tiled = 0;      // forward: 1 = LDS-staged Cartesian tiles, 0 = row kernel
-  int adj_tiled = 0;      // adjoint: 1 = LDS-staged polar chunks per output tile, 0 = row kernels
-  int tile = 8;           // Cartesian tile side of the staged kernels (8, 16 or 32)
-  int tile_points = 128;  // forward: samples per block; adjoint: polar rows staged per chunk
-  int tile_chunks = 1;    // adjoint: chunks one block accumulates before writing
+  // staged kernels per value type: bit vt (1 f32, 2 bf16, 4 f16) set = staged, clear = rows
+  int fwd_tiled = 7;      // forward: LDS-staged Cartesian tiles
+  int adj_tiled = 6;      // adjoint: LDS-staged output tiles (+ row kernels on dense cells)
+  int tile = 8;           // Cartesian tile side of the staged kernels (8 or 16)
+  int tile_points = 64;   // forward: samples per block
+  int adj_tile_points = 128;   // adjoint: most samples a staged tile's region may hold
   int normal_tiled = 1;   // normal operator: LDS-staged grid tiles (1) or direct taps (0)
   int sell_xcd_rows = 8192;   // sliced-ELL adjoint: rows per XCD interleave run (0 = contiguous)
   int medium_xcd_rows = 1024; // wave-per-row adjoint: rows per XCD interleave run
@@ -97,31 +98,34 @@ struct HostAdj {
   std::vector<int32_t> chunk_beg, chunk_end, long_chunk_ptr;   // into the tail entries
 };
 
-// Forward, LDS-staged: polar samples grouped by the Cartesian tile (side TS) that holds their
-// window centre; a block stages the tile plus a halo of h = (k_w-1)/2 (patch side PS = TS + 2h)
-// and reads every tap from LDS.  Tap s of sample i is patch slot pt_slot[i*W2 + s] (0xFFFF: none).
+// Forward, LDS-staged, window form: polar samples grouped by the Cartesian tile (side TS) that
+// holds their window centre; a block stages the tile plus a halo of h = (k_w-1)/2 below and h+1
+// above (patch side PS = TS + 2h + 1: a centre rounded onto the grid's upper edge keeps its whole
+// window in the patch) and reads every tap from LDS.  Sample i's k_w x k_w window starts at patch
+// slot pt_base[i]; tap (s1, s2) is slot pt_base[i] + s1*PS + s2 with value pt_val[i*W2 + s1*k_w
+// + s2] (zero for a tap the matrix does not hold).
 struct HostFwdTiles {
-  int TS = 0, PS = 0, NT = 0, W2 = 0, WS = 0;   // WS: tap stride (W2 rounded up to 4)
+  int TS = 0, PS = 0, NT = 0, KW = 0, W2 = 0;
   std::vector<int32_t> wi_tile, wi_beg;    // [n_wi], [n_wi + 1] into the sample list
   std::vector<int32_t> pt_row;             // polar row of each sample
-  std::vector<uint16_t> pt_slot;           // [P][WS]
-  std::vector<double> pt_val;              // [P][WS]
+  std::vector<int32_t> pt_base;            // [P] first window slot in the patch
+  std::vector<double> pt_val;              // [P][W2] window-ordered values
 };
 
-// Adjoint, LDS-staged: for each Cartesian output tile the polar rows its entries reference are
-// staged in chunks of <= qmax rows; a block accumulates up to kch chunks for the tile's TS*TS
-// rows and writes them to X (wi_out = -1) or to partial-sum slot wi_out, later reduced in order.
-struct HostAdjTiles {
-  int TS = 0, NT = 0;
-  std::vector<int32_t> wi_tile, wi_chunk_beg, wi_chunk_end, wi_out;   // [n_wi]
-  std::vector<int32_t> ch_pt_beg;          // [n_chunks + 1] into ch_pts
-  std::vector<int32_t> ch_pts;             // staged polar rows
-  std::vector<int32_t> ch_row_off;         // [n_chunks][TS*TS + 1] into the entries
-  std::vector<uint16_t> en_slot;           // LDS slot (position in the chunk) of each entry
-  std::vector<double> en_val;
-  std::vector<int32_t> red_tile, red_beg, red_cnt;   // tiles summed from partial slots
-  int64_t n_pslots = 0;
-  int emax = 0;                            // most entries in one chunk
+// Adjoint, LDS-staged, window form: a block owns one Cartesian tile (side TS) and stages every
+// polar sample whose window centre lies in the tile's region (the tile grown by h on each side,
+// side RS = TS + 2h), bucketed by centre cell; output cell m sums, over the k_w^2 centre cells
+// m - s (s in [-h, h]^2), the bucket's samples times their window value at position s + h.
+// Tiles whose region holds more than adj_tile_points samples (near the Fourier origin) are
+// "dense": their cells go to the row kernels through a row layout built over those cells only.
+struct HostAdjWin {
+  int TS = 0, RS = 0, NT = 0, KW = 0, W2 = 0, QMAX = 0;
+  std::vector<int32_t> wi_tile;            // [n_wi] staged tiles
+  std::vector<int32_t> wi_q;               // [n_wi + 1] into the tile sample list
+  std::vector<uint16_t> wi_boff;           // [n_wi][RS*RS + 1] bucket offsets from wi_q[w]
+  std::vector<int32_t> q_row;              // polar row of each tile sample
+  std::vector<double> q_val;               // [Q][W2] window-ordered values
+  std::vector<char> dense_cell;            // [M] library cell index -> 1 if in a dense tile
 };
 
 tomo_status resolve_geometry(const tomo_geometry* in, Geom* g);
@@ -129,11 +133,14 @@ double kernel_value(double t, int W, double beta);
 void build_sdag(const Geom& g, HostCSR* sdag, std::vector<int32_t>* centres = nullptr);
 tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
                             const Tuning& t, HostFwdTiles* out);
-tomo_status build_adj_tiles(const Geom& g, const HostCSR& s, const Tuning& t, HostAdjTiles* out);
+tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
+                          const Tuning& t, HostAdjWin* out);
 void transpose_csr(const HostCSR& a, HostCSR* at);
 void build_ell(const HostCSR& a, int W2, HostEll* out);
 tomo_status check_tuning(const Tuning& t);
-void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* out);
+// rows: if non-null, only rows r with (*rows)[r] != 0 are laid out (the others are not written)
+void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* out,
+                      const std::vector<char>* rows = nullptr);
 tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
                           const std::vector<int32_t>& centres, const Tuning& t, double* max_rel);
 void deapod_factors(const Geom& g, std::vector<double>* kd);
@@ -173,20 +180,18 @@ struct DevAdj {
 
 struct DevFwdTiles {
   int64_t n_wi = 0;
-  int TS = 0, PS = 0, NT = 0, WS = 0;
+  int TS = 0, PS = 0, NT = 0, KW = 0;
   int32_t *wi_tile = nullptr, *wi_beg = nullptr, *pt_row = nullptr;
-  uint16_t* pt_slot = nullptr;
+  int32_t* pt_base = nullptr;
   void* val[3] = {nullptr, nullptr, nullptr};
 };
 
-struct DevAdjTiles {
-  int64_t n_wi = 0, n_red = 0, n_pslots = 0;
-  int TS = 0, NT = 0, qmax = 0, emax = 0;
-  int32_t *wi_tile = nullptr, *wi_cb = nullptr, *wi_ce = nullptr, *wi_out = nullptr;
-  int32_t *ch_pt_beg = nullptr, *ch_pts = nullptr, *ch_row_off = nullptr;
-  uint16_t* en_slot = nullptr;
-  void* en_val[3] = {nullptr, nullptr, nullptr};
-  int32_t *red_tile = nullptr, *red_beg = nullptr, *red_cnt = nullptr;
+struct DevAdjWin {
+  int64_t n_wi = 0;               // staged tiles (one block each)
+  int TS = 0, RS = 0, NT = 0, KW = 0, QMAX = 0;
+  int32_t *wi_tile = nullptr, *wi_q = nullptr, *q_row = nullptr;
+  uint16_t* wi_boff = nullptr;
+  void* q_val[3] = {nullptr, nullptr, nullptr};
 };
 
 struct FFTPlans {
@@ -214,6 +219,7 @@ struct tomo_op {
   tomo::HostAdj hadj;             // adjoint layout for the current tuning
   std::vector<double> kd;         // separable deapodisation factors [n]
   int device = -1;
+  int n_cu = 256;                 // compute units of the device (persistent grids)
   uint32_t values = 0;
   int64_t cols_touched = 0, polar_nonempty = 0;
   // device
@@ -234,8 +240,8 @@ struct tomo_op {
   bool adj_ready = false;         // false while (or after a failed) adjoint layout upload
   std::vector<int32_t> centres;   // window centre (j1, j2) of every polar row, host
   tomo::DevFwdTiles ftile;        // LDS-staged forward layout
-  tomo::DevAdjTiles atile;        // LDS-staged adjoint layout
-  float2* tile_partials = nullptr;   // [n_pslots][TS*TS][cmax]
+  tomo::DevAdjWin awin;           // LDS-staged adjoint layout
+  tomo::DevAdj adj_dense;         // row layout of the staged adjoint's dense cells
   bool tiles_ready = false;
   std::map<int, tomo::FFTPlans> plans;   // keyed by channel count C
   tomo::SolverBuffers sb;
@@ -295,6 +301,7 @@ tomo_status launch_adj_tile(const tomo_op* op, const float2* Y, float2* X, int C
 size_t fwd_tile_lds_bytes(const tomo_op* op, int C);
 bool fwd_tile_supported(const tomo_op* op);
 size_t adj_tile_lds_bytes(const tomo_op* op, int C);
+bool adj_tile_supported(const tomo_op* op);
 constexpr size_t kMaxTileLds = 65536;   // staged kernels are used when their LDS fits this
 
 // composite operators on caller buffers

@@ -483,9 +483,8 @@ tomo_status fwd_impl(const tomo_op* op, const void* val, const float2* X, float2
 }
 
 template <int CPL, typename V>
-tomo_status adj_impl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
+tomo_status adj_impl(const tomo_op* op, const DevAdj& d, int vt, const float2* Y, float2* X, int C,
                      const float* dscale, hipStream_t st) {
-  const DevAdj& d = op->adj;
   AdjArgs a;
   a.logT = ilog2((C + CPL - 1) / CPL);
   const int64_t rpb = kBlock >> a.logT;
@@ -550,12 +549,12 @@ tomo_status fwd_cpl(const tomo_op* op, const void* val, const float2* X, float2*
 }
 
 template <typename V>
-tomo_status adj_cpl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
+tomo_status adj_cpl(const tomo_op* op, const DevAdj& d, int vt, const float2* Y, float2* X, int C,
                     const float* dscale, hipStream_t st) {
   switch (pick_cpl(op->tune.adj_cpl, C)) {
-    case 1: return adj_impl<1, V>(op, vt, Y, X, C, dscale, st);
-    case 2: return adj_impl<2, V>(op, vt, Y, X, C, dscale, st);
-    case 4: return adj_impl<4, V>(op, vt, Y, X, C, dscale, st);
+    case 1: return adj_impl<1, V>(op, d, vt, Y, X, C, dscale, st);
+    case 2: return adj_impl<2, V>(op, d, vt, Y, X, C, dscale, st);
+    case 4: return adj_impl<4, V>(op, d, vt, Y, X, C, dscale, st);
     default: return fail(TOMO_EINVAL, "channel count %d not supported", C);
   }
 }
@@ -567,7 +566,7 @@ tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C
   if (vt < 0 || vt > 2 || !op->fwd.val[vt])
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
-  if (op->tune.fwd_tiled && op->tiles_ready && fwd_tile_supported(op) &&
+  if (((op->tune.fwd_tiled >> vt) & 1) && op->tiles_ready && fwd_tile_supported(op) &&
       fwd_tile_lds_bytes(op, C) <= kMaxTileLds)
     return launch_fwd_tile(op, X, Y, C, vt, st);
   switch (vt) {
@@ -583,12 +582,16 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (!op->adj_ready) return fail(TOMO_ESTATE, "adjoint layout unavailable (failed re-tuning)");
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
-  if (op->tune.adj_tiled && op->tiles_ready && adj_tile_lds_bytes(op, C) <= kMaxTileLds)
-    return launch_adj_tile(op, Y, X, C, vt, dscale, st);
+  const DevAdj* rows = &op->adj;
+  if (((op->tune.adj_tiled >> vt) & 1) && op->tiles_ready && adj_tile_supported(op) &&
+      adj_tile_lds_bytes(op, C) <= kMaxTileLds) {
+    TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, st));   // staged tiles
+    rows = &op->adj_dense;                                    // then the dense cells
+  }
   switch (vt) {
-    case TOMO_VAL_F32: return adj_cpl<float>(op, vt, Y, X, C, dscale, st);
-    case TOMO_VAL_BF16: return adj_cpl<bf16_t>(op, vt, Y, X, C, dscale, st);
-    default: return adj_cpl<_Float16>(op, vt, Y, X, C, dscale, st);
+    case TOMO_VAL_F32: return adj_cpl<float>(op, *rows, vt, Y, X, C, dscale, st);
+    case TOMO_VAL_BF16: return adj_cpl<bf16_t>(op, *rows, vt, Y, X, C, dscale, st);
+    default: return adj_cpl<_Float16>(op, *rows, vt, Y, X, C, dscale, st);
   }
 }
 

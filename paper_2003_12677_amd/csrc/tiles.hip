@@ -6,18 +6,21 @@
 // cache resident.  These kernels stage what a block reads in LDS once:
 //
 // forward  Y = S^dagger X: samples are grouped by the Cartesian tile (TS x TS) holding their
-//          window centre; a block copies the tile plus a halo of h = (k_w-1)/2 from X into
-//          LDS (the "patch", PS x PS points x up to 16 complex channels) and evaluates every
-//          sample's taps from LDS.
-// adjoint  X = S diag(D) Y: a block owns one Cartesian tile of output rows; the polar rows its
-//          entries reference are staged in LDS in chunks (scaled by D on the way in), together
-//          with the chunk's entries (LDS slot, value) and per-row offsets, so the accumulation
-//          loop touches only LDS.  Rows near the Fourier origin sum thousands of same-sign
-//          terms and their error reaches every pixel through the DC coefficient, so row sums are
-//          accumulated in float64 and rounded once.  A block accumulates up to tile_chunks
-//          chunks in registers;
-//          tiles with more chunks (near the origin) are split over several blocks whose partial
-//          sums are added in a fixed order by a small reduction kernel (no atomics).
+//          window centre; a block copies the tile plus its halo from X into LDS (the "patch",
+//          PS x PS points x up to 16 complex channels) and the work item's sample records
+//          (output row, first window slot, k_w^2 window-ordered values) with coalesced loads,
+//          then evaluates every sample's k_w x k_w taps from LDS at fixed offsets from its first
+//          slot.  A tap the matrix does not hold has value zero (it multiplies a finite patch
+//          value).  Per sample the block issues no global load of its own: a tile's patch is one
+//          load per point instead of one gather per tap (about 5x fewer line requests).
+// adjoint  X = S diag(D) Y: a block owns one Cartesian tile of output cells and stages, with
+//          coalesced loads, every polar sample whose window centre lies in the tile's region
+//          (the tile grown by h; samples bucketed by centre cell): its row of Y (times D) and
+//          its window values.  Cell m then sums, for each window position p, the samples of
+//          the bucket at centre cell m + h - p times their value at p, reading only LDS, in a
+//          fixed order (no atomics; run-to-run identical).  Regions holding more samples than
+//          the block can stage (near the Fourier origin, where rows reach thousands of
+//          entries) are left to the row kernels, which run on a layout of just those cells.
 //
 // A lane group of 8 lanes owns one row; lane t holds CPL complex channels, so a block covers
 // 8*CPL channels (grid.y walks the channel chunks).
@@ -34,11 +37,19 @@ constexpr int kLanes = 8;
 constexpr int kGroups = kBlock / kLanes;   // 32 lane groups per block
 
 struct bf16_t { uint16_t bits; };
-__device__ __forceinline__ float ldv(const float* v, int64_t e) { return v[e]; }
-__device__ __forceinline__ float ldv(const bf16_t* v, int64_t e) {
-  return __uint_as_float((uint32_t)v[e].bits << 16);
+// Values are loaded raw under the load's predicate and converted afterwards, so that a batch of
+// 16-bit loads is issued back to back instead of each waiting for its own conversion.
+__device__ __forceinline__ uint32_t ldraw(const float* v, int64_t e) { return __float_as_uint(v[e]); }
+__device__ __forceinline__ uint32_t ldraw(const bf16_t* v, int64_t e) { return v[e].bits; }
+__device__ __forceinline__ uint32_t ldraw(const _Float16* v, int64_t e) {
+  return *reinterpret_cast<const uint16_t*>(v + e);
 }
-__device__ __forceinline__ float ldv(const _Float16* v, int64_t e) { return (float)v[e]; }
+__device__ __forceinline__ float cvt(const float*, uint32_t r) { return __uint_as_float(r); }
+__device__ __forceinline__ float cvt(const bf16_t*, uint32_t r) { return __uint_as_float(r << 16); }
+__device__ __forceinline__ float cvt(const _Float16*, uint32_t r) {
+  const uint16_t h = (uint16_t)r;
+  return (float)__builtin_bit_cast(_Float16, h);
+}
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   const int64_t x = bid & 7, local = bid >> 3;
@@ -87,248 +98,212 @@ struct FwdTileArgs {
   const int32_t* wi_tile;
   const int32_t* wi_beg;
   const int32_t* pt_row;
-  const uint16_t* pt_slot;   // [P][WS]
+  const int32_t* pt_base;
   const float2* X;
   float2* Y;
-  int C, G, oG, TS, PS, NT, h, WS, n_wi;
+  int C, G, oG, TS, NT, TP;
 };
 
 // Staging is written as batches of independent loads into registers followed by LDS stores, so
 // a block pays one memory round trip per batch instead of one per element.
 constexpr int kStageBatch = 8;
+constexpr int kMaxTilePoints = 128;
 
-template <int CPL, typename V, int WS, int SPG>
+template <int KW>
+constexpr int window_stride() { return (KW * KW + 3) / 4 * 4; }   // LDS floats per sample
+
+template <int CPL, typename V, int KW, int PS>
 __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __restrict__ val) {
-  extern __shared__ float2 patch[];          // [PS*PS][CH]
-  constexpr int CH = kLanes * CPL;
+  constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
+  constexpr int PP = PS * PS;
+  constexpr int NPL = (PP * kLanes + kBlock - 1) / kBlock;            // patch loads per thread
+  constexpr int NVL = (kMaxTilePoints * W2 + kBlock - 1) / kBlock;    // value loads per thread
+  extern __shared__ float2 smem[];
+  float2* patch = smem;                                                      // [PP][CH]
+  float* s_val = reinterpret_cast<float*>(patch + PP * CH);                  // [TP][WP]
+  int* s_row = reinterpret_cast<int*>(s_val + a.TP * WP);                    // [TP]
+  int* s_base = s_row + a.TP;                                                // [TP]
   const int wi = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int c0 = blockIdx.y * CH;
   const int nch = min(CH, a.C - c0);
   const int tl = a.wi_tile[wi];
-  const int b0 = a.wi_beg[wi], b1 = a.wi_beg[wi + 1];
-  const int g = threadIdx.x / kLanes;
-  const int cl = (threadIdx.x % kLanes) * CPL;
-  // this group's samples: indices, taps and weights, loaded before the patch is complete
-  int row[SPG];
-  uint16_t sl[SPG][WS];
-  float w[SPG][WS];
+  const int b0 = a.wi_beg[wi], ns = a.wi_beg[wi + 1] - b0;
+  const int j01 = -a.oG + (tl / a.NT) * a.TS - H;
+  const int j02 = -a.oG + (tl % a.NT) * a.TS - H;
+  // issue every load of the block (sample records, then the patch) before the first LDS store
+  uint32_t v[NVL];
 #pragma unroll
-  for (int q = 0; q < SPG; ++q) {
-    const int i = b0 + g + q * kGroups;
-    row[q] = -1;
-    if (i < b1) {
-      row[q] = a.pt_row[i];
-#pragma unroll
-      for (int s = 0; s < WS; ++s) {
-        sl[q][s] = a.pt_slot[(int64_t)i * WS + s];
-        w[q][s] = ldv(val, (int64_t)i * WS + s);
-      }
-    }
+  for (int u = 0; u < NVL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    v[u] = 0;
+    if (k < ns * W2) v[u] = ldraw(val, (int64_t)b0 * W2 + k);
   }
-  // stage the tile plus halo
-  const int j01 = -a.oG + (tl / a.NT) * a.TS - a.h;
-  const int j02 = -a.oG + (tl % a.NT) * a.TS - a.h;
-  const int PP = a.PS * a.PS;
-  for (int base = threadIdx.x; base < PP * kLanes; base += kBlock * kStageBatch) {
-    Vec<CPL> v[kStageBatch];
+  int rw = 0, bs = 0;
+  if ((int)threadIdx.x < ns) {
+    rw = a.pt_row[b0 + threadIdx.x];
+    bs = a.pt_base[b0 + threadIdx.x];
+  }
+  constexpr int NB = NPL < kStageBatch ? NPL : kStageBatch;
+  for (int base = 0; base < NPL; base += NB) {
+    Vec<CPL> x[NB];
 #pragma unroll
-    for (int u = 0; u < kStageBatch; ++u) {
-      const int idx = base + u * kBlock;
+    for (int u = 0; u < NB; ++u) {
+      const int idx = threadIdx.x + (base + u) * kBlock;
       const int p = idx / kLanes, l = (idx % kLanes) * CPL;
       if (idx < PP * kLanes && l < nch) {
-        const int g1 = wrap(j01 + p / a.PS, a.G), g2 = wrap(j02 + p % a.PS, a.G);
-        v[u] = vload<CPL>(a.X + ((int64_t)g1 * a.G + g2) * a.C + c0 + l);
+        const int g1 = wrap(j01 + p / PS, a.G), g2 = wrap(j02 + p % PS, a.G);
+        x[u] = vload<CPL>(a.X + ((int64_t)g1 * a.G + g2) * a.C + c0 + l);
       }
     }
 #pragma unroll
-    for (int u = 0; u < kStageBatch; ++u) {
-      const int idx = base + u * kBlock;
+    for (int u = 0; u < NB; ++u) {
+      const int idx = threadIdx.x + (base + u) * kBlock;
       const int p = idx / kLanes, l = (idx % kLanes) * CPL;
-      if (idx < PP * kLanes && l < nch) vstore<CPL>(patch + p * CH + l, v[u]);
+      if (idx < PP * kLanes && l < nch) vstore<CPL>(patch + p * CH + l, x[u]);
     }
   }
-  __syncthreads();
-  if (cl >= nch) return;
 #pragma unroll
-  for (int q = 0; q < SPG; ++q) {
-    if (row[q] < 0) continue;
+  for (int u = 0; u < NVL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    if (k < ns * W2) s_val[(k / W2) * WP + k % W2] = cvt(val, v[u]);
+  }
+  if ((int)threadIdx.x < ns) {
+    s_row[threadIdx.x] = rw;
+    s_base[threadIdx.x] = bs;
+  }
+  __syncthreads();
+  const int g = threadIdx.x / kLanes;
+  const int cl = (threadIdx.x % kLanes) * CPL;
+  if (cl >= nch) return;
+  for (int i = g; i < ns; i += kGroups) {
+    const float2* p = patch + s_base[i] * CH + cl;
+    const float* w = s_val + i * WP;
     Vec<CPL> acc;
     vzero(acc);
 #pragma unroll
-    for (int s = 0; s < WS; ++s) {
-      if (sl[q][s] != 0xFFFF) {
-        const Vec<CPL> x = vload<CPL>(patch + sl[q][s] * CH + cl);
+    for (int s1 = 0; s1 < KW; ++s1)
 #pragma unroll
-        for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += w[q][s] * x.v[k];
+      for (int s2 = 0; s2 < KW; ++s2) {
+        const Vec<CPL> x = vload<CPL>(p + (s1 * PS + s2) * CH);
+        const float ws = w[s1 * KW + s2];
+#pragma unroll
+        for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += ws * x.v[k];
       }
-    }
-    vstore<CPL>(a.Y + (int64_t)row[q] * a.C + c0 + cl, acc);
+    vstore<CPL>(a.Y + (int64_t)s_row[i] * a.C + c0 + cl, acc);
   }
 }
 
 // ------------------------------------------------------------------------------------------
 // adjoint
 // ------------------------------------------------------------------------------------------
-struct AdjTileArgs {
+struct AdjWinArgs {
   const int32_t* wi_tile;
-  const int32_t* wi_cb;       // first chunk
-  const int32_t* wi_ce;       // one past the last chunk
-  const int32_t* wi_out;      // -1: write X, else partial slot
-  const int32_t* ch_pt_beg;
-  const int32_t* ch_pts;
-  const int32_t* ch_row_off;  // [chunk][R + 1]
-  const uint16_t* en_slot;
+  const int32_t* wi_q;
+  const uint16_t* wi_boff;
+  const int32_t* q_row;
   const float2* Y;
   float2* X;
-  float2* partials;           // [slot][R][C]
   const float* dscale;        // per FFT-ordered radial index, or null
-  double inv_nt;
-  int C, G, oG, TS, NT, qmax, emax;
+  int C, G, oG, NT, nt, QMAX;
 };
 
-constexpr int kRowsPerGroup(int R) { return R / kGroups; }
+constexpr int kMaxAdjPoints = 256;
+constexpr int kMaxAdjRows = kMaxAdjPoints * kLanes / kBlock;      // row loads per thread
 
-template <int CPL, typename V, int RPG>
-__global__ __launch_bounds__(kBlock) void k_adj_tile(AdjTileArgs a, const V* __restrict__ val) {
-  constexpr int CH = kLanes * CPL;
+// One block per staged tile, placed by an XCD-aware remap so that neighbouring tiles share an
+// L2.  The block loads its list offsets, then its sample rows, values and bucket offsets, then
+// the rows of Y those samples name.
+template <int CPL, typename V, int KW, int TS, bool SCALE>
+__global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __restrict__ val) {
+  constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
+  constexpr int RS = TS + 2 * H, NBO = RS * RS + 1;
+  constexpr int NBL = (NBO + kBlock - 1) / kBlock;                      // bucket offsets
+  constexpr int NVL = (kMaxAdjPoints * W2 + kBlock - 1) / kBlock;       // value loads
   extern __shared__ float2 smem[];
-  float2* pts = smem;                                               // [qmax][CH]
-  float* sval = reinterpret_cast<float*>(pts + a.qmax * CH);         // [emax]
-  int* soff = reinterpret_cast<int*>(sval + a.emax);                 // [R + 1]
-  uint16_t* sslot = reinterpret_cast<uint16_t*>(soff + kGroups * RPG + 1);   // [emax]
-  const int R = kGroups * RPG;
+  float2* sy = smem;                                                     // [QMAX][CH]
+  float* sv = reinterpret_cast<float*>(sy + a.QMAX * CH);                // [QMAX][WP]
+  int* sb = reinterpret_cast<int*>(sv + a.QMAX * WP);                    // [NBO]
   const int wi = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int c0 = blockIdx.y * CH;
   const int nch = min(CH, a.C - c0);
+  const int tl = a.wi_tile[wi];
+  const int q0 = a.wi_q[wi], nq = a.wi_q[wi + 1] - q0;
+  int bo[NBL];
+#pragma unroll
+  for (int u = 0; u < NBL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    bo[u] = (k < NBO) ? (int)a.wi_boff[(int64_t)wi * NBO + k] : 0;
+  }
+  uint32_t v[NVL];
+#pragma unroll
+  for (int u = 0; u < NVL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    v[u] = 0;
+    if (k < nq * W2) v[u] = ldraw(val, (int64_t)q0 * W2 + k);
+  }
+  int r[kMaxAdjRows];
+#pragma unroll
+  for (int u = 0; u < kMaxAdjRows; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    const int l = (idx % kLanes) * CPL;
+    r[u] = (idx < nq * kLanes && l < nch) ? a.q_row[q0 + idx / kLanes] : -1;
+  }
+  Vec<CPL> y[kMaxAdjRows];
+#pragma unroll
+  for (int u = 0; u < kMaxAdjRows; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    const int l = (idx % kLanes) * CPL;
+    if (r[u] >= 0) y[u] = vload<CPL>(a.Y + (int64_t)r[u] * a.C + c0 + l);
+  }
+  if constexpr (SCALE) {
+#pragma unroll
+    for (int u = 0; u < kMaxAdjRows; ++u)
+      if (r[u] >= 0) {
+        const float d = a.dscale[r[u] / a.nt];
+#pragma unroll
+        for (int k = 0; k < 2 * CPL; ++k) y[u].v[k] *= d;
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < NBL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    if (k < NBO) sb[k] = bo[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NVL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    if (k < nq * W2) sv[(k / W2) * WP + k % W2] = cvt(val, v[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kMaxAdjRows; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    if (r[u] >= 0) vstore<CPL>(sy + (idx / kLanes) * CH + (idx % kLanes) * CPL, y[u]);
+  }
+  __syncthreads();
   const int g = threadIdx.x / kLanes;
   const int cl = (threadIdx.x % kLanes) * CPL;
-  const bool active = cl < nch;
-  double acc[RPG][2 * CPL];
-#pragma unroll
-  for (int r = 0; r < RPG; ++r)
-#pragma unroll
-    for (int c = 0; c < 2 * CPL; ++c) acc[r][c] = 0.0;
-  for (int ch = a.wi_cb[wi]; ch < a.wi_ce[wi]; ++ch) {
-    // stage the chunk: polar rows (times D), entries, row offsets; every phase issues a batch
-    // of independent loads before storing to LDS
-    const int q0 = a.ch_pt_beg[ch], nq = a.ch_pt_beg[ch + 1] - q0;
-    const int* off = a.ch_row_off + (int64_t)ch * (R + 1);
-    const int e0 = off[0], ne = off[R] - e0;
-    for (int base = threadIdx.x; base < nq * kLanes; base += kBlock * kStageBatch) {
-      int pcol[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int idx = base + u * kBlock;
-        pcol[u] = (idx < nq * kLanes) ? a.ch_pts[q0 + idx / kLanes] : -1;
-      }
-      Vec<CPL> v[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int l = ((base + u * kBlock) % kLanes) * CPL;
-        if (pcol[u] >= 0 && l < nch) v[u] = vload<CPL>(a.Y + (int64_t)pcol[u] * a.C + c0 + l);
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int idx = base + u * kBlock;
-        const int l = (idx % kLanes) * CPL;
-        if (pcol[u] < 0 || l >= nch) continue;
-        if (a.dscale) {
-          const float d = a.dscale[(int)(((double)pcol[u] + 0.5) * a.inv_nt)];
-#pragma unroll
-          for (int k = 0; k < 2 * CPL; ++k) v[u].v[k] *= d;
-        }
-        vstore<CPL>(pts + (idx / kLanes) * CH + l, v[u]);
-      }
-    }
-    for (int i = threadIdx.x; i <= R; i += kBlock) soff[i] = off[i] - e0;
-    for (int base = threadIdx.x; base < ne; base += kBlock * kStageBatch) {
-      uint16_t ts[kStageBatch];
-      float tv[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = base + u * kBlock;
-        if (i < ne) {
-          ts[u] = a.en_slot[e0 + i];
-          tv[u] = ldv(val, (int64_t)e0 + i);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = base + u * kBlock;
-        if (i < ne) {
-          sslot[i] = ts[u];
-          sval[i] = tv[u];
-        }
-      }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int r = 0; r < RPG; ++r) {
-        const int rr = g + r * kGroups;
-        const int b = soff[rr], e = soff[rr + 1];
-        for (int k = b; k < e; ++k) {
-          const Vec<CPL> y = vload<CPL>(pts + sslot[k] * CH + cl);
-          const float w = sval[k];
-#pragma unroll
-          for (int c = 0; c < 2 * CPL; ++c) acc[r][c] += (double)(w * y.v[c]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (!active) return;
-  const int tl = a.wi_tile[wi];
-  const int t1 = tl / a.NT, t2 = tl % a.NT;
-  const int out = a.wi_out[wi];
-#pragma unroll
-  for (int r = 0; r < RPG; ++r) {
-    const int rr = g + r * kGroups;
-    Vec<CPL> o;
-#pragma unroll
-    for (int c = 0; c < 2 * CPL; ++c) o.v[c] = (float)acc[r][c];
-    if (out >= 0) {
-      vstore<CPL>(a.partials + ((int64_t)out * R + rr) * a.C + c0 + cl, o);
-    } else {
-      const int j1 = -a.oG + t1 * a.TS + rr / a.TS, j2 = -a.oG + t2 * a.TS + rr % a.TS;
-      if (j1 > a.G - 1 - a.oG || j2 > a.G - 1 - a.oG) continue;   // outside the grid
-      const int64_t m = (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G);
-      vstore<CPL>(a.X + m * a.C + c0 + cl, o);
-    }
-  }
-}
-
-// tiles split over several blocks: X rows = sum of the blocks' partial sums, in block order
-template <int CPL>
-__global__ __launch_bounds__(kBlock) void k_adj_tile_reduce(const int32_t* __restrict__ red_tile,
-                                                            const int32_t* __restrict__ red_beg,
-                                                            const int32_t* __restrict__ red_cnt,
-                                                            const float2* __restrict__ partials,
-                                                            float2* __restrict__ X, int C, int G,
-                                                            int oG, int TS, int NT) {
-  constexpr int CH = kLanes * CPL;
-  const int R = TS * TS;
-  const int i = blockIdx.x;
-  const int c0 = blockIdx.y * CH;
-  const int nch = min(CH, C - c0);
-  const int tl = red_tile[i], t1 = tl / NT, t2 = tl % NT;
-  const int cl = (threadIdx.x % kLanes) * CPL;
   if (cl >= nch) return;
-  for (int rr = threadIdx.x / kLanes; rr < R; rr += kGroups) {
-    const int j1 = -oG + t1 * TS + rr / TS, j2 = -oG + t2 * TS + rr % TS;
-    if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
-    double acc[2 * CPL];
+  const int jb1 = -a.oG + (tl / a.NT) * TS, jb2 = -a.oG + (tl % a.NT) * TS;
+  for (int c = g; c < TS * TS; c += kGroups) {
+    const int m1 = c / TS, m2 = c % TS;
+    const int j1 = jb1 + m1, j2 = jb2 + m2;
+    if (j1 > a.G - 1 - a.oG || j2 > a.G - 1 - a.oG) continue;   // past the grid's end
+    Vec<CPL> acc;
+    vzero(acc);
 #pragma unroll
-    for (int k = 0; k < 2 * CPL; ++k) acc[k] = 0.0;
-    for (int s = 0; s < red_cnt[i]; ++s) {
-      const Vec<CPL> p = vload<CPL>(partials + ((int64_t)(red_beg[i] + s) * R + rr) * C + c0 + cl);
+    for (int p1 = 0; p1 < KW; ++p1)
 #pragma unroll
-      for (int k = 0; k < 2 * CPL; ++k) acc[k] += (double)p.v[k];
-    }
-    Vec<CPL> o;
+      for (int p2 = 0; p2 < KW; ++p2) {
+        const int b = (m1 + 2 * H - p1) * RS + (m2 + 2 * H - p2);
+        const int e = sb[b + 1];
+        for (int k = sb[b]; k < e; ++k) {
+          const float w = sv[k * WP + p1 * KW + p2];
+          const Vec<CPL> x = vload<CPL>(sy + k * CH + cl);
 #pragma unroll
-    for (int k = 0; k < 2 * CPL; ++k) o.v[k] = (float)acc[k];
-    vstore<CPL>(X + ((int64_t)wrap(j1, G) * G + wrap(j2, G)) * C + c0 + cl, o);
+          for (int q = 0; q < 2 * CPL; ++q) acc.v[q] += w * x.v[q];
+        }
+      }
+    vstore<CPL>(a.X + ((int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G)) * a.C + c0 + cl, acc);
   }
 }
 
@@ -337,74 +312,77 @@ tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y,
                           hipStream_t st) {
   const DevFwdTiles& d = op->ftile;
   constexpr int CH = kLanes * CPL;
-  FwdTileArgs a{d.wi_tile, d.wi_beg, d.pt_row, d.pt_slot, X, Y,
-                C, op->g.G, op->g.G / 2, d.TS, d.PS, d.NT, op->g.h, d.WS, (int)d.n_wi};
-  const size_t lds = (size_t)d.PS * d.PS * CH * sizeof(float2);
+  FwdTileArgs a{d.wi_tile, d.wi_beg, d.pt_row, d.pt_base, X, Y,
+                C, op->g.G, op->g.G / 2, d.TS, d.NT, op->tune.tile_points};
+  const size_t lds = fwd_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
   const V* v = (const V*)d.val[vt];
-  const int spg = (op->tune.tile_points + kGroups - 1) / kGroups;   // samples per lane group
-#define TOMO_FWD_TILE(WS_, SPG_)                                                                  \
-  if (d.WS == WS_ && spg <= SPG_) {                                                             \
-    hipLaunchKernelGGL((k_fwd_tile<CPL, V, WS_, SPG_>), grid, dim3(kBlock), lds, st, a, v);     \
+#define TOMO_FWD_TILE(KW_, TS_)                                                                  \
+  if (d.KW == KW_ && d.TS == TS_) {                                                             \
+    constexpr int PS_ = TS_ + 2 * (KW_ / 2) + 1;                                                \
+    hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_>), grid, dim3(kBlock), lds, st, a, v);     \
     TOMO_HIP(hipGetLastError());                                                                \
     return TOMO_OK;                                                                             \
   }
-  TOMO_FWD_TILE(12, 1) TOMO_FWD_TILE(12, 2) TOMO_FWD_TILE(12, 4)
-  TOMO_FWD_TILE(28, 1) TOMO_FWD_TILE(28, 2)
+  TOMO_FWD_TILE(3, 8) TOMO_FWD_TILE(3, 16) TOMO_FWD_TILE(5, 8) TOMO_FWD_TILE(5, 16)
 #undef TOMO_FWD_TILE
-  return fail(TOMO_EUNSUPPORTED, "staged forward kernel has no variant for %d taps, %d samples",
-              d.WS, op->tune.tile_points);
-  TOMO_HIP(hipGetLastError());
-  return TOMO_OK;
+  return fail(TOMO_EUNSUPPORTED, "staged forward kernel has no variant for k_w %d, tile %d", d.KW,
+              d.TS);
 }
 
 template <int CPL, typename V>
 tomo_status adj_tile_impl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
                           const float* dscale, hipStream_t st) {
-  const DevAdjTiles& d = op->atile;
+  const DevAdjWin& d = op->awin;
+  if (d.n_wi == 0) return TOMO_OK;
   constexpr int CH = kLanes * CPL;
-  AdjTileArgs a{d.wi_tile, d.wi_cb, d.wi_ce, d.wi_out, d.ch_pt_beg, d.ch_pts, d.ch_row_off,
-                d.en_slot, Y, X, op->tile_partials, dscale, 1.0 / (double)op->g.nt,
-                C, op->g.G, op->g.G / 2, d.TS, d.NT, d.qmax, d.emax};
-  const int R = d.TS * d.TS;
-  const size_t lds = (size_t)d.qmax * CH * sizeof(float2) + (size_t)d.emax * sizeof(float) +
-                     (size_t)(R + 1) * sizeof(int) + (size_t)d.emax * sizeof(uint16_t);
+  AdjWinArgs a{d.wi_tile, d.wi_q, d.wi_boff, d.q_row, Y, X, dscale,
+               C, op->g.G, op->g.G / 2, d.NT, op->g.nt, d.QMAX};
+  const size_t lds = adj_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
-  const V* v = (const V*)d.en_val[vt];
-  switch (R / kGroups) {
-    case 2: hipLaunchKernelGGL((k_adj_tile<CPL, V, 2>), grid, dim3(kBlock), lds, st, a, v); break;
-    case 8: hipLaunchKernelGGL((k_adj_tile<CPL, V, 8>), grid, dim3(kBlock), lds, st, a, v); break;
-    case 32: hipLaunchKernelGGL((k_adj_tile<CPL, V, 32>), grid, dim3(kBlock), lds, st, a, v); break;
-    default: return fail(TOMO_EUNSUPPORTED, "staged adjoint kernel has no variant for tile %d", d.TS);
+  const V* v = (const V*)d.q_val[vt];
+#define TOMO_ADJ_WIN(KW_, TS_)                                                                   \
+  if (d.KW == KW_ && d.TS == TS_) {                                                             \
+    if (dscale)                                                                                 \
+      hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, true>), grid, dim3(kBlock), lds, st, a, v); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, false>), grid, dim3(kBlock), lds, st, a, v); \
+    TOMO_HIP(hipGetLastError());                                                                \
+    return TOMO_OK;                                                                             \
   }
-  TOMO_HIP(hipGetLastError());
-  if (d.n_red > 0) {
-    hipLaunchKernelGGL((k_adj_tile_reduce<CPL>), dim3((unsigned)d.n_red, grid.y), dim3(kBlock), 0,
-                       st, d.red_tile, d.red_beg, d.red_cnt, op->tile_partials, X, C, op->g.G,
-                       op->g.G / 2, d.TS, d.NT);
-    TOMO_HIP(hipGetLastError());
-  }
-  return TOMO_OK;
+  TOMO_ADJ_WIN(3, 8) TOMO_ADJ_WIN(3, 16) TOMO_ADJ_WIN(5, 8) TOMO_ADJ_WIN(5, 16)
+#undef TOMO_ADJ_WIN
+  return fail(TOMO_EUNSUPPORTED, "staged adjoint kernel has no variant for k_w %d, tile %d", d.KW,
+              d.TS);
 }
 
 }  // namespace
 
 bool fwd_tile_supported(const tomo_op* op) {
-  const int spg = (op->tune.tile_points + kGroups - 1) / kGroups;
-  return (op->ftile.WS == 12 && spg <= 4) || (op->ftile.WS == 28 && spg <= 2);
+  const DevFwdTiles& d = op->ftile;
+  return (d.KW == 3 || d.KW == 5) && (d.TS == 8 || d.TS == 16) &&
+         op->tune.tile_points <= kMaxTilePoints;
 }
 
 size_t fwd_tile_lds_bytes(const tomo_op* op, int C) {
   const int cpl = (C % 2 == 0) ? 2 : 1;
-  return (size_t)op->ftile.PS * op->ftile.PS * kLanes * cpl * sizeof(float2);
+  const DevFwdTiles& d = op->ftile;
+  const int wp = (d.KW * d.KW + 3) / 4 * 4;
+  return (size_t)d.PS * d.PS * kLanes * cpl * sizeof(float2) +
+         (size_t)op->tune.tile_points * (wp * sizeof(float) + 2 * sizeof(int));
+}
+
+bool adj_tile_supported(const tomo_op* op) {
+  const DevAdjWin& d = op->awin;
+  return (d.KW == 3 || d.KW == 5) && (d.TS == 8 || d.TS == 16) && d.QMAX <= kMaxAdjPoints;
 }
 
 size_t adj_tile_lds_bytes(const tomo_op* op, int C) {
   const int cpl = (C % 2 == 0) ? 2 : 1;
-  const DevAdjTiles& d = op->atile;
-  const int R = d.TS * d.TS;
-  return (size_t)d.qmax * kLanes * cpl * sizeof(float2) + (size_t)d.emax * sizeof(float) +
-         (size_t)(R + 1) * sizeof(int) + (size_t)d.emax * sizeof(uint16_t);
+  const DevAdjWin& d = op->awin;
+  const int wp = (d.KW * d.KW + 3) / 4 * 4;
+  return (size_t)d.QMAX * (kLanes * cpl * sizeof(float2) + wp * sizeof(float)) +
+         (size_t)(d.RS * d.RS + 1) * sizeof(int);
 }
 
 tomo_status launch_fwd_tile(const tomo_op* op, const float2* X, float2* Y, int C, int vt,

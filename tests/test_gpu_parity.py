@@ -233,9 +233,11 @@ TUNINGS = [
     dict(ROW, adj_sell_max=0, adj_medium_max=0, adj_chunk=8),     # every row chunked
     dict(ROW, adj_sell_max=1024, adj_medium_max=1024),            # every row in sliced ELL
     dict(ROW, adj_sell_max=4, adj_medium_max=16, adj_chunk=24, adj_sell_sigma=1),
-    dict(tile=8, tile_points=32, tile_chunks=1),                  # staged, many split tiles
-    dict(tile=32, tile_points=64, tile_chunks=2),
-    dict(fwd_tiled=1, adj_tiled=0),
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, tile_points=32, adj_tile_points=32),   # many dense tiles
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, tile_points=64, adj_tile_points=128),
+    dict(fwd_tiled=7, adj_tiled=7, tile=16, tile_points=128, adj_tile_points=256),
+    dict(fwd_tiled=2, adj_tiled=1),                                  # staged for one value type
+    dict(fwd_tiled=0, adj_tiled=7, adj_sell_max=4, adj_medium_max=16, adj_chunk=24),
     dict(ROW, adj_sell_xcd_rows=64, adj_medium_xcd_rows=8),       # short XCD interleave runs
     dict(ROW, adj_sell_xcd_rows=0, adj_medium_xcd_rows=0),        # one contiguous range per XCD
     dict(ROW, fwd_rows_per_group=2),                              # pipelined forward
@@ -244,7 +246,7 @@ TUNINGS = [
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: "_".join(f"{k}{v}" for k, v in t.items()))
-@pytest.mark.parametrize("batch", [7, 16, 32])
+@pytest.mark.parametrize("batch", [5, 7, 16, 32])
 def test_slice_spmm_tunings(tomo, tuning, batch):
     """Every kernel layout the tuning space allows gives the oracle's CSR products."""
     n, nt, npb = 64, 90, 91
@@ -258,6 +260,8 @@ def test_slice_spmm_tunings(tomo, tuning, batch):
     Xo = np.empty((g.G * g.G, C), dtype=np.complex128)
     Xo[cm] = Xc[..., 0] + 1j * Xc[..., 1]
     assert rel_l2(complex_channels(op.slice_fwd(_dev(Xc), batch)), (ref.S_dag @ Xo)[pm]) < 1e-6
+    lo_dag = round_values(ref.S_dag, "bf16")
+    assert rel_l2(complex_channels(op.slice_fwd(_dev(Xc), batch, values="bf16")), (lo_dag @ Xo)[pm]) < 1e-6
     Yc = _rand((g.L * nt, C, 2), 600 + batch)
     Yo = np.empty((g.L * nt, C), dtype=np.complex128)
     Yo[pm] = Yc[..., 0] + 1j * Yc[..., 1]
@@ -266,4 +270,28 @@ def test_slice_spmm_tunings(tomo, tuning, batch):
     assert torch.equal(op.slice_adj(_dev(Yc), batch), Xa)
     lo = round_values(ref.S, "bf16")
     assert rel_l2(complex_channels(op.slice_adj(_dev(Yc), batch, values="bf16")), (lo @ Yo)[cm]) < 1e-6
+    op.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=_ids)
+@pytest.mark.parametrize("tile", [8, 16])
+def test_staged_kernels_on_every_geometry(tomo, shape, tile):
+    """The LDS-staged SpMMs at ragged sizes, padded and off-centre geometries and k_w = 5
+    (windows on the grid's upper edge, tiles past the grid's end)."""
+    n, nt, npb, extra = shape
+    op = _gpu_op(tomo, n, nt, npb, extra, max_batch=6)
+    op.set_tuning(fwd_tiled=7, adj_tiled=7, tile=tile, tile_points=64, adj_tile_points=64)
+    ref = _oracle(n, nt, npb, extra)
+    g = ref.geom
+    cm, pm = cart_map(g), polar_row_map(g)
+    for batch in (1, 6):
+        C = (batch + 1) // 2
+        Xc = _rand((g.G * g.G, C, 2), 800 + batch)
+        Xo = np.empty((g.G * g.G, C), dtype=np.complex128)
+        Xo[cm] = Xc[..., 0] + 1j * Xc[..., 1]
+        assert rel_l2(complex_channels(op.slice_fwd(_dev(Xc), batch)), (ref.S_dag @ Xo)[pm]) < 1e-6
+        Yc = _rand((g.L * nt, C, 2), 900 + batch)
+        Yo = np.empty((g.L * nt, C), dtype=np.complex128)
+        Yo[pm] = Yc[..., 0] + 1j * Yc[..., 1]
+        assert rel_l2(complex_channels(op.slice_adj(_dev(Yc), batch)), (ref.S @ Yo)[cm]) < 1e-6
     op.close()

@@ -155,12 +155,13 @@ def test_host_only_operator_rejects_apply():
 
 
 @pytest.mark.parametrize("d", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6]], ids=lambda d: "_".join(f"{k}{v}" for k, v in d.items()))
-@pytest.mark.parametrize("tuning", [{}, dict(tile=8, tile_points=32, tile_chunks=1),
-                                    dict(tile=32, tile_points=64, tile_chunks=2),
+@pytest.mark.parametrize("tuning", [{}, dict(tile=8, tile_points=32, adj_tile_points=32),
+                                    dict(tile=16, tile_points=64, adj_tile_points=256),
                                     dict(adj_sell_max=4, adj_medium_max=20, adj_chunk=8, adj_sell_sigma=3)])
 def test_kernel_layouts_replay_the_csr_products(d, tuning):
     """Every device layout (fixed-stride forward, sliced-ELL / wave / chunked adjoint, LDS-staged
-    tiles with split tiles and partial sums) replayed on the host equals the CSR products."""
+    window-form tiles, and the row layout of the staged adjoint's dense cells) replayed on the
+    host equals the CSR products."""
     op = tomo.Operator(device=-1, max_batch=2, **d)
     op.set_tuning(**tuning)
     err = op.check_layouts()
