@@ -1,11 +1,13 @@
 // Autotuner for the SpMM layout parameters (the tomo_tuning search space): times the forward and
 // adjoint SpMMs for one batch width and value type on the operator's own work buffers (filled
 // with hashed values), and walks the parameters one at a time (coordinate descent), keeping
-// whichever setting is fastest.  The adjoint's row-bin parameters change the host layout, so
-// each of their candidates costs a re-layout and upload; the search therefore visits a short
-// list per parameter.
+// whichever setting is fastest: staged or row kernels for this value type, tile shapes and
+// capacities, row bins, channels per lane and XCD interleave.  Row-bin and tile parameters
+// change host layouts, so each of their candidates costs a re-layout and upload; the search
+// therefore visits a short list per parameter.
 
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "internal.h"
@@ -67,32 +69,44 @@ tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms,
   double bf = 0, ba = 0;
   TOMO_TRY(measure_fwd(&bf));
   TOMO_TRY(measure_adj(&ba));
+  // which SpMM a parameter affects: the forward, the adjoint, or both (the shared tile side)
+  enum Side { kFwd, kAdj, kBoth };
   struct Param {
-    int Tuning::*field;
+    std::function<int&(Tuning&)> field;
     std::vector<int> values;
-    bool forward;
+    Side side;
   };
+  // the staged flags are value-type masks: the search sets or clears this value type's bit
+  const int bit = 1 << vt;
+  auto mask_values = [&](int cur) { return std::vector<int>{cur & ~bit, cur | bit}; };
   const std::vector<Param> params = {
-      {&Tuning::fwd_rows_per_group, {1, 2, 4}, true},
-      {&Tuning::fwd_cpl, {1, 2, 4}, true},
-      {&Tuning::adj_cpl, {1, 2, 4}, false},
-      {&Tuning::sell_max, {8, 16, 24, 32, 48, 64, 96}, false},
-      {&Tuning::medium_max, {64, 128, 256, 512}, false},
-      {&Tuning::sell_xcd_rows, {0, 1, 2048, 4096, 8192, 16384}, false},
-      {&Tuning::medium_xcd_rows, {1, 256, 1024, 4096}, false},
+      {[](Tuning& t) -> int& { return t.fwd_tiled; }, mask_values(best.fwd_tiled), kFwd},
+      {[](Tuning& t) -> int& { return t.adj_tiled; }, mask_values(best.adj_tiled), kAdj},
+      {[](Tuning& t) -> int& { return t.tile; }, {8, 16}, kBoth},
+      {[](Tuning& t) -> int& { return t.tile_points; }, {32, 64, 96, 128}, kFwd},
+      {[](Tuning& t) -> int& { return t.adj_tile_points; }, {64, 96, 128, 160, 192, 256}, kAdj},
+      {[](Tuning& t) -> int& { return t.fwd_rows_per_group; }, {1, 2, 4}, kFwd},
+      {[](Tuning& t) -> int& { return t.fwd_cpl; }, {1, 2, 4}, kFwd},
+      {[](Tuning& t) -> int& { return t.adj_cpl; }, {1, 2, 4}, kAdj},
+      {[](Tuning& t) -> int& { return t.sell_max; }, {8, 16, 24, 32, 48, 64, 96}, kAdj},
+      {[](Tuning& t) -> int& { return t.medium_max; }, {64, 128, 256, 512}, kAdj},
+      {[](Tuning& t) -> int& { return t.sell_xcd_rows; }, {0, 1, 2048, 4096, 8192, 16384}, kAdj},
+      {[](Tuning& t) -> int& { return t.medium_xcd_rows; }, {1, 256, 1024, 4096}, kAdj},
   };
   for (int round = 0; round < std::max(1, rounds); ++round) {
     for (const Param& p : params) {
       for (int v : p.values) {
         Tuning t = best;
-        t.*(p.field) = v;
-        if (t.*(p.field) == best.*(p.field) || check_tuning(t) != TOMO_OK) continue;
+        p.field(t) = v;
+        if (v == p.field(best) || check_tuning(t) != TOMO_OK) continue;
         TOMO_TRY(apply_tuning(op, t));
-        double ms = 0;
-        TOMO_TRY(p.forward ? measure_fwd(&ms) : measure_adj(&ms));
-        if (ms < (p.forward ? bf : ba)) {
+        double f = bf, a = ba;
+        if (p.side != kAdj) TOMO_TRY(measure_fwd(&f));
+        if (p.side != kFwd) TOMO_TRY(measure_adj(&a));
+        if (f + a < bf + ba) {
           best = t;
-          (p.forward ? bf : ba) = ms;
+          bf = f;
+          ba = a;
         }
       }
       TOMO_TRY(apply_tuning(op, best));

@@ -148,17 +148,22 @@ __device__ __forceinline__ float tv_dt(const float* __restrict__ p1, const float
   return v;
 }
 
+// The split-Bregman kernels walk one n x n slice per blockIdx.y with 32-bit pixel indices (a
+// 64-bit remainder per element made them several times slower than their memory traffic).
+#define TOMO_SB_PIXELS                                                                         \
+  const int64_t base_ = (int64_t)blockIdx.y * n * n;                                           \
+  for (int pix = blockIdx.x * 256 + threadIdx.x; pix < n * n; pix += gridDim.x * 256) {        \
+    const int i1 = pix / n, i2 = pix - i1 * n;                                                 \
+    const int64_t i = base_ + pix;
+
 // rhs = mu ATf + lam D^T (d - b), per slice of n x n (tv buffers: d1, d2, b1, b2)
 __global__ __launch_bounds__(256) void k_sb_rhs(const float* __restrict__ ATf,
                                                 const float* __restrict__ d1,
                                                 const float* __restrict__ d2,
                                                 const float* __restrict__ b1,
                                                 const float* __restrict__ b2,
-                                                float* __restrict__ rhs, float mu, float lam, int n,
-                                                int64_t total) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t pix = i % ((int64_t)n * n);
-    const int i1 = (int)(pix / n), i2 = (int)(pix % n);
+                                                float* __restrict__ rhs, float mu, float lam, int n) {
+  TOMO_SB_PIXELS
     // D^T of (d - b): evaluate the two fields at the three points the operator touches
     const float a = (i1 < n - 1) ? d1[i] - b1[i] : 0.f;
     const float c = (i2 < n - 1) ? d2[i] - b2[i] : 0.f;
@@ -171,10 +176,8 @@ __global__ __launch_bounds__(256) void k_sb_rhs(const float* __restrict__ ATf,
 
 // q = mu q + lam D^T D p   (q holds A^T A p on entry)
 __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, float* __restrict__ q,
-                                                   float mu, float lam, int n, int64_t total) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t pix = i % ((int64_t)n * n);
-    const int i1 = (int)(pix / n), i2 = (int)(pix % n);
+                                                   float mu, float lam, int n) {
+  TOMO_SB_PIXELS
     const float c = p[i];
     // D p at (i1, i2), (i1-1, i2) [component 1] and (i1, i2-1) [component 2]
     const float g1 = (i1 < n - 1) ? p[i + n] - c : 0.f;
@@ -189,11 +192,8 @@ __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, 
 // s = D u + b; d = shrink(s, 1/lam) (isotropic); b = s - d
 __global__ __launch_bounds__(256) void k_sb_shrink(const float* __restrict__ u, float* __restrict__ d1,
                                                    float* __restrict__ d2, float* __restrict__ b1,
-                                                   float* __restrict__ b2, float thr, int n,
-                                                   int64_t total) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t pix = i % ((int64_t)n * n);
-    const int i1 = (int)(pix / n), i2 = (int)(pix % n);
+                                                   float* __restrict__ b2, float thr, int n) {
+  TOMO_SB_PIXELS
     const float c = u[i];
     const float s1 = ((i1 < n - 1) ? u[i + n] - c : 0.f) + b1[i];
     const float s2 = ((i2 < n - 1) ? u[i + 1] - c : 0.f) + b2[i];
@@ -360,7 +360,7 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
   const bool nrm = normal_supported(c.op) == TOMO_OK;
   clear_error();
   const int n = c.op->g.n;
-  const unsigned grid = grid_for(tot);
+  const dim3 grid(grid_for((int64_t)n * n), (unsigned)c.B);
   // q = mu A^T A v + lam D^T D v
   auto apply_M = [&](const float* v, float* q) -> tomo_status {
     if (nrm) {
@@ -369,8 +369,7 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
       TOMO_TRY(apply_project(c.op, v, w.q, c.B, vt, c.st));
       TOMO_TRY(apply_backproject(c.op, w.q, q, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
     }
-    hipLaunchKernelGGL(k_sb_addlap, dim3(grid), dim3(256), 0, c.st, v, q, (float)mu, (float)lam, n,
-                       tot);
+    hipLaunchKernelGGL(k_sb_addlap, grid, dim3(256), 0, c.st, v, q, (float)mu, (float)lam, n);
     TOMO_HIP(hipGetLastError());
     return TOMO_OK;
   };
@@ -378,8 +377,8 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
   TOMO_TRY(launch_fill(x, 0.f, tot, c.st));
   TOMO_TRY(launch_fill(d1, 0.f, 4 * tot, c.st));                              // d1, d2, e1, e2
   for (int k = 0; k < outer; ++k) {
-    hipLaunchKernelGGL(k_sb_rhs, dim3(grid), dim3(256), 0, c.st, ATf, d1, d2, e1, e2, rhs,
-                       (float)mu, (float)lam, n, tot);
+    hipLaunchKernelGGL(k_sb_rhs, grid, dim3(256), 0, c.st, ATf, d1, d2, e1, e2, rhs,
+                       (float)mu, (float)lam, n);
     TOMO_HIP(hipGetLastError());
     // CG on M x = rhs from the current x: r = rhs - M x, p = r
     TOMO_TRY(apply_M(x, w.t));
@@ -400,8 +399,8 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
       TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));
       std::swap(cur, nxt);
     }
-    hipLaunchKernelGGL(k_sb_shrink, dim3(grid), dim3(256), 0, c.st, x, d1, d2, e1, e2,
-                       (float)(1.0 / lam), n, tot);
+    hipLaunchKernelGGL(k_sb_shrink, grid, dim3(256), 0, c.st, x, d1, d2, e1, e2,
+                       (float)(1.0 / lam), n);
     TOMO_HIP(hipGetLastError());
   }
   return TOMO_OK;

@@ -51,12 +51,11 @@ __global__ __launch_bounds__(kTvBlock) void k_tv(const float* __restrict__ x, in
                                                  float weight, float* __restrict__ grad,
                                                  double* __restrict__ partial) {
   const int s = blockIdx.y;
-  const int64_t npix = (int64_t)n * n;
-  const float* u = x + s * npix;
+  const int npix = n * n;                 // 32-bit pixel indices (a 64-bit division per pixel is slow)
+  const float* u = x + (int64_t)s * npix;
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kTvBlock + threadIdx.x; i < npix;
-       i += (int64_t)gridDim.x * kTvBlock) {
-    const int i1 = (int)(i / n), i2 = (int)(i - (int64_t)i1 * n);
+  for (int i = blockIdx.x * kTvBlock + threadIdx.x; i < npix; i += gridDim.x * kTvBlock) {
+    const int i1 = i / n, i2 = i - i1 * n;
     float p1, p2, m;
     tv_p(u, n, i1, i2, eps, p1, p2, m);
     if constexpr (VALUE) acc += (double)m;
@@ -72,7 +71,7 @@ __global__ __launch_bounds__(kTvBlock) void k_tv(const float* __restrict__ x, in
         tv_p(u, n, i1, i2 - 1, eps, q1, q2, mq);
         g += q2;
       }
-      grad[s * npix + i] = weight * g;
+      grad[(int64_t)s * npix + i] = weight * g;
     }
   }
   if constexpr (VALUE) {
