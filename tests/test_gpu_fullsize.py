@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import round_values
 from synth import phantom_stack
 from tests.gpu_util import cart_map, oracle_op, polar_row_map, rel_l2
 
@@ -67,6 +68,47 @@ def test_fullsize_spmm_sampled_rows(big, ref):
     X = Xg2.cpu().numpy()[rows2]
     assert rel_l2(X[..., 0] + 1j * X[..., 1], Xref) < 1e-6
     assert torch.equal(big.slice_adj(torch.from_numpy(Yc).cuda(), B), Xg2)
+
+
+def test_fullsize_bf16_spmm_sampled_rows_in_benchmark_configuration(big, ref):
+    """The launch the benchmark times: batch 32 with bf16 values, i.e. the LDS-staged forward and
+    the staged adjoint with the row kernels on the cells near the origin.  Sampled rows of both
+    products against the oracle's matrices with bf16-rounded values, half of the adjoint's rows
+    drawn from within 400 cells of the origin (where the staged adjoint leaves the dense tiles
+    to the row kernels and borders them), and run-to-run identity."""
+    g = ref.geom
+    C = B // 2
+    tun = big.get_tuning()
+    assert tun["fwd_tiled"] & 2 and tun["adj_tiled"] & 2      # the staged kernels are what runs
+    rng = np.random.default_rng(11)
+    cm, pm = cart_map(g), polar_row_map(g)
+    cm_inv = np.empty_like(cm)
+    cm_inv[cm] = np.arange(cm.size)
+    pm_inv = np.empty_like(pm)
+    pm_inv[pm] = np.arange(pm.size)
+    Xc = rng.standard_normal((g.G * g.G, C, 2), dtype=np.float32)
+    Yg = big.slice_fwd(torch.from_numpy(Xc).cuda(), B, values="bf16")
+    torch.cuda.synchronize()
+    rows = rng.choice(g.n_theta * g.L, 4000, replace=False)
+    Xlib = Xc[..., 0].astype(np.float64) + 1j * Xc[..., 1]
+    Yref = _sampled_rows_ref(round_values(ref.S_dag[pm[rows]], "bf16"), np.arange(rows.size), cm_inv, Xlib)
+    Y = Yg.cpu().numpy()[rows]
+    assert rel_l2(Y[..., 0] + 1j * Y[..., 1], Yref) < 1e-6
+    Yc = rng.standard_normal((g.L * g.n_theta, C, 2), dtype=np.float32)
+    Ylib = Yc[..., 0].astype(np.float64) + 1j * Yc[..., 1]
+    Xg = big.slice_adj(torch.from_numpy(Yc).cuda(), B, values="bf16")
+    torch.cuda.synchronize()
+    # rows near the Fourier origin (the dense tiles) and random rows elsewhere
+    j = np.arange(g.G)
+    jc = np.where(j <= g.G - 1 - g.G // 2, j, j - g.G)
+    rad = np.hypot(jc[:, None], jc[None, :]).reshape(-1)            # library cell order
+    near = np.nonzero(rad < 400)[0]
+    rows2 = np.unique(np.concatenate([rng.choice(near, 3000, replace=False),
+                                      rng.choice(g.G * g.G, 3000, replace=False)]))
+    Xref = _sampled_rows_ref(round_values(ref.S[cm[rows2]], "bf16"), np.arange(rows2.size), pm_inv, Ylib)
+    X = Xg.cpu().numpy()[rows2]
+    assert rel_l2(X[..., 0] + 1j * X[..., 1], Xref) < 1e-6
+    assert torch.equal(big.slice_adj(torch.from_numpy(Yc).cuda(), B, values="bf16"), Xg)
 
 
 def test_fullsize_operators_sampled_slices(big, ref):
