@@ -52,6 +52,45 @@ __global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ pa
   if (threadIdx.x == 0) out[s] = t;
 }
 
+// Fused conjugate-gradient vector steps (each saves a pass over an image-sized vector):
+//   k_cg_step:     x += alpha[s] p;  p = r + beta[s] p       (the deferred solution update)
+//   k_axpy_dot:    r -= alpha[s] q;  partial sums of |r|^2  (residual update and its norm)
+__global__ __launch_bounds__(256) void k_cg_step(float* __restrict__ x, float* __restrict__ p,
+                                                 const float* __restrict__ r,
+                                                 const double* __restrict__ alpha,
+                                                 const double* __restrict__ beta, int64_t len) {
+  const int s = blockIdx.y;
+  const float fa = (float)alpha[s], fb = (float)beta[s];
+  const int64_t base = (int64_t)s * len;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    const float pv = p[base + i];
+    float xv = 1.0f * x[base + i];
+    xv += fa * pv;
+    x[base + i] = xv;
+    float nv = 1.0f * r[base + i];
+    nv += fb * pv;
+    p[base + i] = nv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_axpy_dot(float* __restrict__ r, const float* __restrict__ q,
+                                                  const double* __restrict__ alpha, int64_t len,
+                                                  double* __restrict__ partial) {
+  const int s = blockIdx.y;
+  const float fa = -(float)alpha[s];
+  float* pr = r + (int64_t)s * len;
+  const float* pq = q + (int64_t)s * len;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    float v = 1.0f * pr[i];
+    v += fa * pq[i];
+    pr[i] = v;
+    acc += (double)v * (double)v;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[(int64_t)s * gridDim.x + blockIdx.x] = t;
+}
+
 // out = sa*ca[s]*a + sb*cb[s]*b per slice (null ca / cb mean 1; null b means no second term);
 // out may be a or b (element-wise in place)
 __global__ __launch_bounds__(256) void k_lincomb(float* out, const float* a,
@@ -280,6 +319,22 @@ struct Ctx {
                   double sa, double sb, int64_t len) const {
     return launch_lincomb(out, a, b, ca, cb, sa, sb, len, B, st);
   }
+  // x += alpha p; p = r + beta p   (alpha, beta: this iteration's slots)
+  tomo_status cg_step(float* x, float* p, const float* r, int64_t len) const {
+    hipLaunchKernelGGL(k_cg_step, dim3(grid_for(len), B), dim3(256), 0, st, x, p, r, sc(kAlpha),
+                       sc(kBeta), len);
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
+  // r -= alpha q; slot = |r|^2
+  tomo_status axpy_dot(float* r, const float* q, int64_t len, int slot) const {
+    hipLaunchKernelGGL(k_axpy_dot, dim3(kDotBlocks, B), dim3(256), 0, st, r, q, sc(kAlpha), len,
+                       op->sb.partial);
+    TOMO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.partial, kDotBlocks, sc(slot));
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
 };
 
 // CGLS on A_vt from x (zero, or x's contents when use_x0) with rhs b; x is updated in place.
@@ -301,13 +356,12 @@ tomo_status cgls(const Ctx& c, const float* b, float* x, int vt, int iters, bool
     TOMO_TRY(c.dot(w.q, w.q, c.sino, kDelta));                                // delta = |q|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));      // x += alpha p
     TOMO_TRY(c.lin(w.r, w.r, w.q, nullptr, c.sc(kAlpha), 1.0, -1.0, c.sino));// r -= alpha q
     TOMO_TRY(apply_backproject(c.op, w.r, w.s, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
     TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));                                    // gamma' = |s|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));   // p = s + beta p
+    TOMO_TRY(c.cg_step(x, w.p, w.s, c.img));             // x += alpha p; p = s + beta p
     std::swap(cur, nxt);
   }
   return TOMO_OK;
@@ -332,12 +386,10 @@ tomo_status cgnr(const Ctx& c, const float* b, float* x, int vt, int iters, bool
     TOMO_TRY(c.dot(w.p, w.t, c.img, kDelta));                                 // delta = p.q
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));      // x += alpha p
-    TOMO_TRY(c.lin(w.s, w.s, w.t, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img)); // r -= alpha q
-    TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));                                    // gamma' = |r|^2
+    TOMO_TRY(c.axpy_dot(w.s, w.t, c.img, nxt));          // r -= alpha q; gamma' = |r|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));   // p = r + beta p
+    TOMO_TRY(c.cg_step(x, w.p, w.s, c.img));             // x += alpha p; p = r + beta p
     std::swap(cur, nxt);
   }
   return TOMO_OK;
