@@ -319,7 +319,8 @@ def uneven_leg(torch, tomo):
             eager.append((op, b, Xc, Yp, Xa))
         res["operators"].append({"n": n, "n_angles": nt, "n_det": npb, "slices": count,
                                  "batches": batches, "nnz": op.info.nnz,
-                                 "tuned": {k: tune[k] for k in ("fwd_rows_per_group",
+                                 "tuned": {k: tune[k] for k in ("fwd_tiled", "adj_tiled", "tile",
+                                           "tile_points", "adj_tile_points", "fwd_rows_per_group",
                                            "fwd_channels_per_lane", "adj_channels_per_lane",
                                            "adj_sell_max", "adj_medium_max",
                                            "adj_sell_xcd_rows", "adj_medium_xcd_rows")},
