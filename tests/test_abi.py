@@ -32,3 +32,21 @@ def test_version_and_error_string():
     lib = tomo.load()
     assert tomo.version() == "1.0.0"
     assert isinstance(lib.tomo_last_error(), bytes)
+
+
+def test_documented_tuning_defaults_and_field_order_match_the_library():
+    """The header states the tuning defaults in field order; the binding's struct mirrors the
+    header's field order."""
+    text = open(HEADER).read()
+    m = re.search(r"Defaults \(in field order\):\s*([0-9,\s]+)\.", text)
+    assert m, "defaults line missing"
+    documented = [int(v) for v in m.group(1).replace("\n", " ").split(",")]
+    body = text[text.index("typedef struct {", text.index("Kernel layout parameters")):]
+    body = body[:body.index("} tomo_tuning;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    op = tomo.Operator(8, 6, 9, device=-1)
+    tuning = op.get_tuning()
+    op.close()
+    assert fields == list(tuning.keys())
+    assert documented == list(tuning.values())
