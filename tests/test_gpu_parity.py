@@ -173,11 +173,14 @@ def test_low_precision_values_match_rounded_oracle(tomo, vt):
     y = _rand((4, nt, npb), 12)
     yg = _host(op.project(_dev(x), values=vt))
     xg = _host(op.backproject(_dev(y), values=vt))
+    xf = _host(op.irradon(_dev(y), values=vt, filter="hamming"))
     errs = []
     for s in range(4):
         xs = x[s].astype(np.float32).astype(np.float64)
+        ys = y[s].astype(np.float32).astype(np.float64)
         assert rel_l2(yg[s], lo.project(xs)) < TOL
-        assert rel_l2(xg[s], lo.backproject(y[s].astype(np.float32).astype(np.float64))) < TOL
+        assert rel_l2(xg[s], lo.backproject(ys)) < TOL
+        assert rel_l2(xf[s], lo.irradon(ys, "hamming")) < TOL
         errs.append(rel_l2(yg[s], ref.project(xs)))
     # bf16 keeps 8 significant bits (relative rounding <= 2^-9), f16 11 bits
     assert max(errs) < (4e-3 if vt == "bf16" else 5e-4)
@@ -270,6 +273,12 @@ def test_slice_spmm_tunings(tomo, tuning, batch):
     assert torch.equal(op.slice_adj(_dev(Yc), batch), Xa)
     lo = round_values(ref.S, "bf16")
     assert rel_l2(complex_channels(op.slice_adj(_dev(Yc), batch, values="bf16")), (lo @ Yo)[cm]) < 1e-6
+    # the filter diagonal on the way in (scaled staging in the staged adjoint)
+    from oracle import ramp_filter
+    Dpolar = np.tile(ramp_filter(g, "hamming"), nt)
+    for vt, S_vt in (("f32", ref.S), ("bf16", lo)):
+        Xf = op.slice_adj(_dev(Yc), batch, values=vt, filter="hamming")
+        assert rel_l2(complex_channels(Xf), (S_vt @ (Dpolar[:, None] * Yo))[cm]) < 1e-6, vt
     op.close()
 
 
