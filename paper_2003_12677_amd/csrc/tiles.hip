@@ -22,8 +22,9 @@
 //          the block can stage (near the Fourier origin, where rows reach thousands of
 //          entries) are left to the row kernels, which run on a layout of just those cells.
 //
-// A lane group of 8 lanes owns one row; lane t holds CPL complex channels, so a block covers
-// 8*CPL channels (grid.y walks the channel chunks).
+// A lane group of 8 lanes owns one output row at a time (a polar sample in the forward, a
+// Cartesian cell in the adjoint); lane t holds CPL complex channels, so a block covers 8*CPL
+// channels (grid.y walks the channel chunks).
 
 #include <hip/hip_runtime.h>
 
