@@ -582,12 +582,15 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
           const int j1 = -oG + t1 * a.TS + m1, j2 = -oG + t2 * a.TS + m2;
           if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
           double acc = 0;
-          for (int p1 = 0; p1 < kw; ++p1)
-            for (int p2 = 0; p2 < kw; ++p2) {
-              const int b = (m1 + 2 * h - p1) * RS + (m2 + 2 * h - p2);
-              for (int k = bo[b]; k < bo[b + 1]; ++k)
-                acc += a.q_val[(size_t)(q0 + k) * a.W2 + p1 * kw + p2] * y[a.q_row[(size_t)(q0 + k)]];
+          for (int p1 = 0; p1 < kw; ++p1) {
+            const int rb = (m1 + 2 * h - p1) * RS + m2;   // one run per window row
+            for (int k = bo[rb]; k < bo[rb + kw]; ++k) {
+              int t = 0;
+              while (t + 1 < kw && k >= bo[rb + t + 1]) ++t;
+              const int p2 = 2 * h - t;
+              acc += a.q_val[(size_t)(q0 + k) * a.W2 + p1 * kw + p2] * y[a.q_row[(size_t)(q0 + k)]];
             }
+          }
           out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc;
         }
     }

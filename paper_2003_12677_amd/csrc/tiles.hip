@@ -291,19 +291,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __res
     if (j1 > a.G - 1 - a.oG || j2 > a.G - 1 - a.oG) continue;   // past the grid's end
     Vec<CPL> acc;
     vzero(acc);
+    // for window row p1 the k_w buckets (centre cells (m1 + 2h - p1, m2 + t), t < k_w) are
+    // consecutive in the region, so their samples form one run; bucket t holds window column
+    // p2 = 2h - t.  One loop per window row instead of one per bucket.
 #pragma unroll
-    for (int p1 = 0; p1 < KW; ++p1)
+    for (int p1 = 0; p1 < KW; ++p1) {
+      const int rb = (m1 + 2 * H - p1) * RS + m2;
+      int o[KW + 1];
 #pragma unroll
-      for (int p2 = 0; p2 < KW; ++p2) {
-        const int b = (m1 + 2 * H - p1) * RS + (m2 + 2 * H - p2);
-        const int e = sb[b + 1];
-        for (int k = sb[b]; k < e; ++k) {
-          const float w = sv[k * WP + p1 * KW + p2];
-          const Vec<CPL> x = vload<CPL>(sy + k * CH + cl);
+      for (int t = 0; t <= KW; ++t) o[t] = sb[rb + t];
+      const float* wrow = sv + p1 * KW + 2 * H;
+      for (int k = o[0]; k < o[KW]; ++k) {
+        int t = 0;
 #pragma unroll
-          for (int q = 0; q < 2 * CPL; ++q) acc.v[q] += w * x.v[q];
-        }
+        for (int u = 1; u < KW; ++u) t += (k >= o[u]) ? 1 : 0;
+        const float w = wrow[k * WP - t];
+        const Vec<CPL> x = vload<CPL>(sy + k * CH + cl);
+#pragma unroll
+        for (int q = 0; q < 2 * CPL; ++q) acc.v[q] += w * x.v[q];
       }
+    }
     vstore<CPL>(a.X + ((int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G)) * a.C + c0 + cl, acc);
   }
 }
