@@ -91,6 +91,47 @@ __global__ __launch_bounds__(256) void k_axpy_dot(float* __restrict__ r, const f
   if (threadIdx.x == 0) partial[(int64_t)s * gridDim.x + blockIdx.x] = t;
 }
 
+//   k_dot2_partial: partial sums of a.a and a.b in one pass (the two SIRT-BB step inner products)
+//   k_sirt_update:  x -= alpha[s] g;  g -= alpha[s] h
+__global__ __launch_bounds__(256) void k_dot2_partial(const float* __restrict__ a,
+                                                      const float* __restrict__ b, int64_t len,
+                                                      double* __restrict__ partial_aa,
+                                                      double* __restrict__ partial_ab) {
+  const int s = blockIdx.y;
+  const float* pa = a + (int64_t)s * len;
+  const float* pb = b + (int64_t)s * len;
+  double aa = 0.0, ab = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    const double va = (double)pa[i];
+    aa += va * va;
+    ab += va * (double)pb[i];
+  }
+  const double taa = block_sum(aa);
+  __syncthreads();   // block_sum's shared scratch is reused
+  const double tab = block_sum(ab);
+  if (threadIdx.x == 0) {
+    partial_aa[(int64_t)s * gridDim.x + blockIdx.x] = taa;
+    partial_ab[(int64_t)s * gridDim.x + blockIdx.x] = tab;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sirt_update(float* __restrict__ x, float* __restrict__ g,
+                                                     const float* __restrict__ h,
+                                                     const double* __restrict__ alpha, int64_t len) {
+  const int s = blockIdx.y;
+  const float fa = -(float)alpha[s];
+  const int64_t base = (int64_t)s * len;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    const float gv = g[base + i];
+    float xv = 1.0f * x[base + i];
+    xv += fa * gv;
+    x[base + i] = xv;
+    float nv = 1.0f * gv;
+    nv += fa * h[base + i];
+    g[base + i] = nv;
+  }
+}
+
 // out = sa*ca[s]*a + sb*cb[s]*b per slice (null ca / cb mean 1; null b means no second term);
 // out may be a or b (element-wise in place)
 __global__ __launch_bounds__(256) void k_lincomb(float* out, const float* a,
@@ -294,7 +335,7 @@ tomo_status ensure_solver(tomo_op* op) {
       {(void**)&b.tvb, 6 * img},
       {(void**)&b.r, sino}, {(void**)&b.q, sino}, {(void**)&b.rb, sino},
       {(void**)&b.scal, kSlots * B * sizeof(double)},
-      {(void**)&b.partial, B * kDotBlocks * sizeof(double)}};
+      {(void**)&b.partial, 2 * B * kDotBlocks * sizeof(double)}};   // two reductions at once
   for (auto& r : req) {
     if (hipMalloc(r.p, r.bytes) != hipSuccess) {
       *r.p = nullptr;
@@ -323,6 +364,18 @@ struct Ctx {
   tomo_status cg_step(float* x, float* p, const float* r, int64_t len) const {
     hipLaunchKernelGGL(k_cg_step, dim3(grid_for(len), B), dim3(256), 0, st, x, p, r, sc(kAlpha),
                        sc(kBeta), len);
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
+  // slot_aa = a.a, slot_ab = a.b in one pass
+  tomo_status dot2(const float* a, const float* b, int64_t len, int slot_aa, int slot_ab) const {
+    double* p2 = op->sb.partial + (int64_t)B * kDotBlocks;
+    hipLaunchKernelGGL(k_dot2_partial, dim3(kDotBlocks, B), dim3(256), 0, st, a, b, len,
+                       op->sb.partial, p2);
+    TOMO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.partial, kDotBlocks, sc(slot_aa));
+    TOMO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, p2, kDotBlocks, sc(slot_ab));
     TOMO_HIP(hipGetLastError());
     return TOMO_OK;
   }
@@ -474,13 +527,13 @@ tomo_status sirt_bb(const Ctx& c, const float* b, float* x, int vt, int iters, i
       TOMO_TRY(apply_project(c.op, w.p, w.q, c.B, vt, c.st));              // q = A g
       TOMO_TRY(apply_backproject(c.op, w.q, w.s, c.B, vt, filter, 1.0f, c.st));   // h = A^T_D A g
     }
-    TOMO_TRY(c.dot(w.p, w.p, c.img, kNum));
-    TOMO_TRY(c.dot(w.p, w.s, c.img, kDen));
+    TOMO_TRY(c.dot2(w.p, w.s, c.img, kNum, kDen));                           // g.g, g.h
     hipLaunchKernelGGL(k_sirt_step, dim3(1), dim3(256), 0, c.st, c.sc(kNum), c.sc(kDen), c.sc(kPNum),
                        c.sc(kPDen), c.sc(kAlpha), c.B, it == 0 ? 1 : 0);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img));    // x -= alpha g
-    TOMO_TRY(c.lin(w.p, w.p, w.s, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img));// g -= alpha h
+    hipLaunchKernelGGL(k_sirt_update, dim3(grid_for(c.img), c.B), dim3(256), 0, c.st, x, w.p, w.s,
+                       c.sc(kAlpha), c.img);                                  // x -= a g; g -= a h
+    TOMO_HIP(hipGetLastError());
   }
   return TOMO_OK;
 }
