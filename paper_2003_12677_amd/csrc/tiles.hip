@@ -113,12 +113,14 @@ constexpr int kMaxTilePoints = 128;
 template <int KW>
 constexpr int window_stride() { return (KW * KW + 3) / 4 * 4; }   // LDS floats per sample
 
-template <int CPL, typename V, int KW, int PS>
+// MAXP: the most samples a work item may hold (a compile-time bound, so that the staging loops
+// issue only the loads a block of that capacity can need)
+template <int CPL, typename V, int KW, int PS, int MAXP>
 __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __restrict__ val) {
   constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
   constexpr int PP = PS * PS;
   constexpr int NPL = (PP * kLanes + kBlock - 1) / kBlock;            // patch loads per thread
-  constexpr int NVL = (kMaxTilePoints * W2 + kBlock - 1) / kBlock;    // value loads per thread
+  constexpr int NVL = (MAXP * W2 + kBlock - 1) / kBlock;              // value loads per thread
   extern __shared__ float2 smem[];
   float2* patch = smem;                                                      // [PP][CH]
   float* s_val = reinterpret_cast<float*>(patch + PP * CH);                  // [TP][WP]
@@ -209,17 +211,17 @@ struct AdjWinArgs {
 };
 
 constexpr int kMaxAdjPoints = 256;
-constexpr int kMaxAdjRows = kMaxAdjPoints * kLanes / kBlock;      // row loads per thread
 
 // One block per staged tile, placed by an XCD-aware remap so that neighbouring tiles share an
 // L2.  The block loads its list offsets, then its sample rows, values and bucket offsets, then
 // the rows of Y those samples name.
-template <int CPL, typename V, int KW, int TS, bool SCALE>
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
 __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __restrict__ val) {
   constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
   constexpr int RS = TS + 2 * H, NBO = RS * RS + 1;
   constexpr int NBL = (NBO + kBlock - 1) / kBlock;                      // bucket offsets
-  constexpr int NVL = (kMaxAdjPoints * W2 + kBlock - 1) / kBlock;       // value loads
+  constexpr int NVL = (MAXP * W2 + kBlock - 1) / kBlock;                // value loads
+  constexpr int NYL = (MAXP * kLanes + kBlock - 1) / kBlock;            // row loads
   extern __shared__ float2 smem[];
   float2* sy = smem;                                                     // [QMAX][CH]
   float* sv = reinterpret_cast<float*>(sy + a.QMAX * CH);                // [QMAX][WP]
@@ -242,23 +244,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __res
     v[u] = 0;
     if (k < nq * W2) v[u] = ldraw(val, (int64_t)q0 * W2 + k);
   }
-  int r[kMaxAdjRows];
+  int r[NYL];
 #pragma unroll
-  for (int u = 0; u < kMaxAdjRows; ++u) {
+  for (int u = 0; u < NYL; ++u) {
     const int idx = threadIdx.x + u * kBlock;
     const int l = (idx % kLanes) * CPL;
     r[u] = (idx < nq * kLanes && l < nch) ? a.q_row[q0 + idx / kLanes] : -1;
   }
-  Vec<CPL> y[kMaxAdjRows];
+  Vec<CPL> y[NYL];
 #pragma unroll
-  for (int u = 0; u < kMaxAdjRows; ++u) {
+  for (int u = 0; u < NYL; ++u) {
     const int idx = threadIdx.x + u * kBlock;
     const int l = (idx % kLanes) * CPL;
     if (r[u] >= 0) y[u] = vload<CPL>(a.Y + (int64_t)r[u] * a.C + c0 + l);
   }
   if constexpr (SCALE) {
 #pragma unroll
-    for (int u = 0; u < kMaxAdjRows; ++u)
+    for (int u = 0; u < NYL; ++u)
       if (r[u] >= 0) {
         const float d = a.dscale[r[u] / a.nt];
 #pragma unroll
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __res
     if (k < nq * W2) sv[(k / W2) * WP + k % W2] = cvt(val, v[u]);
   }
 #pragma unroll
-  for (int u = 0; u < kMaxAdjRows; ++u) {
+  for (int u = 0; u < NYL; ++u) {
     const int idx = threadIdx.x + u * kBlock;
     if (r[u] >= 0) vstore<CPL>(sy + (idx / kLanes) * CH + (idx % kLanes) * CPL, y[u]);
   }
@@ -325,10 +327,15 @@ tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y,
   const size_t lds = fwd_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
   const V* v = (const V*)d.val[vt];
+  const bool small = op->tune.tile_points <= 64;
 #define TOMO_FWD_TILE(KW_, TS_)                                                                  \
   if (d.KW == KW_ && d.TS == TS_) {                                                             \
     constexpr int PS_ = TS_ + 2 * (KW_ / 2) + 1;                                                \
-    hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_>), grid, dim3(kBlock), lds, st, a, v);     \
+    if (small)                                                                                  \
+      hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_, 64>), grid, dim3(kBlock), lds, st, a, v); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_, kMaxTilePoints>), grid, dim3(kBlock), lds, \
+                         st, a, v);                                                             \
     TOMO_HIP(hipGetLastError());                                                                \
     return TOMO_OK;                                                                             \
   }
@@ -349,17 +356,25 @@ tomo_status adj_tile_impl(const tomo_op* op, int vt, const float2* Y, float2* X,
   const size_t lds = adj_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
   const V* v = (const V*)d.q_val[vt];
+  const bool small = d.QMAX <= 128;
+#define TOMO_ADJ_WIN_P(KW_, TS_, P_)                                                             \
+  if (dscale)                                                                                   \
+    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, true, P_>), grid, dim3(kBlock), lds, st, a, v); \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, false, P_>), grid, dim3(kBlock), lds, st, a, v);
 #define TOMO_ADJ_WIN(KW_, TS_)                                                                   \
   if (d.KW == KW_ && d.TS == TS_) {                                                             \
-    if (dscale)                                                                                 \
-      hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, true>), grid, dim3(kBlock), lds, st, a, v); \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, false>), grid, dim3(kBlock), lds, st, a, v); \
+    if (small) {                                                                                \
+      TOMO_ADJ_WIN_P(KW_, TS_, 128)                                                             \
+    } else {                                                                                    \
+      TOMO_ADJ_WIN_P(KW_, TS_, kMaxAdjPoints)                                                   \
+    }                                                                                           \
     TOMO_HIP(hipGetLastError());                                                                \
     return TOMO_OK;                                                                             \
   }
   TOMO_ADJ_WIN(3, 8) TOMO_ADJ_WIN(3, 16) TOMO_ADJ_WIN(5, 8) TOMO_ADJ_WIN(5, 16)
 #undef TOMO_ADJ_WIN
+#undef TOMO_ADJ_WIN_P
   return fail(TOMO_EUNSUPPORTED, "staged adjoint kernel has no variant for k_w %d, tile %d", d.KW,
               d.TS);
 }
