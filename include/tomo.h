@@ -121,7 +121,7 @@ typedef struct {
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB (and for k_w 3 or 5), else the
  * row kernels.
- * Defaults (in field order): 2, 2, 48, 4096, 128, 1024, 7, 6, 8, 64, 128, 1, 8192, 1024, 2, 1, 1. */
+ * Defaults (in field order): 2, 2, 48, 4096, 128, 1024, 7, 6, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 0. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -158,6 +158,10 @@ typedef struct {
   int32_t grid_fft;               /* Cartesian 2D DFTs: 1 = hand-written row and column kernels
                                      fused with the embed / crop steps when the grid side is a
                                      power of two in [16, 4096]; 0 = rocFFT                    */
+  int32_t adj_sell_tiles;         /* order of the sliced-ELL rows: 1 = Cartesian cells in 4 x 8
+                                     tiles (a block's rows are neighbouring cells, which share
+                                     most of their gathered polar rows); 0 = grid order, sorted
+                                     by length within adj_sell_sigma windows                   */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */

@@ -59,7 +59,8 @@ class tomo_tuning(ctypes.Structure):
                 ("tile_points", ctypes.c_int32), ("adj_tile_points", ctypes.c_int32),
                 ("normal_tiled", ctypes.c_int32), ("adj_sell_xcd_rows", ctypes.c_int32),
                 ("adj_medium_xcd_rows", ctypes.c_int32), ("fwd_rows_per_group", ctypes.c_int32),
-                ("det_fft", ctypes.c_int32), ("grid_fft", ctypes.c_int32)]
+                ("det_fft", ctypes.c_int32), ("grid_fft", ctypes.c_int32),
+                ("adj_sell_tiles", ctypes.c_int32)]
 
 
 class tomo_solve_opts(ctypes.Structure):

@@ -665,6 +665,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->fwd_rows_per_group = op->tune.fwd_rows_per_group;
   out->det_fft = op->tune.det_fft;
   out->grid_fft = op->tune.grid_fft;
+  out->adj_sell_tiles = op->tune.sell_tiles;
   return TOMO_OK;
 }
 
@@ -689,6 +690,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.fwd_rows_per_group = in->fwd_rows_per_group;
   t.det_fft = in->det_fft;
   t.grid_fft = in->grid_fft;
+  t.sell_tiles = in->adj_sell_tiles;
   return apply_tuning(op, t);
 }
 
@@ -698,6 +700,7 @@ namespace tomo {
 tomo_status apply_tuning(tomo_op* op, const Tuning& t) {
   TOMO_TRY(check_tuning(t));
   const bool relayout = t.sell_max != op->tune.sell_max || t.sell_sigma != op->tune.sell_sigma ||
+                        t.sell_tiles != op->tune.sell_tiles ||
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
   // the staged adjoint's dense cells use a row layout with the same bins, so it is rebuilt too
   const bool retile = relayout || t.tile != op->tune.tile || t.tile_points != op->tune.tile_points ||

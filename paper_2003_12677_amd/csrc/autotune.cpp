@@ -91,6 +91,7 @@ tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms,
       {[](Tuning& t) -> int& { return t.sell_max; }, {8, 16, 24, 32, 48, 64, 96}, kAdj},
       {[](Tuning& t) -> int& { return t.medium_max; }, {64, 128, 256, 512}, kAdj},
       {[](Tuning& t) -> int& { return t.sell_sigma; }, {1, 64, 512, 4096, 16384}, kAdj},
+      {[](Tuning& t) -> int& { return t.sell_tiles; }, {0, 1}, kAdj},
       {[](Tuning& t) -> int& { return t.chunk; }, {256, 512, 1024, 2048}, kAdj},
       {[](Tuning& t) -> int& { return t.sell_xcd_rows; }, {0, 1, 2048, 4096, 8192, 16384}, kAdj},
       {[](Tuning& t) -> int& { return t.medium_xcd_rows; }, {1, 256, 1024, 4096}, kAdj},

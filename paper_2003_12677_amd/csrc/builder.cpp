@@ -242,6 +242,7 @@ tomo_status check_tuning(const Tuning& t) {
     return fail(TOMO_EINVAL, "XCD interleave rows must be in [0, 2^24]");
   if (t.det_fft != 0 && t.det_fft != 1) return fail(TOMO_EINVAL, "det_fft must be 0 or 1");
   if (t.grid_fft != 0 && t.grid_fft != 1) return fail(TOMO_EINVAL, "grid_fft must be 0 or 1");
+  if (t.sell_tiles != 0 && t.sell_tiles != 1) return fail(TOMO_EINVAL, "adj_sell_tiles must be 0 or 1");
   if (t.fwd_rows_per_group != 1 && t.fwd_rows_per_group != 2 && t.fwd_rows_per_group != 4)
     return fail(TOMO_EINVAL, "fwd_rows_per_group must be 1, 2 or 4");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
@@ -265,11 +266,25 @@ void build_adj_layout(const HostCSR& s, const Tuning& t, HostAdj* o, const std::
     else if (l <= t.medium_max) medium.push_back((int32_t)r);
     else lng.push_back((int32_t)r);
   }
-  // sort by decreasing length inside windows of sigma rows (keeps neighbouring rows together)
-  for (size_t w = 0; w < sell.size(); w += (size_t)t.sell_sigma) {
-    auto b = sell.begin() + w;
-    auto e = sell.begin() + std::min(sell.size(), w + (size_t)t.sell_sigma);
-    std::stable_sort(b, e, [&](int32_t x, int32_t y) { return len(x) > len(y); });
+  const int64_t G = (int64_t)std::llround(std::sqrt((double)s.rows));
+  if (t.sell_tiles && G * G == s.rows) {
+    // Cartesian cells in 4 x 8 tiles of the centred grid (a block of 32 rows is one tile), tiles
+    // and the cells inside them in row-major order
+    const int64_t oG = G / 2, nt2 = (G + 7) / 8;
+    auto key = [&](int32_t r) {
+      const int64_t f1 = r / G, f2 = r % G;
+      const int64_t u1 = (f1 <= G - 1 - oG ? f1 : f1 - G) + oG;
+      const int64_t u2 = (f2 <= G - 1 - oG ? f2 : f2 - G) + oG;
+      return ((u1 / 4) * nt2 + u2 / 8) * 32 + (u1 % 4) * 8 + u2 % 8;
+    };
+    std::stable_sort(sell.begin(), sell.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+  } else {
+    // sort by decreasing length inside windows of sigma rows (keeps neighbouring rows together)
+    for (size_t w = 0; w < sell.size(); w += (size_t)t.sell_sigma) {
+      auto b = sell.begin() + w;
+      auto e = sell.begin() + std::min(sell.size(), w + (size_t)t.sell_sigma);
+      std::stable_sort(b, e, [&](int32_t x, int32_t y) { return len(x) > len(y); });
+    }
   }
   o->sell_rows = (int64_t)sell.size();
   const int64_t ns = (o->sell_rows + kSliceRows - 1) / kSliceRows;

@@ -74,6 +74,7 @@ struct Tuning {
   int fwd_rows_per_group = 2; // forward: rows per lane group in the pipelined kernel (1, 2, 4)
   int det_fft = 1;            // detector transforms: fused hand-written (1, L = 2^m) or library (0)
   int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1, G = 2^m) or library (0)
+  int sell_tiles = 0;         // sliced-ELL rows in 4 x 8 Cartesian tiles (1) or grid order (0)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout

@@ -236,6 +236,8 @@ TUNINGS = [
     dict(ROW, adj_sell_max=0, adj_medium_max=0, adj_chunk=8),     # every row chunked
     dict(ROW, adj_sell_max=1024, adj_medium_max=1024),            # every row in sliced ELL
     dict(ROW, adj_sell_max=4, adj_medium_max=16, adj_chunk=24, adj_sell_sigma=1),
+    dict(ROW, adj_sell_tiles=1),                                   # sliced ELL in 4 x 8 cell tiles
+    dict(adj_sell_tiles=1, adj_tile_points=64),
     dict(fwd_tiled=7, adj_tiled=7, tile=8, tile_points=32, adj_tile_points=32),   # many dense tiles
     dict(fwd_tiled=7, adj_tiled=7, tile=8, tile_points=64, adj_tile_points=128),
     dict(fwd_tiled=7, adj_tiled=7, tile=16, tile_points=128, adj_tile_points=256),

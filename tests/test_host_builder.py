@@ -157,7 +157,8 @@ def test_host_only_operator_rejects_apply():
 @pytest.mark.parametrize("d", [GEOMS[0], GEOMS[3], GEOMS[5], GEOMS[6]], ids=lambda d: "_".join(f"{k}{v}" for k, v in d.items()))
 @pytest.mark.parametrize("tuning", [{}, dict(tile=8, tile_points=32, adj_tile_points=32),
                                     dict(tile=16, tile_points=64, adj_tile_points=256),
-                                    dict(adj_sell_max=4, adj_medium_max=20, adj_chunk=8, adj_sell_sigma=3)])
+                                    dict(adj_sell_max=4, adj_medium_max=20, adj_chunk=8, adj_sell_sigma=3),
+                                    dict(adj_sell_tiles=1, adj_sell_max=24)])
 def test_kernel_layouts_replay_the_csr_products(d, tuning):
     """Every device layout (fixed-stride forward, sliced-ELL / wave / chunked adjoint, LDS-staged
     window-form tiles, and the row layout of the staged adjoint's dense cells) replayed on the
