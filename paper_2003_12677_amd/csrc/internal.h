@@ -57,7 +57,7 @@ struct HostCSR {
 // Layout parameters of the two SpMMs (the autotuner's search space; tomo_set_tuning).
 struct Tuning {
   int fwd_cpl = 2;        // complex channels per lane in the forward kernel (1, 2 or 4)
-  int adj_cpl = 2;        // complex channels per lane in the adjoint kernel (1, 2 or 4)
+  int adj_cpl = 4;        // complex channels per lane in the adjoint row kernels (1, 2 or 4)
   int sell_max = 48;      // S rows with <= sell_max entries: sliced ELL, 8 rows per slice
   int sell_sigma = 4096;  // rows are sorted by length within windows of sell_sigma rows
   int medium_max = 128;   // longer rows up to medium_max entries: one wavefront per row
@@ -74,7 +74,7 @@ struct Tuning {
   int fwd_rows_per_group = 2; // forward: rows per lane group in the pipelined kernel (1, 2, 4)
   int det_fft = 1;            // detector transforms: fused hand-written (1, L = 2^m) or library (0)
   int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1, G = 2^m) or library (0)
-  int sell_tiles = 0;         // sliced-ELL rows in 4 x 8 Cartesian tiles (1) or grid order (0)
+  int sell_tiles = 1;         // sliced-ELL rows in 4 x 8 Cartesian tiles (1) or grid order (0)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
