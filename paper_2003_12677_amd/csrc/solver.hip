@@ -29,17 +29,32 @@ __device__ __forceinline__ double block_sum(double v) {
   return r;
 }
 
-// partial[s][j] = sum over the j-th strided share of slice s of a*b, in float64
+// partial[s][j] = sum over the j-th strided share of slice s of a*b, in float64; four strided
+// elements per step with independent accumulators keep four loads in flight per thread, and a
+// self product (SELF) loads each element once
+template <bool SELF>
 __global__ __launch_bounds__(256) void k_dot_partial(const float* __restrict__ a,
                                                      const float* __restrict__ b, int64_t len,
                                                      double* __restrict__ partial) {
   const int s = blockIdx.y;
   const float* pa = a + (int64_t)s * len;
-  const float* pb = b + (int64_t)s * len;
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
-    acc += (double)pa[i] * (double)pb[i];
-  const double t = block_sum(acc);
+  const float* pb = SELF ? pa : b + (int64_t)s * len;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < len; i += 4 * stride) {
+    float va[4], vb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) va[u] = pa[i + u * stride];
+    if constexpr (!SELF) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vb[u] = pb[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += (double)va[u] * (double)(SELF ? va[u] : vb[u]);
+  }
+  for (; i < len; i += stride) acc[0] += (double)pa[i] * (double)pb[i];
+  const double t = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
   if (threadIdx.x == 0) partial[(int64_t)s * gridDim.x + blockIdx.x] = t;
 }
 
@@ -197,7 +212,10 @@ enum { kGamma0 = 0, kGamma1, kDelta, kAlpha, kBeta, kNum, kDen, kPNum, kPDen, kT
 
 tomo_status launch_dot(const float* a, const float* b, int64_t len, int B, double* partial,
                        double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, B), dim3(256), 0, st, a, b, len, partial);
+  if (a == b)
+    hipLaunchKernelGGL(k_dot_partial<true>, dim3(kDotBlocks, B), dim3(256), 0, st, a, b, len, partial);
+  else
+    hipLaunchKernelGGL(k_dot_partial<false>, dim3(kDotBlocks, B), dim3(256), 0, st, a, b, len, partial);
   TOMO_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, partial, kDotBlocks, out);
   TOMO_HIP(hipGetLastError());
