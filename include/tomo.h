@@ -356,10 +356,12 @@ void tomo_graph_destroy(tomo_graph* g);
 /* Density filter (Sec. 3): per-polar-sample weights D_v ~ arg min ||S D_v - c 1|| over the
  * Cartesian grid, c = kappa(0)^2 the mass of the separable gridding kernel, among weights even
  * in the frequency (D_v(k, a) = D_v(-k, a), which keeps the filtered back projection of a real
- * sinogram real), by `iters` CGLS steps from zero (float32 vectors, float64 dots; the
- * least-squares problem is rank deficient, so the weights are defined by this iteration).  Kept in the operator for
- * TOMO_FILTER_DENSITY; *resid (nullable) receives ||S D_v - c 1||_2.  Synchronises the device
- * and uses temporary device memory.  Errors: TOMO_EINVAL, TOMO_ESTATE, TOMO_ENOMEM, TOMO_EHIP. */
+ * sinogram real), by `iters` (1..100000) CGLS steps from zero with the float32 matrix values
+ * (float32 vectors, float64 dots; the least-squares problem is rank deficient, so the weights
+ * are defined by this iteration).  Kept in the operator for TOMO_FILTER_DENSITY, replacing
+ * earlier weights; *resid (nullable) receives ||S D_v - c 1||_2 from the iteration's residual.
+ * Synchronises the device and uses temporary device memory.  Errors: TOMO_EINVAL (NULL op,
+ * iters out of range), TOMO_ESTATE (no device, no float32 values), TOMO_ENOMEM, TOMO_EHIP. */
 tomo_status tomo_density_filter(tomo_op* op, int32_t iters, double* resid);
 
 /* Host copy of the density weights: w [L * n_theta] float32, FFT-ordered polar rows
