@@ -64,7 +64,7 @@ struct Tuning {
   int chunk = 1024;       // rows above medium_max: chunks of <= chunk entries, one block each
   // staged kernels per value type: bit vt (1 f32, 2 bf16, 4 f16) set = staged, clear = rows
   int fwd_tiled = 7;      // forward: LDS-staged Cartesian tiles
-  int adj_tiled = 6;      // adjoint: LDS-staged output tiles (+ row kernels on dense cells)
+  int adj_tiled = 7;      // adjoint: LDS-staged output tiles (+ row kernels on dense cells)
   int tile = 8;           // Cartesian tile side of the staged kernels (8 or 16)
   int tile_points = 64;   // forward: samples per block
   int adj_tile_points = 128;   // adjoint: most samples a staged tile's region may hold
