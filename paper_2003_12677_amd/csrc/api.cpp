@@ -163,6 +163,11 @@ tomo_status upload_tiles(tomo_op* op) {
 }
 
 void free_device(tomo_op* op) {
+  if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+  if (op->ev_join) (void)hipEventDestroy(op->ev_join);
+  if (op->aux) (void)hipStreamDestroy(op->aux);
+  op->ev_fork = op->ev_join = nullptr;
+  op->aux = nullptr;
   free_tiles(op);
   destroy_plans(op);
   free_solver(op);
@@ -187,6 +192,9 @@ tomo_status upload_all(tomo_op* op) {
   const Geom& g = op->g;
   op->cmax = (g.max_batch + 1) / 2;
   TOMO_HIP(hipDeviceGetAttribute(&op->n_cu, hipDeviceAttributeMultiprocessorCount, op->device));
+  TOMO_HIP(hipStreamCreateWithFlags(&op->aux, hipStreamNonBlocking));
+  TOMO_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+  TOMO_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
   {
     HostEll ell;
     build_ell(op->sdag, g.kw * g.kw, &ell);

@@ -220,7 +220,11 @@ struct tomo_op {
   tomo::HostAdj hadj;             // adjoint layout for the current tuning
   std::vector<double> kd;         // separable deapodisation factors [n]
   int device = -1;
-  int n_cu = 256;                 // compute units of the device (persistent grids)
+  int n_cu = 256;                 // compute units of the device
+  // second stream of the staged adjoint: the dense-cell row kernels run there, forked from and
+  // joined back to the caller's stream by events, beside the staged kernel (disjoint outputs)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   uint32_t values = 0;
   int64_t cols_touched = 0, polar_nonempty = 0;
   // device

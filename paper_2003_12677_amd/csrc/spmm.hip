@@ -582,17 +582,26 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (!op->adj_ready) return fail(TOMO_ESTATE, "adjoint layout unavailable (failed re-tuning)");
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
-  const DevAdj* rows = &op->adj;
+  auto rows = [&](const DevAdj& d, hipStream_t s) -> tomo_status {
+    switch (vt) {
+      case TOMO_VAL_F32: return adj_cpl<float>(op, d, vt, Y, X, C, dscale, s);
+      case TOMO_VAL_BF16: return adj_cpl<bf16_t>(op, d, vt, Y, X, C, dscale, s);
+      default: return adj_cpl<_Float16>(op, d, vt, Y, X, C, dscale, s);
+    }
+  };
   if (((op->tune.adj_tiled >> vt) & 1) && op->tiles_ready && adj_tile_supported(op) &&
       adj_tile_lds_bytes(op, C) <= kMaxTileLds) {
-    TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, st));   // staged tiles
-    rows = &op->adj_dense;                                    // then the dense cells
+    // the dense cells' row kernels on the second stream, beside the staged tiles (they write
+    // disjoint cells); the caller's stream waits for both
+    TOMO_HIP(hipEventRecord(op->ev_fork, st));
+    TOMO_HIP(hipStreamWaitEvent(op->aux, op->ev_fork, 0));
+    TOMO_TRY(rows(op->adj_dense, op->aux));
+    TOMO_HIP(hipEventRecord(op->ev_join, op->aux));
+    TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, st));
+    TOMO_HIP(hipStreamWaitEvent(st, op->ev_join, 0));
+    return TOMO_OK;
   }
-  switch (vt) {
-    case TOMO_VAL_F32: return adj_cpl<float>(op, *rows, vt, Y, X, C, dscale, st);
-    case TOMO_VAL_BF16: return adj_cpl<bf16_t>(op, *rows, vt, Y, X, C, dscale, st);
-    default: return adj_cpl<_Float16>(op, *rows, vt, Y, X, C, dscale, st);
-  }
+  return rows(op->adj, st);
 }
 
 }  // namespace tomo
