@@ -165,9 +165,11 @@ tomo_status upload_tiles(tomo_op* op) {
 void free_device(tomo_op* op) {
   if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
   if (op->ev_join) (void)hipEventDestroy(op->ev_join);
+  if (op->ev_join2) (void)hipEventDestroy(op->ev_join2);
   if (op->aux) (void)hipStreamDestroy(op->aux);
-  op->ev_fork = op->ev_join = nullptr;
-  op->aux = nullptr;
+  if (op->aux2) (void)hipStreamDestroy(op->aux2);
+  op->ev_fork = op->ev_join = op->ev_join2 = nullptr;
+  op->aux = op->aux2 = nullptr;
   free_tiles(op);
   destroy_plans(op);
   free_solver(op);
@@ -193,8 +195,10 @@ tomo_status upload_all(tomo_op* op) {
   op->cmax = (g.max_batch + 1) / 2;
   TOMO_HIP(hipDeviceGetAttribute(&op->n_cu, hipDeviceAttributeMultiprocessorCount, op->device));
   TOMO_HIP(hipStreamCreateWithFlags(&op->aux, hipStreamNonBlocking));
+  TOMO_HIP(hipStreamCreateWithFlags(&op->aux2, hipStreamNonBlocking));
   TOMO_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
   TOMO_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
+  TOMO_HIP(hipEventCreateWithFlags(&op->ev_join2, hipEventDisableTiming));
   {
     HostEll ell;
     build_ell(op->sdag, g.kw * g.kw, &ell);

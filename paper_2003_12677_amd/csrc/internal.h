@@ -223,8 +223,8 @@ struct tomo_op {
   int n_cu = 256;                 // compute units of the device
   // second stream of the staged adjoint: the dense-cell row kernels run there, forked from and
   // joined back to the caller's stream by events, beside the staged kernel (disjoint outputs)
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t aux = nullptr, aux2 = nullptr;   // dense sliced-ELL rows; dense longer rows
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
   uint32_t values = 0;
   int64_t cols_touched = 0, polar_nonempty = 0;
   // device

@@ -591,14 +591,22 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
   };
   if (((op->tune.adj_tiled >> vt) & 1) && op->tiles_ready && adj_tile_supported(op) &&
       adj_tile_lds_bytes(op, C) <= kMaxTileLds) {
-    // the dense cells' row kernels on the second stream, beside the staged tiles (they write
-    // disjoint cells); the caller's stream waits for both
+    // the dense cells' row kernels on two more streams (sliced-ELL rows; wave-per-row and
+    // chunked rows), beside the staged tiles: all three write disjoint cells, and the caller's
+    // stream waits for the other two
+    DevAdj sell = op->adj_dense, tail = op->adj_dense;
+    sell.n_medium = sell.n_long = sell.n_chunks = 0;
+    tail.n_slices = 0;
     TOMO_HIP(hipEventRecord(op->ev_fork, st));
     TOMO_HIP(hipStreamWaitEvent(op->aux, op->ev_fork, 0));
-    TOMO_TRY(rows(op->adj_dense, op->aux));
+    TOMO_HIP(hipStreamWaitEvent(op->aux2, op->ev_fork, 0));
+    TOMO_TRY(rows(sell, op->aux));
     TOMO_HIP(hipEventRecord(op->ev_join, op->aux));
+    TOMO_TRY(rows(tail, op->aux2));
+    TOMO_HIP(hipEventRecord(op->ev_join2, op->aux2));
     TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, st));
     TOMO_HIP(hipStreamWaitEvent(st, op->ev_join, 0));
+    TOMO_HIP(hipStreamWaitEvent(st, op->ev_join2, 0));
     return TOMO_OK;
   }
   return rows(op->adj, st);
