@@ -306,3 +306,26 @@ def test_staged_kernels_on_every_geometry(tomo, shape, tile):
         Yo[pm] = Yc[..., 0] + 1j * Yc[..., 1]
         assert rel_l2(complex_channels(op.slice_adj(_dev(Yc), batch)), (ref.S @ Yo)[cm]) < 1e-6
     op.close()
+
+
+def test_staged_adjoint_on_a_side_stream_matches_the_default_stream(tomo):
+    """The staged adjoint forks its dense-cell kernels to streams of its own and joins them back
+    to the caller's stream: a call on a non-default torch stream, consumed after the caller
+    synchronises that stream, equals the default-stream result bit for bit."""
+    n, nt, npb, batch = 64, 90, 91, 16
+    op = _gpu_op(tomo, n, nt, npb, {}, max_batch=16, values=("f32", "bf16"))
+    g = oracle_op(n, nt, npb).geom
+    C = batch // 2
+    Y = _dev(_rand((g.L * nt, C, 2), 950))
+    ref = {vt: op.slice_adj(Y, batch, values=vt).clone() for vt in ("f32", "bf16")}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        outs = {vt: op.slice_adj(Y, batch, values=vt) for vt in ("f32", "bf16")}
+        again = op.slice_adj(Y, batch, values="bf16")
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for vt in ("f32", "bf16"):
+        assert torch.equal(outs[vt], ref[vt]), vt
+    assert torch.equal(again, ref["bf16"])
+    op.close()
