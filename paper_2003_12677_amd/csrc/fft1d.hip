@@ -69,16 +69,25 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
   const int na = min(AG, nt - a0);
   const int64_t plane = (int64_t)nt * np;
   const bool odd = 2 * c + 1 < B;
-  for (int i = threadIdx.x; i < AG * L; i += kFB) {
+  // elements per thread, loaded as one batch (all loads issued before the first LDS store)
+  constexpr int NE = (AG * L + kFB - 1) / kFB;
+  float2 v[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int i = threadIdx.x + u * kFB;
     const int q = i / L, m = i % L;
     const int b = (m + cdet) & (L - 1);
-    float2 v = make_float2(0.f, 0.f);
-    if (q < na && b < np) {
+    v[u] = make_float2(0.f, 0.f);
+    if (i < AG * L && q < na && b < np) {
       const int64_t off = (int64_t)(a0 + q) * np + b;
-      v.x = y[(int64_t)(2 * c) * plane + off];
-      if (odd) v.y = y[(int64_t)(2 * c + 1) * plane + off];
+      v[u].x = y[(int64_t)(2 * c) * plane + off];
+      if (odd) v[u].y = y[(int64_t)(2 * c + 1) * plane + off];
     }
-    buf[lds(i)] = v;
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int i = threadIdx.x + u * kFB;
+    if (i < AG * L) buf[lds(i)] = v[u];
   }
   __syncthreads();
   fft_lds<L, AG, false>(buf, tw);

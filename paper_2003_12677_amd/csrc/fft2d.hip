@@ -52,20 +52,31 @@ __global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
                                                     int on) {
   __shared__ float2 buf[lds_size<AG * G>()];
   constexpr int groups = G / AG;
+  // elements per thread, loaded as one batch (all loads issued before the first LDS store)
+  constexpr int NE = (AG * G + kFB - 1) / kFB;
   const int c = blockIdx.x / groups, g1_0 = (blockIdx.x % groups) * AG;
   const int64_t plane = (int64_t)n * n;
   const bool odd = 2 * c + 1 < B;
-  for (int i = threadIdx.x; i < AG * G; i += kFB) {
+  float re[NE], im[NE], kk[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int i = threadIdx.x + u * kFB;
     const int q = i / G, g2 = i % G;
     const int i1 = (g1_0 + q + on) & (G - 1), i2 = (g2 + on) & (G - 1);
-    float2 v = make_float2(0.f, 0.f);
-    if (i1 < n && i2 < n) {
-      const float k = kd[i1] * kd[i2];
+    re[u] = 0.f;
+    im[u] = 0.f;
+    kk[u] = 0.f;
+    if (i < AG * G && i1 < n && i2 < n) {
       const int64_t off = (int64_t)i1 * n + i2;
-      v.x = x[(int64_t)(2 * c) * plane + off] * k;
-      if (odd) v.y = x[(int64_t)(2 * c + 1) * plane + off] * k;
+      kk[u] = kd[i1] * kd[i2];
+      re[u] = x[(int64_t)(2 * c) * plane + off];
+      if (odd) im[u] = x[(int64_t)(2 * c + 1) * plane + off];
     }
-    buf[lds(i)] = v;
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int i = threadIdx.x + u * kFB;
+    if (i < AG * G) buf[lds(i)] = make_float2(re[u] * kk[u], im[u] * kk[u]);
   }
   __syncthreads();
   fft_lds<G, AG, false>(buf, tw);
