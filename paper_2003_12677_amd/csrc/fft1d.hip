@@ -41,8 +41,21 @@ __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restri
   const int c = blockIdx.x / agroups, a0 = (blockIdx.x % agroups) * AG;
   const int na = min(AG, nt - a0);
   const float2* src = Ys + ((int64_t)c * nt + a0) * L;
-  for (int i = threadIdx.x; i < AG * L; i += kFB)
-    buf[lds(i)] = (i < na * L) ? src[i] : make_float2(0.f, 0.f);
+  {
+    constexpr int NE = (AG * L + kFB - 1) / kFB;  // loads per thread, issued as one batch
+    float2 v[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      v[u] = make_float2(0.f, 0.f);
+      if (i < na * L) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      if (i < AG * L) buf[lds(i)] = v[u];
+    }
+  }
   __syncthreads();
   fft_lds<L, AG, true>(buf, tw);
   const int64_t plane = (int64_t)nt * np;

@@ -92,9 +92,19 @@ __global__ __launch_bounds__(kFB) void k_cols(float2* __restrict__ Xs,
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
   const int c = (int)(blk / groups), j2_0 = (int)(blk % groups) * W;
   float2* base = Xs + (int64_t)c * G * G + j2_0;
-  for (int i = threadIdx.x; i < W * G; i += kFB) {
-    const int g1 = i / W, w = i % W;
-    buf[lds(w * G + g1)] = base[(int64_t)g1 * G + w];
+  {
+    constexpr int NE = (W * G + kFB - 1) / kFB;   // loads per thread, issued as one batch
+    float2 v[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      if (i < W * G) v[u] = base[(int64_t)(i / W) * G + i % W];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      if (i < W * G) buf[lds((i % W) * G + i / W)] = v[u];
+    }
   }
   __syncthreads();
   fft_lds<G, W, INV>(buf, tw);
@@ -114,7 +124,20 @@ __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict_
   constexpr int groups = G / AG;
   const int c = blockIdx.x / groups, g1_0 = (blockIdx.x % groups) * AG;
   const float2* src = Xs + ((int64_t)c * G + g1_0) * G;
-  for (int i = threadIdx.x; i < AG * G; i += kFB) buf[lds(i)] = src[i];
+  {
+    constexpr int NE = (AG * G + kFB - 1) / kFB;  // loads per thread, issued as one batch
+    float2 v[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      if (i < AG * G) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      if (i < AG * G) buf[lds(i)] = v[u];
+    }
+  }
   __syncthreads();
   fft_lds<G, AG, true>(buf, tw);
   const int64_t plane = (int64_t)n * n;
