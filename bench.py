@@ -28,7 +28,7 @@ N_IMG, N_ANG, N_DET, BATCH = 2048, 1501, 2048, 32
 WORKLOAD = "parallel-beam 2048x2048, 1501 angles in [0,pi), 2048 bins, batch 32 slices"
 COUNTERS = os.path.join(ROOT, "profiles", "spmm_2048_1501_b32_counters.json")
 SPMM_SOURCES = [os.path.join(ROOT, "paper_2003_12677_amd", "csrc", f)
-                for f in ("spmm.hip", "tiles.hip")]
+                for f in ("spmm.hip", "tiles.hip", "builder.cpp")]
 
 
 def parse():
@@ -93,8 +93,8 @@ def step_percentiles(torch, fn, iters: int):
 
 
 def source_digest(tuning: dict) -> str:
-    """Identity of the SpMM kernels a counter summary was taken from: their sources and the
-    operator's layout tuning."""
+    """Identity of the SpMM kernels a counter summary was taken from: their sources, the
+    builder of their layouts and the operator's layout tuning."""
     h = hashlib.sha256()
     for f in SPMM_SOURCES:
         with open(f, "rb") as fh:
@@ -320,7 +320,8 @@ def uneven_leg(torch, tomo):
         res["operators"].append({"n": n, "n_angles": nt, "n_det": npb, "slices": count,
                                  "batches": batches, "nnz": op.info.nnz,
                                  "tuned": {k: tune[k] for k in ("fwd_tiled", "adj_tiled", "tile",
-                                           "tile_points", "adj_tile_points", "fwd_rows_per_group",
+                                           "tile_points", "adj_tile_points", "tile_strip",
+                                           "fwd_rows_per_group",
                                            "fwd_channels_per_lane", "adj_channels_per_lane",
                                            "adj_sell_max", "adj_medium_max",
                                            "adj_sell_xcd_rows", "adj_medium_xcd_rows")},

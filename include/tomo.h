@@ -121,7 +121,7 @@ typedef struct {
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB (and for k_w 3 or 5), else the
  * row kernels.
- * Defaults (in field order): 2, 4, 48, 4096, 128, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1. */
+ * Defaults (in field order): 2, 4, 48, 4096, 128, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -162,6 +162,12 @@ typedef struct {
                                      tiles (a block's rows are neighbouring cells, which share
                                      most of their gathered polar rows); 0 = grid order, sorted
                                      by length within adj_sell_sigma windows                   */
+  int32_t tile_strip;             /* order in which the staged kernels visit their tiles: strips
+                                     this many tiles wide, each walked tile row by tile row, so
+                                     that a tile's neighbours above and below were visited a
+                                     strip width earlier and their shared halo samples are still
+                                     in the XCD's L2 (0 = row-major over the whole grid); results
+                                     do not depend on it; 0..4096                              */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */

@@ -60,7 +60,7 @@ class tomo_tuning(ctypes.Structure):
                 ("normal_tiled", ctypes.c_int32), ("adj_sell_xcd_rows", ctypes.c_int32),
                 ("adj_medium_xcd_rows", ctypes.c_int32), ("fwd_rows_per_group", ctypes.c_int32),
                 ("det_fft", ctypes.c_int32), ("grid_fft", ctypes.c_int32),
-                ("adj_sell_tiles", ctypes.c_int32)]
+                ("adj_sell_tiles", ctypes.c_int32), ("tile_strip", ctypes.c_int32)]
 
 
 class tomo_solve_opts(ctypes.Structure):

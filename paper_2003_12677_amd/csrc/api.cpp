@@ -678,6 +678,7 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->det_fft = op->tune.det_fft;
   out->grid_fft = op->tune.grid_fft;
   out->adj_sell_tiles = op->tune.sell_tiles;
+  out->tile_strip = op->tune.tile_strip;
   return TOMO_OK;
 }
 
@@ -703,6 +704,7 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.det_fft = in->det_fft;
   t.grid_fft = in->grid_fft;
   t.sell_tiles = in->adj_sell_tiles;
+  t.tile_strip = in->tile_strip;
   return apply_tuning(op, t);
 }
 
@@ -716,7 +718,7 @@ tomo_status apply_tuning(tomo_op* op, const Tuning& t) {
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
   // the staged adjoint's dense cells use a row layout with the same bins, so it is rebuilt too
   const bool retile = relayout || t.tile != op->tune.tile || t.tile_points != op->tune.tile_points ||
-                      t.adj_tile_points != op->tune.adj_tile_points;
+                      t.adj_tile_points != op->tune.adj_tile_points || t.tile_strip != op->tune.tile_strip;
   op->tune = t;
   if (op->device < 0) {
     if (relayout) build_adj_layout(op->s, op->tune, &op->hadj);

@@ -85,6 +85,7 @@ tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms,
       {[](Tuning& t) -> int& { return t.tile; }, {8, 16}, kBoth},
       {[](Tuning& t) -> int& { return t.tile_points; }, {32, 64, 96, 128}, kFwd},
       {[](Tuning& t) -> int& { return t.adj_tile_points; }, {64, 96, 128, 160, 192, 256}, kAdj},
+      {[](Tuning& t) -> int& { return t.tile_strip; }, {0, 16, 32, 128}, kBoth},
       {[](Tuning& t) -> int& { return t.fwd_rows_per_group; }, {1, 2, 4}, kFwd},
       {[](Tuning& t) -> int& { return t.fwd_cpl; }, {1, 2, 4}, kFwd},
       {[](Tuning& t) -> int& { return t.adj_cpl; }, {1, 2, 4}, kAdj},

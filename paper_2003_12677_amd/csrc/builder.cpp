@@ -243,6 +243,7 @@ tomo_status check_tuning(const Tuning& t) {
   if (t.det_fft != 0 && t.det_fft != 1) return fail(TOMO_EINVAL, "det_fft must be 0 or 1");
   if (t.grid_fft != 0 && t.grid_fft != 1) return fail(TOMO_EINVAL, "grid_fft must be 0 or 1");
   if (t.sell_tiles != 0 && t.sell_tiles != 1) return fail(TOMO_EINVAL, "adj_sell_tiles must be 0 or 1");
+  if (t.tile_strip < 0 || t.tile_strip > 4096) return fail(TOMO_EINVAL, "tile_strip must be in [0, 4096]");
   if (t.fwd_rows_per_group != 1 && t.fwd_rows_per_group != 2 && t.fwd_rows_per_group != 4)
     return fail(TOMO_EINVAL, "fwd_rows_per_group must be 1, 2 or 4");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
@@ -344,6 +345,22 @@ namespace {
 inline int centred(int64_t f, int G, int oG) { return (f <= G - 1 - oG) ? (int)f : (int)(f - G); }
 // tile index along one axis of the centred coordinate j
 inline int tile_of(int j, int oG, int TS) { return (j + oG) / TS; }
+// Tile visiting order of the staged kernels: strips `strip` tiles wide, each walked tile row by
+// tile row (0, or a strip as wide as the grid: row-major).  Blocks go to the XCDs in contiguous
+// runs of this order, so the tiles above and below a tile, whose halos overlap its own, run on
+// the same XCD about a strip width earlier or later and find the shared data in its L2.
+std::vector<int> tile_order(int NT, int strip) {
+  std::vector<int> o;
+  o.reserve((size_t)NT * NT);
+  if (strip <= 0 || strip >= NT) {
+    for (int i = 0; i < NT * NT; ++i) o.push_back(i);
+    return o;
+  }
+  for (int s0 = 0; s0 < NT; s0 += strip)
+    for (int t1 = 0; t1 < NT; ++t1)
+      for (int t2 = s0; t2 < std::min(NT, s0 + strip); ++t2) o.push_back(t1 * NT + t2);
+  return o;
+}
 }  // namespace
 
 tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
@@ -358,7 +375,11 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
   const int64_t N = sdag.rows;
   const int ntiles = o->NT * o->NT;
   const int origin_tile = tile_of(0, oG, TS) * o->NT + tile_of(0, oG, TS);
-  std::vector<int32_t> tile_of_row(N);
+  // points are grouped by their tile's place in the visiting order
+  const std::vector<int> worder = tile_order(o->NT, t.tile_strip);
+  std::vector<int> rank(ntiles);
+  for (int i = 0; i < ntiles; ++i) rank[worder[i]] = i;
+  std::vector<int32_t> rank_of_row(N);
   std::vector<int64_t> count(ntiles + 1, 0);
   for (int64_t r = 0; r < N; ++r) {
     int tl = origin_tile;   // rows without a window (unpaired Nyquist sample) still write zeros
@@ -368,22 +389,23 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
       const int t2 = std::min(std::max(tile_of(c2, oG, TS), 0), o->NT - 1);
       tl = t1 * o->NT + t2;
     }
-    tile_of_row[r] = tl;
-    count[tl + 1]++;
+    rank_of_row[r] = rank[tl];
+    count[rank[tl] + 1]++;
   }
   for (int i = 0; i < ntiles; ++i) count[i + 1] += count[i];
   std::vector<int32_t> order(N);
   {
     std::vector<int64_t> next(count.begin(), count.end() - 1);
-    for (int64_t r = 0; r < N; ++r) order[next[tile_of_row[r]]++] = (int32_t)r;
+    for (int64_t r = 0; r < N; ++r) order[next[rank_of_row[r]]++] = (int32_t)r;
   }
   o->pt_row = order;
   o->pt_base.assign((size_t)N, 0);
   o->pt_val.assign((size_t)N * o->W2, 0.0);
   o->wi_beg.push_back(0);
-  for (int tl = 0; tl < ntiles; ++tl) {
+  for (int rk = 0; rk < ntiles; ++rk) {
+    const int tl = worder[rk];
     const int j01 = -oG + (tl / o->NT) * TS - h, j02 = -oG + (tl % o->NT) * TS - h;   // patch origin
-    for (int64_t i = count[tl]; i < count[tl + 1]; ++i) {
+    for (int64_t i = count[rk]; i < count[rk + 1]; ++i) {
       const int64_t r = order[i];
       const int32_t c1 = centres[(size_t)r * 2], c2 = centres[(size_t)r * 2 + 1];
       if (c1 == INT32_MIN) {
@@ -403,9 +425,9 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
         o->pt_val[(size_t)i * o->W2 + s1 * kw + s2] = sdag.val[e];
       }
     }
-    for (int64_t b = count[tl]; b < count[tl + 1]; b += t.tile_points) {
+    for (int64_t b = count[rk]; b < count[rk + 1]; b += t.tile_points) {
       o->wi_tile.push_back(tl);
-      o->wi_beg.push_back((int32_t)std::min<int64_t>(b + t.tile_points, count[tl + 1]));
+      o->wi_beg.push_back((int32_t)std::min<int64_t>(b + t.tile_points, count[rk + 1]));
     }
   }
   return TOMO_OK;
@@ -454,47 +476,47 @@ tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<
   }
   o->dense_cell.assign((size_t)G * G, 0);
   o->wi_q.push_back(0);
-  for (int t1 = 0; t1 < NT; ++t1)
-    for (int t2 = 0; t2 < NT; ++t2) {
-      // region cell (a, b) is extended-grid cell (t1*TS + a, t2*TS + b)
-      auto bucket = [&](int a, int b, int64_t* beg, int64_t* end) {
-        const int64_t e1 = (int64_t)t1 * TS + a, e2 = (int64_t)t2 * TS + b;
-        if (e1 >= E || e2 >= E) { *beg = *end = 0; return; }
-        *beg = cell_ptr[(size_t)(e1 * E + e2)];
-        *end = cell_ptr[(size_t)(e1 * E + e2) + 1];
-      };
-      int64_t nq = 0;
-      for (int a = 0; a < RS; ++a)
-        for (int b = 0; b < RS; ++b) {
-          int64_t bb, be;
-          bucket(a, b, &bb, &be);
-          nq += be - bb;
-        }
-      if (nq > o->QMAX) {
-        for (int a = 0; a < TS; ++a)
-          for (int b = 0; b < TS; ++b) {
-            const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
-            if (j1 <= G - 1 - oG && j2 <= G - 1 - oG)
-              o->dense_cell[(size_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = 1;
-          }
-        continue;
+  for (const int tl : tile_order(NT, t.tile_strip)) {
+    const int t1 = tl / NT, t2 = tl % NT;
+    // region cell (a, b) is extended-grid cell (t1*TS + a, t2*TS + b)
+    auto bucket = [&](int a, int b, int64_t* beg, int64_t* end) {
+      const int64_t e1 = (int64_t)t1 * TS + a, e2 = (int64_t)t2 * TS + b;
+      if (e1 >= E || e2 >= E) { *beg = *end = 0; return; }
+      *beg = cell_ptr[(size_t)(e1 * E + e2)];
+      *end = cell_ptr[(size_t)(e1 * E + e2) + 1];
+    };
+    int64_t nq = 0;
+    for (int a = 0; a < RS; ++a)
+      for (int b = 0; b < RS; ++b) {
+        int64_t bb, be;
+        bucket(a, b, &bb, &be);
+        nq += be - bb;
       }
-      o->wi_tile.push_back(t1 * NT + t2);
-      int64_t k = 0;
-      for (int a = 0; a < RS; ++a)
-        for (int b = 0; b < RS; ++b) {
-          o->wi_boff.push_back((uint16_t)k);
-          int64_t bb, be;
-          bucket(a, b, &bb, &be);
-          for (int64_t i = bb; i < be; ++i, ++k) {
-            const int32_t r = cell_rows[(size_t)i];
-            o->q_row.push_back(r);
-            o->q_val.insert(o->q_val.end(), wv.begin() + (size_t)r * W2, wv.begin() + (size_t)(r + 1) * W2);
-          }
+    if (nq > o->QMAX) {
+      for (int a = 0; a < TS; ++a)
+        for (int b = 0; b < TS; ++b) {
+          const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
+          if (j1 <= G - 1 - oG && j2 <= G - 1 - oG)
+            o->dense_cell[(size_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = 1;
         }
-      o->wi_boff.push_back((uint16_t)k);
-      o->wi_q.push_back((int32_t)o->q_row.size());
+      continue;
     }
+    o->wi_tile.push_back(t1 * NT + t2);
+    int64_t k = 0;
+    for (int a = 0; a < RS; ++a)
+      for (int b = 0; b < RS; ++b) {
+        o->wi_boff.push_back((uint16_t)k);
+        int64_t bb, be;
+        bucket(a, b, &bb, &be);
+        for (int64_t i = bb; i < be; ++i, ++k) {
+          const int32_t r = cell_rows[(size_t)i];
+          o->q_row.push_back(r);
+          o->q_val.insert(o->q_val.end(), wv.begin() + (size_t)r * W2, wv.begin() + (size_t)(r + 1) * W2);
+        }
+      }
+    o->wi_boff.push_back((uint16_t)k);
+    o->wi_q.push_back((int32_t)o->q_row.size());
+  }
   if (o->q_row.size() >= (size_t)INT32_MAX) return fail(TOMO_EINVAL, "staged adjoint layout too large");
   return TOMO_OK;
 }

@@ -75,6 +75,7 @@ struct Tuning {
   int det_fft = 1;            // detector transforms: fused hand-written (1, L = 2^m) or library (0)
   int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1, G = 2^m) or library (0)
   int sell_tiles = 1;         // sliced-ELL rows in 4 x 8 Cartesian tiles (1) or grid order (0)
+  int tile_strip = 32;        // staged kernels visit tiles in strips this many tiles wide (0 = rows)
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout

@@ -242,6 +242,8 @@ TUNINGS = [
     dict(fwd_tiled=7, adj_tiled=7, tile=8, tile_points=64, adj_tile_points=128),
     dict(fwd_tiled=7, adj_tiled=7, tile=16, tile_points=128, adj_tile_points=256),
     dict(fwd_tiled=2, adj_tiled=1),                                  # staged for one value type
+    dict(fwd_tiled=7, adj_tiled=7, tile_strip=0),                    # row-major tile order
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, tile_strip=3, adj_tile_points=64),   # ragged strips
     dict(fwd_tiled=0, adj_tiled=7, adj_sell_max=4, adj_medium_max=16, adj_chunk=24),
     dict(ROW, adj_sell_xcd_rows=64, adj_medium_xcd_rows=8),       # short XCD interleave runs
     dict(ROW, adj_sell_xcd_rows=0, adj_medium_xcd_rows=0),        # one contiguous range per XCD
@@ -328,4 +330,24 @@ def test_staged_adjoint_on_a_side_stream_matches_the_default_stream(tomo):
     for vt in ("f32", "bf16"):
         assert torch.equal(outs[vt], ref[vt]), vt
     assert torch.equal(again, ref["bf16"])
+    op.close()
+
+
+def test_tile_visiting_order_does_not_change_the_results(tomo):
+    """The staged kernels' tile order (strips of tiles, or row-major) only moves work between
+    blocks: every order gives the same products bit for bit, in every value type."""
+    n, nt, npb, batch = 96, 120, 137, 12
+    op = _gpu_op(tomo, n, nt, npb, {}, max_batch=12, values=("f32", "bf16", "f16"))
+    op.set_tuning(fwd_tiled=7, adj_tiled=7, tile=8, tile_points=64, adj_tile_points=64)
+    X = _dev(_rand(tuple(op.cart_shape(batch)), 960))
+    Y = _dev(_rand(tuple(op.polar_shape(batch)), 961))
+    ref = None
+    for strip in (0, 1, 3, 5, 32):
+        op.set_tuning(tile_strip=strip)
+        out = [op.slice_fwd(X, batch, values=vt).clone() for vt in ("f32", "bf16", "f16")]
+        out += [op.slice_adj(Y, batch, values=vt).clone() for vt in ("f32", "bf16", "f16")]
+        if ref is None:
+            ref = out
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), strip
     op.close()

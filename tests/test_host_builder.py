@@ -106,7 +106,8 @@ def test_tuning_rejects_out_of_range():
     op = tomo.Operator(device=-1, max_batch=2, n=16, n_angles=12, n_det=23)
     before = op.get_tuning()
     for bad in (dict(fwd_channels_per_lane=3), dict(adj_sell_max=-1), dict(adj_chunk=4),
-                dict(adj_medium_max=10, adj_sell_max=20), dict(adj_sell_sigma=0)):
+                dict(adj_medium_max=10, adj_sell_max=20), dict(adj_sell_sigma=0),
+                dict(tile_strip=-1), dict(tile_strip=4097)):
         with pytest.raises(tomo.TomoError):
             op.set_tuning(**bad)
         assert op.get_tuning() == before
@@ -158,7 +159,9 @@ def test_host_only_operator_rejects_apply():
 @pytest.mark.parametrize("tuning", [{}, dict(tile=8, tile_points=32, adj_tile_points=32),
                                     dict(tile=16, tile_points=64, adj_tile_points=256),
                                     dict(adj_sell_max=4, adj_medium_max=20, adj_chunk=8, adj_sell_sigma=3),
-                                    dict(adj_sell_tiles=1, adj_sell_max=24)])
+                                    dict(adj_sell_tiles=1, adj_sell_max=24),
+                                    dict(tile_strip=0), dict(tile_strip=3, adj_tile_points=64),
+                                    dict(tile=16, tile_strip=5)])
 def test_kernel_layouts_replay_the_csr_products(d, tuning):
     """Every device layout (fixed-stride forward, sliced-ELL / wave / chunked adjoint, LDS-staged
     window-form tiles, and the row layout of the staged adjoint's dense cells) replayed on the
