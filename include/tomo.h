@@ -121,7 +121,7 @@ typedef struct {
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB (and for k_w 3 or 5), else the
  * row kernels.
- * Defaults (in field order): 2, 4, 48, 4096, 128, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32. */
+ * Defaults (in field order): 2, 4, 64, 4096, 256, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */

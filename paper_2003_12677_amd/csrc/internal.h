@@ -58,9 +58,9 @@ struct HostCSR {
 struct Tuning {
   int fwd_cpl = 2;        // complex channels per lane in the forward kernel (1, 2 or 4)
   int adj_cpl = 4;        // complex channels per lane in the adjoint row kernels (1, 2 or 4)
-  int sell_max = 48;      // S rows with <= sell_max entries: sliced ELL, 8 rows per slice
+  int sell_max = 64;      // S rows with <= sell_max entries: sliced ELL, 8 rows per slice
   int sell_sigma = 4096;  // rows are sorted by length within windows of sell_sigma rows
-  int medium_max = 128;   // longer rows up to medium_max entries: one wavefront per row
+  int medium_max = 256;   // longer rows up to medium_max entries: one wavefront per row
   int chunk = 1024;       // rows above medium_max: chunks of <= chunk entries, one block each
   // staged kernels per value type: bit vt (1 f32, 2 bf16, 4 f16) set = staged, clear = rows
   int fwd_tiled = 7;      // forward: LDS-staged Cartesian tiles
