@@ -149,58 +149,50 @@ def test_zero_slice_stays_at_rounding_level(tomo):
 
 
 def test_bf16_refinement_matches_oracle(tomo):
-    """Outer residuals with float32 values, inner CGLS with bfloat16 values (R x I).
+    """Outer residuals with float32 values, inner CGLS with bfloat16 values (R x I), against the
+    float64 refinement with the same rounded values.
 
-    Short inner solves (I = 3, before float32 CGLS iterates separate from float64 ones) are held
-    to the spread of float32 oracle realisations.  With I = 8 the separation depends on the
-    rounding sequence: kernel layouts whose single applications all agree with the oracle to
-    1.5e-7 put one of these slices anywhere from 1.4e-5 to 6e-4 from it, beyond the random
-    noise model's reach, and their data misfit ||A x - b|| up to 1.1e-4 from the oracle's.  There
-    the image is bounded at 2e-3 and the misfit at 1e-3 relative, as for long CGLS runs."""
+    Both bounds come from float32 oracle realisations (``krylov_tolerance``): the oracle's
+    refinement with float32 storage and relative noise on every operator output.
+    * Short inner solves (I = 3, before float32 CGLS iterates separate from float64 ones): noise
+      at the float32 level of one application (5e-7), image and misfit both tight.
+    * Longer inner solves (I = 8): the separation amplifies rounding differences
+      super-linearly (i.i.d. noise of 5e-7 moves the image by 2e-5, 5e-6 by 6e-4, and the spread
+      saturates near 3e-3 once the near-null components dominate), and real kernels round
+      coherently rather than independently, so the measured per-application error of a kernel
+      layout does not bound its solve.  What every layout is held to is the operator parity
+      tolerance, 1e-5 relative per application; the realisations are run at that noise level, so
+      the bounds cover any implementation whose single applications pass parity (about 2e-3 for
+      the image, 7e-4 for the misfit)."""
     n, nt, npb, B = 64, 90, 91, 2
     b = _sinograms(n, nt, npb, B, 530)
     op = tomo.Operator(n, nt, npb, max_batch=B, values=("f32", "bf16"), device=0)
     hi = oracle_op(n, nt, npb)
     hi32 = OracleOperator(hi.geom, S=round_values(hi.S, "f32"))
     lo = OracleOperator(hi.geom, S=round_values(hi.S, "bf16"))
-    for R, I in ((3, 3), (3, 8)):
+    for R, I, eps in ((3, 3, 5e-7), (3, 8, 1e-5)):
         xg = _host(op.solve(_dev(b), iters=I, refine_outer=R, values="bf16"))
         for s in range(B):
             bs = r32(b[s])
             xr = refine(hi32.project, lo.project, lo.backproject, bs, R, I)
+            mis_r = np.linalg.norm(hi.project(xr) - bs)
+            runs = []
 
             def run(rng):
-                return refine(noisy_fp32(hi32.project, rng), noisy_fp32(lo.project, rng),
-                              noisy_fp32(lo.backproject, rng), bs, R, I, store=r32)
+                x = refine(noisy_fp32(hi32.project, rng, eps), noisy_fp32(lo.project, rng, eps),
+                           noisy_fp32(lo.backproject, rng, eps), bs, R, I, store=r32)
+                runs.append(x)
+                return x
 
+            tol = krylov_tolerance(run, xr)
+            mis_dev = max(abs(np.linalg.norm(hi.project(x) - bs) - mis_r) for x in runs) / mis_r
+            mis_tol = 2.0 * mis_dev + 1e-6
             err = rel_l2(xg[s], xr)
             mis_g = np.linalg.norm(hi.project(xg[s]) - bs)
-            mis_r = np.linalg.norm(hi.project(xr) - bs)
-            print(f"slice {s}: refinement {R}x{I} (bf16 inner) GPU vs oracle {err:.3e}, "
-                  f"misfit {mis_g:.6e} vs {mis_r:.6e}")
-            if I <= 3:
-                assert err < krylov_tolerance(run, xr), s
-            else:
-                assert err < 2e-3, s
-                assert abs(mis_g - mis_r) < 1e-3 * mis_r, s
-    op.close()
-
-
-def test_cgls_configuration_2_sampled_slices(tomo):
-    """512^2 slices, 360 angles, 724 bins, batch 64 with Poisson noise at I0 = 1e4, 50 CGLS
-    iterations on the GPU; the oracle recomputes two sampled slices."""
-    n, nt, npb, B, iters = 512, 360, 724, 64, 50
-    b = _sinograms(n, nt, npb, B, 2000, noisy=True)
-    op = tomo.Operator(n, nt, npb, max_batch=B, device=0)
-    xg = _host(op.solve(_dev(b), iters=iters))
-    ref = oracle_op(n, nt, npb)
-    for s in (0, B - 1):
-        bs = r32(b[s])
-        xr = cgls(ref.project, ref.backproject, bs, iters)
-        err = rel_l2(xg[s], xr)
-        print(f"slice {s}: CGLS-{iters} at 512^2 GPU vs FP64 oracle {err:.3e}")
-        assert err < krylov_tolerance(_cgls_model(ref, bs, iters), xr, realizations=3), s
-        assert rel_l2(ref.project(xg[s]), ref.project(xr)) < 2e-3
+            print(f"slice {s}: refinement {R}x{I} (bf16 inner) GPU vs oracle {err:.3e} (bound "
+                  f"{tol:.3e}), misfit {mis_g:.6e} vs {mis_r:.6e} (relative bound {mis_tol:.2e})")
+            assert err < tol, s
+            assert abs(mis_g - mis_r) < mis_tol * mis_r, s
     op.close()
 
 
