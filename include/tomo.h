@@ -285,6 +285,20 @@ tomo_status tomo_export_normal(const tomo_op* op, int32_t filter, double* w);
 tomo_status tomo_tv(tomo_op* op, const float* x, int32_t batch, double eps, double weight,
                     float* grad, double* value, void* stream);
 
+/* tomo_tv for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and results, bit for bit,
+ * with the per-(slice, block) float64 reduction partials in a file-scope device array of the
+ * library instead of a buffer the operator allocates on first use.  Allocates nothing (no
+ * hipMalloc, hipFree or allocating library call); the caller passes x, grad and value as for
+ * tomo_tv.  Limit: batch * min(256, ceil(n*n / 256)) <= 65536 partials (512 KiB, held by each GPU
+ * the library runs on until the process ends); every batch an operator accepts fits, and larger
+ * requests return TOMO_EINVAL.  The array is shared by every call on one GPU (each call writes
+ * every partial it reads, so nothing needs clearing): calls that overlap on one GPU, from any
+ * operator or stream, race.  The first call on a device looks up the array's device address
+ * (hipGetSymbolAddress).  Errors: as tomo_tv, plus TOMO_EHIP if that lookup fails. */
+tomo_status tomo_tv_noalloc(const tomo_op* op, const float* x, int32_t batch, double eps,
+                            double weight, float* grad, double* value, void* stream);
+
 /* Sizes and statistics of a built operator (host only, no synchronisation). */
 tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out);
 

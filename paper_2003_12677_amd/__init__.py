@@ -94,6 +94,7 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "tomo_export_normal": (ctypes.c_int, [_P, _I, _P]),
     "tomo_tv": (ctypes.c_int, [_P, _P, _I, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "tomo_tv_noalloc": (ctypes.c_int, [_P, _P, _I, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "tomo_density_filter": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_double)]),
     "tomo_export_density": (ctypes.c_int, [_P, _P]),
     "tomo_graph_create": (ctypes.c_int, [ctypes.POINTER(tomo_step), _I, ctypes.POINTER(_P)]),
@@ -387,6 +388,20 @@ class Operator:
         _check(_lib.tomo_tv(self._handle, _ptr(x), B, float(eps), float(weight), _ptr(g), _ptr(v),
                             _stream(self.device)))
         return v, g
+
+    def tv_noalloc(self, x: torch.Tensor, value: torch.Tensor | None, grad: torch.Tensor | None,
+                   eps: float = 1e-8, weight: float = 1.0) -> None:
+        """``tomo_tv_noalloc``: as :meth:`tv` into caller-given ``value`` (float64 [B]) and
+        ``grad`` (like x) tensors, either may be None; the library allocates nothing."""
+        B = x.shape[0]
+        _need(x, self._image_shape(B), self.device, "x")
+        if grad is not None:
+            _need(grad, self._image_shape(B), self.device, "grad")
+        if value is not None and (value.dtype != torch.float64 or tuple(value.shape) != (B,)
+                                  or not value.is_cuda or value.device.index != self.device):
+            raise ValueError(f"value must be a float64 tensor of shape ({B},) on cuda:{self.device}")
+        _check(_lib.tomo_tv_noalloc(self._handle, _ptr(x), B, float(eps), float(weight), _ptr(grad),
+                                    _ptr(value), _stream(self.device)))
 
 class Graph:
     """``tomo_graph_create``: several operators' steps recorded as one HIP graph.

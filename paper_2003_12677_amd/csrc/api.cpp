@@ -580,9 +580,10 @@ tomo_status tomo_export_normal(const tomo_op* op, int32_t filter, double* w) {
   return TOMO_OK;
 }
 
-tomo_status tomo_tv(tomo_op* op, const float* x, int32_t batch, double eps, double weight,
-                    float* grad, double* value, void* stream) {
-  clear_error();
+namespace {
+
+tomo_status check_tv(const tomo_op* op, const float* x, int32_t batch, double eps, double weight,
+                     const float* grad, const double* value) {
   if (!op) return fail(TOMO_EINVAL, "operator is NULL");
   if (op->device < 0) return fail(TOMO_ESTATE, "operator was built without a device");
   if (batch < 0 || batch > op->g.max_batch)
@@ -592,9 +593,31 @@ tomo_status tomo_tv(tomo_op* op, const float* x, int32_t batch, double eps, doub
   if (batch > 0 && !x) return fail(TOMO_EINVAL, "NULL image pointer");
   if (batch > 0 && (misaligned(x, 4) || misaligned(grad, 4) || misaligned(value, 8)))
     return fail(TOMO_EINVAL, "misaligned pointer");
+  return TOMO_OK;
+}
+
+}  // namespace
+
+tomo_status tomo_tv(tomo_op* op, const float* x, int32_t batch, double eps, double weight,
+                    float* grad, double* value, void* stream) {
+  clear_error();
+  const tomo_status s = check_tv(op, x, batch, eps, weight, grad, value);
+  if (s != TOMO_OK) return s;
   if (batch == 0 || (!grad && !value)) return TOMO_OK;
   DeviceGuard guard(op->device);
   return launch_tv(op, x, batch, eps, weight, grad, value, (hipStream_t)stream);
+}
+
+tomo_status tomo_tv_noalloc(const tomo_op* op, const float* x, int32_t batch, double eps,
+                            double weight, float* grad, double* value, void* stream) {
+  clear_error();
+  const tomo_status s = check_tv(op, x, batch, eps, weight, grad, value);
+  if (s != TOMO_OK) return s;
+  if (batch == 0 || (!grad && !value)) return TOMO_OK;
+  DeviceGuard guard(op->device);
+  if (guard.err != hipSuccess)
+    return fail(TOMO_EHIP, "hipSetDevice(%d): %s", op->device, hipGetErrorString(guard.err));
+  return launch_tv_noalloc(op, x, batch, eps, weight, grad, value, (hipStream_t)stream);
 }
 
 tomo_status tomo_op_info_get(const tomo_op* op, tomo_op_info* out) {

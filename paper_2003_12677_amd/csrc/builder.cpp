@@ -83,8 +83,8 @@ tomo_status resolve_geometry(const tomo_geometry* in, Geom* g) {
     return fail(TOMO_EINVAL, "kernel width kw=%d must be odd and in [1, 15]", r.kw);
   r.h = (r.kw - 1) / 2;
   r.max_batch = in->max_batch;
-  if (r.max_batch < 1 || r.max_batch > 256)
-    return fail(TOMO_EINVAL, "max_batch=%d must be in [1, 256]", r.max_batch);
+  if (r.max_batch < 1 || r.max_batch > tomo::kMaxBatch)
+    return fail(TOMO_EINVAL, "max_batch=%d must be in [1, %d]", r.max_batch, tomo::kMaxBatch);
   if (in->reserved != 0) return fail(TOMO_EINVAL, "reserved field must be 0");
   r.values = in->values ? in->values : TOMO_VALUES_F32;
   if (r.values & ~(uint32_t)(TOMO_VALUES_F32 | TOMO_VALUES_BF16 | TOMO_VALUES_F16))

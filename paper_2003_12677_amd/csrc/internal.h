@@ -276,6 +276,7 @@ tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int3
                         int32_t values);
 
 constexpr int kDotBlocks = 256;   // blocks per slice in the FP64 reductions
+constexpr int kMaxBatch = 256;    // largest max_batch an operator accepts
 
 // FFT plans for C complex channels (created on first use).
 tomo_status get_plans(tomo_op* op, int C, FFTPlans** out);
@@ -324,6 +325,9 @@ void free_solver(tomo_op* op);
 // (nullable, device [B] float64) = weight * TV per slice.
 tomo_status launch_tv(tomo_op* op, const float* x, int B, double eps, double weight, float* grad,
                       double* value, hipStream_t st);
+// tomo_tv with its reduction partials in the library's file-scope scratch array (no allocation)
+tomo_status launch_tv_noalloc(const tomo_op* op, const float* x, int B, double eps, double weight,
+                              float* grad, double* value, hipStream_t st);
 void free_tv(tomo_op* op);
 
 // Normal operator on the channel-slowest Cartesian grid: Out[c][j] = sum over the stencil of

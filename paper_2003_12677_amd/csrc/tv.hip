@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -19,6 +20,19 @@ namespace tomo {
 namespace {
 
 constexpr int kTvBlock = 256;
+
+// Reduction partials of tomo_tv_noalloc: one float64 per (slice, block), for the largest batch
+// an operator accepts.  A file-scope device array (each GPU holds its own copy from the first use
+// until the process ends), so that entry point allocates nothing.  Every call on one GPU shares
+// it: calls that overlap on a GPU race.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a host-side stand-in); it passes the device address looked up once per
+// device by tv_scratch().
+constexpr int kTvScratchDoubles = kMaxBatch * kDotBlocks;
+__device__ __align__(256) double scratch[kTvScratchDoubles];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
 
 __device__ __forceinline__ double tv_wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -92,11 +106,62 @@ __global__ __launch_bounds__(kTvBlock) void k_tv_final(const double* __restrict_
 
 }  // namespace
 
+namespace {
+
+int tv_blocks(const tomo_op* op) {
+  const int64_t npix = (int64_t)op->g.n * op->g.n;
+  return (int)std::min<int64_t>(kDotBlocks, (npix + kTvBlock - 1) / kTvBlock);
+}
+
+// The TV kernels with the per-(slice, block) float64 partials in `partial` (>= B * nblk
+// doubles; unused when value is NULL).  Every partial a call reads is written by the same call
+// first, so the buffer needs no clearing.
+tomo_status run_tv(const tomo_op* op, const float* x, int B, double eps, double weight, float* grad,
+                   double* value, double* partial, hipStream_t st) {
+  const int n = op->g.n;
+  const int nblk = tv_blocks(op);
+  const dim3 grid((unsigned)nblk, (unsigned)B);
+  const float fe = (float)eps, fw = (float)weight;
+  if (grad && value)
+    hipLaunchKernelGGL((k_tv<true, true>), grid, dim3(kTvBlock), 0, st, x, n, fe, fw, grad,
+                       partial);
+  else if (grad)
+    hipLaunchKernelGGL((k_tv<true, false>), grid, dim3(kTvBlock), 0, st, x, n, fe, fw, grad,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_tv<false, true>), grid, dim3(kTvBlock), 0, st, x, n, fe, fw, nullptr,
+                       partial);
+  TOMO_HIP(hipGetLastError());
+  if (value) {
+    hipLaunchKernelGGL(k_tv_final, dim3((unsigned)B), dim3(kTvBlock), 0, st, partial, nblk,
+                       weight, value);
+    TOMO_HIP(hipGetLastError());
+  }
+  return TOMO_OK;
+}
+
+// Device address of `scratch` on `device` (which must be current), looked up on first use.
+tomo_status tv_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(TOMO_EINVAL, "device %d outside the %d devices the TV scratch array serves", device,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TOMO_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = (double*)p;
+  }
+  *out = g_scratch_ptr[device];
+  return TOMO_OK;
+}
+
+}  // namespace
+
 tomo_status launch_tv(tomo_op* op, const float* x, int B, double eps, double weight, float* grad,
                       double* value, hipStream_t st) {
-  const int n = op->g.n;
-  const int64_t npix = (int64_t)n * n;
-  const int nblk = (int)std::min<int64_t>(kDotBlocks, (npix + kTvBlock - 1) / kTvBlock);
   if (value && !op->tv_partial) {
     const size_t bytes = (size_t)op->g.max_batch * kDotBlocks * sizeof(double);
     if (hipMalloc(&op->tv_partial, bytes) != hipSuccess) {
@@ -104,24 +169,21 @@ tomo_status launch_tv(tomo_op* op, const float* x, int B, double eps, double wei
       return fail(TOMO_ENOMEM, "TV reduction buffer of %zu bytes", bytes);
     }
   }
-  const dim3 grid((unsigned)nblk, (unsigned)B);
-  const float fe = (float)eps, fw = (float)weight;
-  if (grad && value)
-    hipLaunchKernelGGL((k_tv<true, true>), grid, dim3(kTvBlock), 0, st, x, n, fe, fw, grad,
-                       op->tv_partial);
-  else if (grad)
-    hipLaunchKernelGGL((k_tv<true, false>), grid, dim3(kTvBlock), 0, st, x, n, fe, fw, grad,
-                       nullptr);
-  else
-    hipLaunchKernelGGL((k_tv<false, true>), grid, dim3(kTvBlock), 0, st, x, n, fe, fw, nullptr,
-                       op->tv_partial);
-  TOMO_HIP(hipGetLastError());
+  return run_tv(op, x, B, eps, weight, grad, value, op->tv_partial, st);
+}
+
+tomo_status launch_tv_noalloc(const tomo_op* op, const float* x, int B, double eps, double weight,
+                              float* grad, double* value, hipStream_t st) {
+  const int64_t need = (int64_t)B * tv_blocks(op);
+  if (need > kTvScratchDoubles)
+    return fail(TOMO_EINVAL, "batch %d needs %lld TV partials, beyond the scratch array's %d", B,
+                (long long)need, kTvScratchDoubles);
+  double* partial = nullptr;
   if (value) {
-    hipLaunchKernelGGL(k_tv_final, dim3((unsigned)B), dim3(kTvBlock), 0, st, op->tv_partial,
-                       nblk, weight, value);
-    TOMO_HIP(hipGetLastError());
+    const tomo_status s = tv_scratch(op->device, &partial);
+    if (s != TOMO_OK) return s;
   }
-  return TOMO_OK;
+  return run_tv(op, x, B, eps, weight, grad, value, partial, st);
 }
 
 void free_tv(tomo_op* op) {
