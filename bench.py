@@ -142,6 +142,30 @@ def _oracle_slices(budget_s: float, max_slices: int, seed: int):
 
 _ORACLE = {}
 
+
+def host_cpu():
+    """CPU model and physical core count of this host (lscpu), and the cores this process may use."""
+    import subprocess
+
+    model, sockets, per_socket = None, None, None
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "Model name":
+                model = v
+            elif k == "Socket(s)":
+                sockets = int(v)
+            elif k == "Core(s) per socket":
+                per_socket = int(v)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    physical = sockets * per_socket if sockets and per_socket else None
+    return {"cpu_model": model, "physical_cores": physical,
+            "usable_cores": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(budget_s: float):
     """The FP64 oracle's forward and adjoint sparse products (S^dagger U, S V') per slice on the
     host: one process, then one process per usable host core, each on its own slices (the
@@ -155,7 +179,9 @@ def cpu_baseline(budget_s: float):
     _ORACLE["op"] = Operator(Geometry(N_IMG, N_ANG, N_DET))
     build_s = time.perf_counter() - t0
     one, el1 = _oracle_slices(budget_s, 64, 0)
-    cores = min(16, len(os.sched_getaffinity(0)))
+    host = host_cpu()
+    # one process per core this job may use, at most 16: the host share one GPU's job is given
+    cores = min(16, host["usable_cores"])
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -168,6 +194,7 @@ def cpu_baseline(budget_s: float):
             "sample": f"{done} slices of S^dagger U + S V' (scipy CSR, complex128 vectors) in "
                       f"{cores} concurrent processes, about {budget_s:.0f} s each ({wall:.1f} s "
                       f"wall); operator build {build_s:.1f} s not timed",
+            "host": dict(host, note="processes are capped at 16, the host CPU share of a one-GPU job"),
             "single_process": {"value": one / el1, "cores": 1,
                                "sample": f"{one} slices in {el1:.1f} s"}}
 
@@ -286,6 +313,111 @@ def accuracy_leg(torch, tomo, op, ref):
     return res
 
 
+STACK_SLICES, STACK_ITERS = 256, 100
+
+
+def _stack_slice(s: int):
+    """Slice s of the 2048^2 stack: exact ellipse line integrals with Poisson noise (I0 = 1e4) in
+    pixel units as float32, and the phantom rasterised with 2x2 supersampling."""
+    import math
+
+    import numpy as np
+
+    from synth import (ellipse_params, ellipse_sinogram, poisson_log_sinogram,
+                       rasterize_ellipses, slice_rng)
+
+    th = np.arange(N_ANG) * math.pi / N_ANG
+    rng = slice_rng(5000 + s)
+    E = ellipse_params(rng, 10, contained=True)
+    P = poisson_log_sinogram(rng, ellipse_sinogram(E, th, N_DET, N_DET // 2, N_IMG), 1e4)
+    return (P / (2.0 / N_IMG)).astype(np.float32), rasterize_ellipses(E, N_IMG, 2).astype(np.float32)
+
+
+def stack_inputs():
+    """One batch of 32 phantom slices and their noisy sinograms, made by a process pool before
+    the GPU is touched."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    procs = min(16, len(os.sched_getaffinity(0)), BATCH)
+    with mp.get_context("fork").Pool(procs) as pool:
+        out = pool.map(_stack_slice, range(BATCH))
+    return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
+
+
+def stack_leg(torch, op, inputs):
+    """The 2048^2 / 1501 / 2048 reconstruction workload: a 256-slice stack streamed through the
+    GPU in batches of 32, CGLS-100 per batch, as plain float32, with bf16 values, and as float32
+    iterative refinement (4 outer float32 residuals of 25 inner iterations with bf16 values, the
+    inner solves as CGLS or as CG on the normal equations through the bf16 normal-operator
+    stencil).  Errors: relative L2 against the phantoms of one batch (32 slices); times: the
+    whole stack (8 batches; the speed does not depend on the values)."""
+    import numpy as np
+
+    sino, truth = inputs
+    dev = torch.device("cuda:0")
+    b = torch.from_numpy(sino).to(dev)
+    t = torch.from_numpy(truth).to(dev)
+    forms = {"cgls_f32": dict(iters=STACK_ITERS),
+             "cgls_bf16": dict(iters=STACK_ITERS, values="bf16"),
+             "cgnr_f32": dict(iters=STACK_ITERS, method="cgnr"),
+             "mixed_cgls_bf16_4x25": dict(iters=STACK_ITERS // 4, refine_outer=4, values="bf16"),
+             "mixed_cgnr_bf16_4x25": dict(iters=STACK_ITERS // 4, refine_outer=4, values="bf16",
+                                          method="cgnr")}
+    x = torch.empty((BATCH, N_IMG, N_IMG), device=dev)
+    res = {"workload": f"{STACK_SLICES} slices of 2048^2, 1501 angles, 2048 bins in batches of "
+                       f"{BATCH}; {STACK_ITERS} iterations per batch",
+           "inputs": "exact line integrals of 10 random ellipses per slice with Poisson noise "
+                     "(I0 = 1e4), float32; phantoms rasterised with 2x2 supersampling",
+           "error_slices": BATCH}
+    for name, kw in forms.items():
+        op.solve(b, x, **kw)
+        err = ((x - t).flatten(1).norm(dim=1) / t.flatten(1).norm(dim=1)).cpu().numpy().astype(np.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(STACK_SLICES // BATCH):
+            op.solve(b, x, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"stack_seconds": el, "slices_per_s": STACK_SLICES / el,
+                     "rel_l2_vs_phantom": {"mean": float(err.mean()), "min": float(err.min()),
+                                           "max": float(err.max())}}
+    ref = res["cgls_f32"]
+    for name in ("mixed_cgls_bf16_4x25", "mixed_cgnr_bf16_4x25", "cgls_bf16", "cgnr_f32"):
+        res[name]["time_over_cgls_f32"] = res[name]["stack_seconds"] / ref["stack_seconds"]
+        res[name]["phantom_error_over_cgls_f32"] = (res[name]["rel_l2_vs_phantom"]["mean"] /
+                                                     ref["rel_l2_vs_phantom"]["mean"])
+    return res
+
+
+def paper_comparison(torch, tomo, gen):
+    """The paper's only GPU throughput figure is for iRadon (filtered back projection incl. the
+    FFTs) of a 2048-slice stack with 2048 angles and 2048 bins.  The same operation here: one
+    MI355X, tomo_irradon with the Hamming-windowed ramp on batches of 32 slices at (2048 angles,
+    2048 bins, 2048^2 pixels), float32 values."""
+    dev = torch.device("cuda:0")
+    op = tomo.Operator(N_IMG, 2048, N_DET, max_batch=BATCH, device=0)
+    y = torch.rand((BATCH, 2048, N_DET), generator=gen, device=dev)
+    x = torch.empty((BATCH, N_IMG, N_IMG), device=dev)
+    op.irradon(y, x)
+    ms = time_loop(torch, lambda: op.irradon(y, x), 10)
+    op.close()
+    return {"ours": {"what": "tomo_irradon, 2048^2 pixels, 2048 angles, 2048 bins, batch 32, f32 values",
+                     "gpus": "1 x MI355X", "slices_per_s": BATCH / (ms * 1e-3), "ms_per_batch": ms},
+            "paper": [
+                {"what": "iRadon of (n_z, n_theta, n_p) = (2048, 2048, 2048)", "seconds": 1.55,
+                 "hardware": "16 x NVIDIA V100 16 GB (Cori GPU nodes)", "slices_per_s": 2048 / 1.55,
+                 "slices_per_s_per_gpu": 2048 / 1.55 / 16, "section": "Sec. 4 (Cori GPU results)"},
+                {"what": "iRadon of (2048, 2048, 2048)", "seconds": 4.11,
+                 "hardware": "256 Intel Haswell cores (8 Cori nodes), MPI", "slices_per_s": 2048 / 4.11,
+                 "section": "Sec. 4 (Cori CPU results)"},
+                {"what": "iRadon of the bread-crumb scan (n_z, n_theta, n_p) = (128, 1313, 3620)",
+                 "seconds": 4.0, "hardware": "8 GPUs of 4 x NVIDIA K80 (CAM)", "slices_per_s": 128 / 4.0,
+                 "section": "Sec. 4 (experimental data)"}],
+            "note": "context, not a target: other hardware, and the paper states no precision"}
+
+
 def uneven_leg(torch, tomo):
     """200 slices with sizes drawn from {256, 512, 1024, 2048}^2 (seeded), 0.75 N angles,
     round(N sqrt 2) bins, fp16 matrix values: one operator per size, autotuned for batches of
@@ -324,7 +456,8 @@ def uneven_leg(torch, tomo):
                                            "fwd_rows_per_group",
                                            "fwd_channels_per_lane", "adj_channels_per_lane",
                                            "adj_sell_max", "adj_medium_max",
-                                           "adj_sell_xcd_rows", "adj_medium_xcd_rows")},
+                                           "adj_sell_xcd_rows", "adj_medium_xcd_rows",
+                                           "adj_dense_mode", "adj_seg_chunks", "adj_run")},
                                  "tuned_ms_b32": [tune["fwd_ms"], tune["adj_ms"]]})
 
     def run_eager():
@@ -341,6 +474,39 @@ def uneven_leg(torch, tomo):
     graph.close()
     res.update(steps=len(steps), eager_ms=ms_e, graph_ms=ms_g,
                eager_slices_per_s=200 / (ms_e * 1e-3), graph_slices_per_s=200 / (ms_g * 1e-3))
+    # the same SpMM pairs as one persistent forward and one persistent adjoint launch over every
+    # operator's staged work (the stack needs the dense tiles staged: adj_dense_mode >= 1)
+    ops = []
+    for st in steps:
+        if st["op"] not in ops:
+            ops.append(st["op"])
+    # one kernel per operator set needs one tile side for all (8, the default) and the dense tiles
+    # staged (adj_dense_mode >= 1)
+    for op in ops:
+        tun = op.get_tuning()
+        op.set_tuning(tile=8, adj_dense_mode=max(1, tun["adj_dense_mode"]))
+    stack = tomo.Stack([dict(op=st["op"], batch=st["batch"], inp=st["inp"], out=st["out"], aux=st["aux"])
+                        for st in steps], values="f16")
+    stack.launch()
+    torch.cuda.synchronize()
+    cg = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(cg, stream=side):
+            stack.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(3):
+        stack.launch()
+        cg.replay()
+    ms_s = time_loop(torch, stack.launch, 20)
+    ms_sg = time_loop(torch, cg.replay, 20)
+    stack.close()
+    res.update(stack_ms=ms_s, stack_graph_ms=ms_sg, stack_slices_per_s=200 / (ms_s * 1e-3),
+               stack_graph_slices_per_s=200 / (ms_sg * 1e-3),
+               stack_what="one persistent forward kernel + one persistent adjoint kernel (+ split-"
+                          "tile sums) over device work lists of every operator's batches (tile side "
+                          "8 and staged dense tiles on every operator)")
     return res
 
 
@@ -399,6 +565,7 @@ def main():
         sys.exit(2)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
     acc_ref = accuracy_reference() if args.accuracy else None
+    stack_in = stack_inputs() if args.extras else None
     import torch
 
     import paper_2003_12677_amd as tomo
@@ -482,7 +649,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"spmm_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"spmm_{dom}_bf16", op.get_tuning()),
-                     "algorithmic_bytes": m[f"{dom}_bytes"], "frac_of_copy": achieved / copy_gbs},
+                     "algorithmic_bytes": m[f"{dom}_bytes"], "frac_of_copy": achieved / copy_gbs,
+                     "step": {"what": "forward + adjoint SpMM step (the metric's fwd+adj)",
+                              "algorithmic_bytes": m["fwd_bytes"] + m["adj_bytes"],
+                              "achieved": (m["fwd_bytes"] + m["adj_bytes"]) / ms_step / 1e6,
+                              "frac": (m["fwd_bytes"] + m["adj_bytes"]) / ms_step / 1e6 / HBM_PEAK_GBS}},
         "copy_GBs": {"value": copy_gbs, "what": "torch copy_ of 1 GiB (read + write bytes / time)"},
         "kernels": res,
         "fp32_values": {"value": BATCH / (ms_f32 * 1e-3), "ms_per_step": ms_f32},
@@ -526,6 +697,14 @@ def main():
         ms_sb1 = time_loop(torch, lambda: op.solve(y, xb, refine_outer=1, **sb), 2)
         out["tv_split_bregman"] = {"ms_per_bregman_step_f32": (ms_sb3 - ms_sb1) / 2,
                                    "cg_steps_per_bregman_step": 5, "batch": BATCH}
+        out["stack_2048"] = stack_leg(torch, op, stack_in)
+        st = out["stack_2048"]
+        best = min(("mixed_cgls_bf16_4x25", "mixed_cgnr_bf16_4x25"), key=lambda k: st[k]["stack_seconds"])
+        out["mixed_vs_fp32_reconstruction"] = {
+            "mixed_form": best, "fp32_form": "cgls_f32",
+            "time_ratio": st[best]["time_over_cgls_f32"],
+            "phantom_error_ratio": st[best]["phantom_error_over_cgls_f32"]}
+        out["paper_comparison"] = paper_comparison(torch, tomo, gen)
     if acc_ref is not None:
         out["accuracy"] = accuracy_leg(torch, tomo, op, acc_ref)
     if args.uneven:

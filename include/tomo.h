@@ -121,7 +121,7 @@ typedef struct {
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB (and for k_w 3 or 5), else the
  * row kernels.
- * Defaults (in field order): 2, 4, 64, 4096, 256, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32. */
+ * Defaults (in field order): 2, 4, 64, 4096, 256, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32, 1, 8, 1. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -168,6 +168,20 @@ typedef struct {
                                      strip width earlier and their shared halo samples are still
                                      in the XCD's L2 (0 = row-major over the whole grid); results
                                      do not depend on it; 0..4096                              */
+  int32_t adj_dense_mode;         /* staged adjoint, tiles whose region holds more than
+                                     adj_tile_points samples (near the Fourier origin): 0 = the
+                                     row kernels on their cells (on two more streams); 1 = staged
+                                     too, in chunks of <= adj_tile_points samples, one block per
+                                     segment of <= adj_seg_chunks chunks accumulating in
+                                     registers (a tile with several segments is summed from
+                                     partial tiles in a fixed order), on a second stream beside
+                                     the other tiles; 2 = the same segments and the other tiles
+                                     in one launch, the dense segments first                  */
+  int32_t adj_seg_chunks;         /* chunks per segment of a dense tile (1..256)             */
+  int32_t adj_run;                /* adj_dense_mode 2: the other staged tiles go to blocks in runs
+                                     of this many tiles (in the visiting order), each block
+                                     loading the next tile while it sums the current one
+                                     (1..256)                                                 */
 } tomo_tuning;
 
 /* Solver selection and options for tomo_solve (Sec. 2.1; Sec. 3.1 lists SIRT and CGLS). */
@@ -326,8 +340,10 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* t);
 /* Autotuner: search the SpMM layout parameters for `batch` slices with value type `values` by
  * timing tomo_slice_fwd / tomo_slice_adj on the operator's own work buffers (hashed inputs;
  * HIP events on a private stream), one parameter at a time over short candidate lists
- * (forward rows per group and channels per lane; adjoint channels per lane, sliced-ELL and
- * wave-per-row bounds, XCD interleave runs), `rounds` passes (1..8).  The fastest setting is
+ * (staged or row kernels per value type, tile side and capacities, tile visiting order, the
+ * staged adjoint's dense-tile form, segment length and tile runs; forward rows per group and
+ * channels per lane; adjoint channels per lane, sliced-ELL and wave-per-row bounds, XCD
+ * interleave runs), `rounds` passes (1..8).  The fastest setting is
  * applied to the operator and returned in *best (nullable), with its times in *fwd_ms /
  * *adj_ms (nullable).  Synchronises the device; results of the operator do not depend on the
  * tuning except through float32 summation order.  Overwrites the operator's work buffers, so
@@ -372,6 +388,41 @@ tomo_status tomo_graph_create(const tomo_step* steps, int32_t n, tomo_graph** ou
 tomo_status tomo_graph_launch(tomo_graph* g, void* stream);
 /* Free the graph (NULL is a no-op); does not synchronise. */
 void tomo_graph_destroy(tomo_graph* g);
+
+/* Persistent SpMM pairs over a stack of operators (uneven stacks, Sec. 3.1: slices in batches,
+ * one setup per geometry): item i computes out_i = S_i^dagger in_i, then aux_i = S_i out_i, like
+ * TOMO_STEP_SPMM_PAIR, for its operator and batch.  A launch runs one forward kernel whose blocks
+ * walk a device work list of (item, staged work item, channel chunk) and one adjoint kernel over
+ * (item, segment, channel chunk) with the operators' dense-tile segments first (longest first),
+ * then one small kernel that sums split dense tiles; nothing else (no allocation, copy or memset),
+ * so a launch may be captured in a HIP graph.  Results equal the items' own tomo_slice_fwd /
+ * tomo_slice_adj with the staged kernels, up to float32 summation order.
+ * Requirements: operators on one device, one kernel width and tile side, the staged layouts
+ * (k_w 3 or 5, tile 8 or 16) with adj_dense_mode 1 or 2, value type `values` built for every
+ * operator.  Buffers as tomo_slice_fwd / tomo_slice_adj (in: [G*G][C], out: [L*nt][C],
+ * aux: [G*G][C] complex64, C = ceil(batch/2), 16-byte aligned); the stack holds the pointers, so
+ * they and the operators must stay alive (and not be re-tuned) while it is used.  Launches of one
+ * stack, and calls on its operators, must not overlap.  tomo_stack_create allocates the work
+ * lists and each item's partial tiles (synchronous).
+ * Errors: TOMO_EINVAL (bad item, mixed devices / kernel widths / tiles, adj_dense_mode 0),
+ * TOMO_ESTATE, TOMO_EUNSUPPORTED (no staged layout), TOMO_ENOMEM, TOMO_EHIP. */
+typedef struct {
+  tomo_op* op;
+  int32_t batch;         /* slices (1 .. the operator's max_batch)                          */
+  int32_t reserved;      /* must be 0                                                        */
+  const float* in;
+  float* out;
+  float* aux;
+} tomo_stack_item;
+
+typedef struct tomo_stack tomo_stack;
+
+tomo_status tomo_stack_create(const tomo_stack_item* items, int32_t n, int32_t values,
+                              tomo_stack** out);
+/* Enqueue the stack's kernels on `stream` (a hipStream_t; NULL = the null stream). */
+tomo_status tomo_stack_launch(tomo_stack* s, void* stream);
+/* Free the stack (NULL is a no-op); does not synchronise. */
+void tomo_stack_destroy(tomo_stack* s);
 
 /* Density filter (Sec. 3): per-polar-sample weights D_v ~ arg min ||S D_v - c 1|| over the
  * Cartesian grid, c = kappa(0)^2 the mass of the separable gridding kernel, among weights even

@@ -60,7 +60,9 @@ class tomo_tuning(ctypes.Structure):
                 ("normal_tiled", ctypes.c_int32), ("adj_sell_xcd_rows", ctypes.c_int32),
                 ("adj_medium_xcd_rows", ctypes.c_int32), ("fwd_rows_per_group", ctypes.c_int32),
                 ("det_fft", ctypes.c_int32), ("grid_fft", ctypes.c_int32),
-                ("adj_sell_tiles", ctypes.c_int32), ("tile_strip", ctypes.c_int32)]
+                ("adj_sell_tiles", ctypes.c_int32), ("tile_strip", ctypes.c_int32),
+                ("adj_dense_mode", ctypes.c_int32), ("adj_seg_chunks", ctypes.c_int32),
+                ("adj_run", ctypes.c_int32)]
 
 
 class tomo_solve_opts(ctypes.Structure):
@@ -81,6 +83,10 @@ class tomo_step(ctypes.Structure):
 
 STEPS = {"spmm_pair": 0, "project": 1, "backproject": 2, "normal": 3}
 
+
+class tomo_stack_item(ctypes.Structure):
+    _fields_ = [("op", _P), ("batch", _I), ("reserved", _I), ("inp", _P), ("out", _P), ("aux", _P)]
+
 SIGNATURES = {
     "tomo_build_operator": (ctypes.c_int, [ctypes.POINTER(tomo_geometry), ctypes.c_int, ctypes.POINTER(_P)]),
     "tomo_project": (ctypes.c_int, [_P, _P, _P, _I, _I, _P]),
@@ -100,6 +106,9 @@ SIGNATURES = {
     "tomo_graph_create": (ctypes.c_int, [ctypes.POINTER(tomo_step), _I, ctypes.POINTER(_P)]),
     "tomo_graph_launch": (ctypes.c_int, [_P, _P]),
     "tomo_graph_destroy": (None, [_P]),
+    "tomo_stack_create": (ctypes.c_int, [ctypes.POINTER(tomo_stack_item), _I, _I, ctypes.POINTER(_P)]),
+    "tomo_stack_launch": (ctypes.c_int, [_P, _P]),
+    "tomo_stack_destroy": (None, [_P]),
     "tomo_op_info_get": (ctypes.c_int, [_P, ctypes.POINTER(tomo_op_info)]),
     "tomo_export_csr": (ctypes.c_int, [_P, _I, _P, _P, _P]),
     "tomo_export_factors": (ctypes.c_int, [_P, _I, _P, _P]),
@@ -445,3 +454,41 @@ def build_operator(*args, **kwargs) -> Operator:
 
 def version() -> str:
     return load().tomo_version().decode()
+
+
+class Stack:
+    """``tomo_stack_create``: persistent SpMM pairs over several operators.  ``items`` is a list
+    of dicts with keys ``op`` (:class:`Operator`), ``batch`` and the tensors ``inp`` (Cartesian
+    input), ``out`` (polar product) and ``aux`` (adjoint of ``out``); all items use the value
+    type ``values``.  The stack keeps references to the operators and tensors."""
+
+    def __init__(self, items, values: str = "f32"):
+        self._keep = list(items)
+        self._handle = None
+        arr = (tomo_stack_item * len(items))()
+        dev = items[0]["op"].device
+        for k, it in enumerate(items):
+            op, b = it["op"], it["batch"]
+            _need(it["inp"], op.cart_shape(b), dev, "inp")
+            _need(it["out"], op.polar_shape(b), dev, "out")
+            _need(it["aux"], op.cart_shape(b), dev, "aux")
+            arr[k] = tomo_stack_item(op._handle, b, 0, it["inp"].data_ptr(), it["out"].data_ptr(),
+                                     it["aux"].data_ptr())
+        self.device = dev
+        h = ctypes.c_void_p()
+        _check(_lib.tomo_stack_create(arr, len(items), VALUES[values], ctypes.byref(h)))
+        self._handle = h
+
+    def launch(self) -> None:
+        _check(_lib.tomo_stack_launch(self._handle, _stream(self.device)))
+
+    def close(self) -> None:
+        if self._handle is not None and _lib is not None:
+            _lib.tomo_stack_destroy(self._handle)
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtomo.so")
 SOURCES = ["builder.cpp", "fft.cpp", "api.cpp", "spmm.hip", "tiles.hip", "layout.hip", "solver.hip", "tv.hip", "normal.hip",
-           "autotune.cpp", "graph.cpp", "fft1d.hip", "fft2d.hip"]
+           "autotune.cpp", "graph.cpp", "fft1d.hip", "fft2d.hip", "stack.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

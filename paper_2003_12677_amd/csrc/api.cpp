@@ -5,6 +5,8 @@
 #include <cstring>
 #include <memory>
 
+#include <complex>
+
 #include "internal.h"
 
 namespace tomo {
@@ -119,7 +121,10 @@ void free_tiles(tomo_op* op) {
   DevAdjWin& a = op->awin;
   dfree(a.wi_tile); dfree(a.wi_q); dfree(a.wi_boff); dfree(a.q_row);
   for (auto& v : a.q_val) dfree(v);
+  dfree(a.seg_tile); dfree(a.seg_chunk); dfree(a.seg_slot); dfree(a.red_tile); dfree(a.red_slot);
+  dfree(a.chunk_tile);
   a = DevAdjWin();
+  dfree(op->seg_partials);
   free_adj_layout(op->adj_dense);
 }
 
@@ -150,6 +155,27 @@ tomo_status upload_tiles(tomo_op* op) {
     TOMO_TRY(upload(&d.wi_boff, h.wi_boff.data(), h.wi_boff.size()));
     TOMO_TRY(upload(&d.q_row, h.q_row.data(), h.q_row.size()));
     TOMO_TRY(upload_values(h.q_val, op->g.values, d.q_val));
+    d.n_wi = h.n_wi;
+    d.n_sseg = h.n_sseg;
+    d.n_seg = (int64_t)h.seg_tile.size();
+    d.max_seg_chunks = 0;
+    for (size_t i = 0; i + 1 < h.seg_chunk.size(); ++i)
+      d.max_seg_chunks = std::max(d.max_seg_chunks, h.seg_chunk[i + 1] - h.seg_chunk[i]);
+    TOMO_TRY(upload(&d.chunk_tile, h.chunk_tile.data(), h.chunk_tile.size()));
+    d.n_red = (int64_t)h.red_tile.size();
+    d.n_slot = h.red_slot.empty() ? 0 : (int64_t)h.red_slot.back();
+    TOMO_TRY(upload(&d.seg_tile, h.seg_tile.data(), h.seg_tile.size()));
+    TOMO_TRY(upload(&d.seg_chunk, h.seg_chunk.data(), h.seg_chunk.size()));
+    TOMO_TRY(upload(&d.seg_slot, h.seg_slot.data(), h.seg_slot.size()));
+    TOMO_TRY(upload(&d.red_tile, h.red_tile.data(), h.red_tile.size()));
+    TOMO_TRY(upload(&d.red_slot, h.red_slot.data(), h.red_slot.size()));
+    if (d.n_slot > 0) {
+      const size_t pb = (size_t)d.n_slot * h.TS * h.TS * op->cmax * sizeof(float2);
+      if (hipMalloc((void**)&op->seg_partials, pb) != hipSuccess) {
+        op->seg_partials = nullptr;
+        return fail(TOMO_ENOMEM, "staged adjoint partial tiles (%zu B)", pb);
+      }
+    }
     // dense cells: the row kernels' layout over those cells (its long rows are a subset of the
     // full layout's, so the long-row partial-sum buffer already fits them)
     HostAdj hd;
@@ -180,14 +206,91 @@ void free_device(tomo_op* op) {
   for (auto& v : op->fwd.val) dfree(v);
   free_adj(op);
   dfree(op->kd_dev);
-  dfree(op->tw1);
-  dfree(op->tw2);
+  for (auto* t : {&op->dft1, &op->dft2}) {
+    dfree(t->tw);
+    dfree(t->chirp);
+    dfree(t->bhat_f);
+    dfree(t->bhat_i);
+    *t = fftk::DftTables();
+  }
   dfree(op->dens);
   for (auto& f : op->filt_dev) dfree(f);
   dfree(op->X);
   dfree(op->Y);
   dfree(op->Xs);
   dfree(op->Ys);
+}
+
+// Tables of the hand-written DFTs of length N (computed in double): for N = 2^m in [16, 4096] the
+// twiddles exp(-2 pi i j / N); for other N in [16, 4096] Bluestein's chirp conj(w_n) =
+// exp(-i pi n^2 / N) and, at the power-of-two length M >= 2N - 1, the twiddles and the DFTs of
+// the convolution kernels w (forward) and conj(w) (inverse) wrapped to negative indices, times 1/M
+// (the DFT in double by the direct sum would be O(M^2); a radix-2 FFT in double is used).
+tomo_status upload_dft_tables(int N, fftk::DftTables* t) {
+  *t = fftk::DftTables();
+  if (N < 16 || N > 4096) return TOMO_OK;
+  const bool pow2 = (N & (N - 1)) == 0;
+  int M = N;
+  if (!pow2)
+    for (M = 16; M < 2 * N - 1; M *= 2) {
+    }
+  auto twiddles = [](int m) {
+    std::vector<std::complex<double>> tw(m);
+    for (int j = 0; j < m; ++j) tw[j] = std::polar(1.0, -2.0 * M_PI * (double)j / (double)m);
+    return tw;
+  };
+  auto to_f2 = [](const std::vector<std::complex<double>>& v, double scale) {
+    std::vector<float2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i)
+      o[i] = make_float2((float)(v[i].real() * scale), (float)(v[i].imag() * scale));
+    return o;
+  };
+  const std::vector<std::complex<double>> tw = twiddles(M);
+  float2* d_tw = nullptr;
+  TOMO_TRY(upload(&d_tw, to_f2(tw, 1.0).data(), (size_t)M));
+  t->tw = d_tw;
+  t->N = N;
+  t->M = M;
+  if (pow2) return TOMO_OK;
+  // w_m = exp(+i pi m^2 / N) with m^2 reduced mod 2N first (exact in integers)
+  auto w = [&](int64_t m) { return std::polar(1.0, M_PI * (double)((m * m) % (2 * (int64_t)N)) / N); };
+  std::vector<std::complex<double>> chirp(N);
+  for (int n = 0; n < N; ++n) chirp[n] = std::conj(w(n));
+  // in-place iterative radix-2 DFT (forward sign) of a length-M sequence in double
+  auto dft = [&](std::vector<std::complex<double>>& a) {
+    for (int i = 1, j = 0; i < M; ++i) {
+      int bit = M >> 1;
+      for (; j & bit; bit >>= 1) j ^= bit;
+      j ^= bit;
+      if (i < j) std::swap(a[i], a[j]);
+    }
+    for (int len = 2; len <= M; len <<= 1)
+      for (int i = 0; i < M; i += len)
+        for (int k = 0; k < len / 2; ++k) {
+          const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * tw[(size_t)k * (M / len)];
+          a[i + k] = u + v;
+          a[i + k + len / 2] = u - v;
+        }
+  };
+  std::vector<std::complex<double>> bf(M, 0.0), bi(M, 0.0);
+  for (int m = 0; m < N; ++m) {
+    bf[m] = w(m);
+    bi[m] = std::conj(w(m));
+    if (m > 0) {
+      bf[M - m] = bf[m];
+      bi[M - m] = bi[m];
+    }
+  }
+  dft(bf);
+  dft(bi);
+  float2 *d_chirp = nullptr, *d_bf = nullptr, *d_bi = nullptr;
+  TOMO_TRY(upload(&d_chirp, to_f2(chirp, 1.0).data(), (size_t)N));
+  t->chirp = d_chirp;
+  TOMO_TRY(upload(&d_bf, to_f2(bf, 1.0 / M).data(), (size_t)M));
+  t->bhat_f = d_bf;
+  TOMO_TRY(upload(&d_bi, to_f2(bi, 1.0 / M).data(), (size_t)M));
+  t->bhat_i = d_bi;
+  return TOMO_OK;
 }
 
 tomo_status upload_all(tomo_op* op) {
@@ -217,19 +320,8 @@ tomo_status upload_all(tomo_op* op) {
     std::vector<float> df(d.begin(), d.end());
     TOMO_TRY(upload(&op->filt_dev[f], df.data(), df.size()));
   }
-  // twiddles exp(-2 pi i j / m) of the hand-written transforms (m = L detector, m = G grid),
-  // from double, for power-of-two sizes
-  auto twiddles = [](int m, float2** dst) -> tomo_status {
-    if (m < 16 || m > 4096 || (m & (m - 1)) != 0) return TOMO_OK;
-    std::vector<float2> tw(m);
-    for (int j = 0; j < m; ++j) {
-      const double ang = -2.0 * M_PI * (double)j / (double)m;
-      tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
-    return upload(dst, tw.data(), tw.size());
-  };
-  TOMO_TRY(twiddles(g.L, &op->tw1));
-  TOMO_TRY(twiddles(g.G, &op->tw2));
+  TOMO_TRY(upload_dft_tables(g.L, &op->dft1));
+  TOMO_TRY(upload_dft_tables(g.G, &op->dft2));
   const size_t xb = (size_t)g.G * g.G * op->cmax * sizeof(float2);
   const size_t yb = (size_t)g.L * g.nt * op->cmax * sizeof(float2);
   if (hipMalloc((void**)&op->X, xb) != hipSuccess) {
@@ -265,9 +357,6 @@ tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int3
   if (batch > 0 && (!in || !out)) return fail(TOMO_EINVAL, "NULL data pointer");
   if (batch > 0 && (misaligned(in, 16) || misaligned(out, 16)))
     return fail(TOMO_EINVAL, "data pointers must be 16-byte aligned");
-  const int C = (batch + 1) / 2;
-  if (C % 2 == 1 && C > 64)
-    return fail(TOMO_EUNSUPPORTED, "odd channel counts above 64 (batch %d) are not supported", batch);
   if (values < 0 || values > 2) return fail(TOMO_EINVAL, "unknown value type %d", values);
   if (!(op->values & (1u << values)))
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", values);
@@ -287,9 +376,15 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
     TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
     TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
   }
-  TOMO_TRY(launch_to_channel_fastest(op->Xs, op->X, (int64_t)g.G * g.G, C, st));
-  TOMO_TRY(launch_spmm_fwd(op, op->X, op->Y, C, vt, st));
-  TOMO_TRY(launch_polar_to_slowest(op->Y, op->Ys, g.L, g.nt, C, st));
+  if (spmm_fwd_slowest_ok(op, C, vt)) {
+    // the staged forward reads its patches from the FFT-side grid and writes the FFT-side polar
+    // rows itself
+    TOMO_TRY(launch_spmm_fwd(op, op->Xs, op->Ys, C, vt, st, true));
+  } else {
+    TOMO_TRY(launch_to_channel_fastest(op->Xs, op->X, (int64_t)g.G * g.G, C, st));
+    TOMO_TRY(launch_spmm_fwd(op, op->X, op->Y, C, vt, st));
+    TOMO_TRY(launch_polar_to_slowest(op->Y, op->Ys, g.L, g.nt, C, st));
+  }
   if (op->tune.det_fft && det_fft_supported(op))
     return launch_det_inverse_crop(op, op->Ys, y, B, 1.0f / (float)g.L, st);
   TOMO_TRY(fft_exec(p->inv1, p, op->Ys, st));
@@ -316,8 +411,13 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
     TOMO_TRY(launch_scale_rows(op->Y, op->dens, (int64_t)g.L * g.nt, C, st));
   else if (filter != TOMO_FILTER_NONE)
     ds = op->filt_dev[filter];
-  TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
-  TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
+  if (spmm_adj_slowest_ok(op, C, vt)) {
+    // the staged adjoint writes its tiles into the FFT-side grid itself
+    TOMO_TRY(launch_spmm_adj(op, op->Y, op->Xs, C, vt, ds, st, true));
+  } else {
+    TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
+    TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
+  }
   if (op->tune.grid_fft && grid_fft_supported(op))
     return launch_grid_inverse(op, op->Xs, x, B, extra_scale / (float)g.L, st);
   TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
@@ -702,6 +802,9 @@ tomo_status tomo_get_tuning(const tomo_op* op, tomo_tuning* out) {
   out->grid_fft = op->tune.grid_fft;
   out->adj_sell_tiles = op->tune.sell_tiles;
   out->tile_strip = op->tune.tile_strip;
+  out->adj_dense_mode = op->tune.adj_dense_mode;
+  out->adj_seg_chunks = op->tune.adj_seg_chunks;
+  out->adj_run = op->tune.adj_run;
   return TOMO_OK;
 }
 
@@ -728,6 +831,9 @@ tomo_status tomo_set_tuning(tomo_op* op, const tomo_tuning* in) {
   t.grid_fft = in->grid_fft;
   t.sell_tiles = in->adj_sell_tiles;
   t.tile_strip = in->tile_strip;
+  t.adj_dense_mode = in->adj_dense_mode;
+  t.adj_seg_chunks = in->adj_seg_chunks;
+  t.adj_run = in->adj_run;
   return apply_tuning(op, t);
 }
 
@@ -741,7 +847,9 @@ tomo_status apply_tuning(tomo_op* op, const Tuning& t) {
                         t.medium_max != op->tune.medium_max || t.chunk != op->tune.chunk;
   // the staged adjoint's dense cells use a row layout with the same bins, so it is rebuilt too
   const bool retile = relayout || t.tile != op->tune.tile || t.tile_points != op->tune.tile_points ||
-                      t.adj_tile_points != op->tune.adj_tile_points || t.tile_strip != op->tune.tile_strip;
+                      t.adj_tile_points != op->tune.adj_tile_points || t.tile_strip != op->tune.tile_strip ||
+                      t.adj_dense_mode != op->tune.adj_dense_mode ||
+                      t.adj_seg_chunks != op->tune.adj_seg_chunks || t.adj_run != op->tune.adj_run;
   op->tune = t;
   if (op->device < 0) {
     if (relayout) build_adj_layout(op->s, op->tune, &op->hadj);

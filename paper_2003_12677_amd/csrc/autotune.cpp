@@ -86,6 +86,9 @@ tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms,
       {[](Tuning& t) -> int& { return t.tile_points; }, {32, 64, 96, 128}, kFwd},
       {[](Tuning& t) -> int& { return t.adj_tile_points; }, {64, 96, 128, 160, 192, 256}, kAdj},
       {[](Tuning& t) -> int& { return t.tile_strip; }, {0, 16, 32, 128}, kBoth},
+      {[](Tuning& t) -> int& { return t.adj_dense_mode; }, {0, 1, 2}, kAdj},
+      {[](Tuning& t) -> int& { return t.adj_seg_chunks; }, {2, 4, 8, 16}, kAdj},
+      {[](Tuning& t) -> int& { return t.adj_run; }, {1, 4, 16}, kAdj},
       {[](Tuning& t) -> int& { return t.fwd_rows_per_group; }, {1, 2, 4}, kFwd},
       {[](Tuning& t) -> int& { return t.fwd_cpl; }, {1, 2, 4}, kFwd},
       {[](Tuning& t) -> int& { return t.adj_cpl; }, {1, 2, 4}, kAdj},
@@ -105,8 +108,13 @@ tomo_status autotune(tomo_op* op, int batch, int vt, int rounds, double* fwd_ms,
         if (v == p.field(best) || check_tuning(t) != TOMO_OK) continue;
         TOMO_TRY(apply_tuning(op, t));
         double f = bf, a = ba;
-        if (p.side != kAdj) TOMO_TRY(measure_fwd(&f));
-        if (p.side != kFwd) TOMO_TRY(measure_adj(&a));
+        // a setting the channel count rules out (row kernels with an odd count above 64) is
+        // refused before launching anything: skip it
+        if ((p.side != kAdj && measure_fwd(&f) != TOMO_OK) ||
+            (p.side != kFwd && measure_adj(&a) != TOMO_OK)) {
+          clear_error();
+          continue;
+        }
         if (f + a < bf + ba) {
           best = t;
           bf = f;

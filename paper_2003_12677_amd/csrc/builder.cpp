@@ -244,6 +244,11 @@ tomo_status check_tuning(const Tuning& t) {
   if (t.grid_fft != 0 && t.grid_fft != 1) return fail(TOMO_EINVAL, "grid_fft must be 0 or 1");
   if (t.sell_tiles != 0 && t.sell_tiles != 1) return fail(TOMO_EINVAL, "adj_sell_tiles must be 0 or 1");
   if (t.tile_strip < 0 || t.tile_strip > 4096) return fail(TOMO_EINVAL, "tile_strip must be in [0, 4096]");
+  if (t.adj_dense_mode < 0 || t.adj_dense_mode > 2) return fail(TOMO_EINVAL, "adj_dense_mode must be 0, 1 or 2");
+  if (t.adj_seg_chunks < 1 || t.adj_seg_chunks > kMaxSegChunks)
+    return fail(TOMO_EINVAL, "adj_seg_chunks must be in [1, %d]", kMaxSegChunks);
+  if (t.adj_run < 1 || t.adj_run > kMaxSegChunks)
+    return fail(TOMO_EINVAL, "adj_run must be in [1, %d]", kMaxSegChunks);
   if (t.fwd_rows_per_group != 1 && t.fwd_rows_per_group != 2 && t.fwd_rows_per_group != 4)
     return fail(TOMO_EINVAL, "fwd_rows_per_group must be 1, 2 or 4");
   if (!cpl_ok(t.fwd_cpl) || !cpl_ok(t.adj_cpl))
@@ -395,8 +400,14 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
   for (int i = 0; i < ntiles; ++i) count[i + 1] += count[i];
   std::vector<int32_t> order(N);
   {
+    // within a tile, samples by angle, then radius (rows visited as a * L + kf), so that a work
+    // item's outputs form runs of consecutive radii in the channel-slowest polar layout
     std::vector<int64_t> next(count.begin(), count.end() - 1);
-    for (int64_t r = 0; r < N; ++r) order[next[rank_of_row[r]]++] = (int32_t)r;
+    for (int a = 0; a < g.nt; ++a)
+      for (int64_t kf = 0; kf < g.L; ++kf) {
+        const int64_t r = kf * g.nt + a;
+        order[next[rank_of_row[r]]++] = (int32_t)r;
+      }
   }
   o->pt_row = order;
   o->pt_base.assign((size_t)N, 0);
@@ -476,23 +487,43 @@ tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<
   }
   o->dense_cell.assign((size_t)G * G, 0);
   o->wi_q.push_back(0);
-  for (const int tl : tile_order(NT, t.tile_strip)) {
-    const int t1 = tl / NT, t2 = tl % NT;
-    // region cell (a, b) is extended-grid cell (t1*TS + a, t2*TS + b)
-    auto bucket = [&](int a, int b, int64_t* beg, int64_t* end) {
-      const int64_t e1 = (int64_t)t1 * TS + a, e2 = (int64_t)t2 * TS + b;
-      if (e1 >= E || e2 >= E) { *beg = *end = 0; return; }
-      *beg = cell_ptr[(size_t)(e1 * E + e2)];
-      *end = cell_ptr[(size_t)(e1 * E + e2) + 1];
-    };
-    int64_t nq = 0;
+  std::vector<int> dense_tiles;
+  // a tile's samples in bucket order (region cells row-major), with offsets bo[RS*RS + 1]
+  auto tile_samples = [&](int t1, int t2, std::vector<int32_t>* rows, std::vector<int64_t>* bo) {
+    rows->clear();
+    bo->clear();
     for (int a = 0; a < RS; ++a)
       for (int b = 0; b < RS; ++b) {
-        int64_t bb, be;
-        bucket(a, b, &bb, &be);
-        nq += be - bb;
+        bo->push_back((int64_t)rows->size());
+        const int64_t e1 = (int64_t)t1 * TS + a, e2 = (int64_t)t2 * TS + b;
+        if (e1 >= E || e2 >= E) continue;
+        for (int64_t i = cell_ptr[(size_t)(e1 * E + e2)]; i < cell_ptr[(size_t)(e1 * E + e2) + 1]; ++i)
+          rows->push_back(cell_rows[(size_t)i]);
       }
+    bo->push_back((int64_t)rows->size());
+  };
+  // one chunk: samples [s0, s1) of a tile's list, bucket offsets clipped to the chunk
+  auto push_chunk = [&](const std::vector<int32_t>& rows, const std::vector<int64_t>& bo, int64_t s0,
+                        int64_t s1) {
+    for (const int64_t b : bo) o->wi_boff.push_back((uint16_t)(std::min(std::max(b, s0), s1) - s0));
+    for (int64_t i = s0; i < s1; ++i) {
+      const int32_t r = rows[(size_t)i];
+      o->q_row.push_back(r);
+      o->q_val.insert(o->q_val.end(), wv.begin() + (size_t)r * W2, wv.begin() + (size_t)(r + 1) * W2);
+    }
+    o->wi_q.push_back((int32_t)o->q_row.size());
+  };
+  std::vector<int32_t> rows;
+  std::vector<int64_t> bo;
+  for (const int tl : tile_order(NT, t.tile_strip)) {
+    const int t1 = tl / NT, t2 = tl % NT;
+    tile_samples(t1, t2, &rows, &bo);
+    const int64_t nq = (int64_t)rows.size();
     if (nq > o->QMAX) {
+      if (t.adj_dense_mode != 0) {
+        dense_tiles.push_back(tl);
+        continue;
+      }
       for (int a = 0; a < TS; ++a)
         for (int b = 0; b < TS; ++b) {
           const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
@@ -501,22 +532,44 @@ tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<
         }
       continue;
     }
-    o->wi_tile.push_back(t1 * NT + t2);
-    int64_t k = 0;
-    for (int a = 0; a < RS; ++a)
-      for (int b = 0; b < RS; ++b) {
-        o->wi_boff.push_back((uint16_t)k);
-        int64_t bb, be;
-        bucket(a, b, &bb, &be);
-        for (int64_t i = bb; i < be; ++i, ++k) {
-          const int32_t r = cell_rows[(size_t)i];
-          o->q_row.push_back(r);
-          o->q_val.insert(o->q_val.end(), wv.begin() + (size_t)r * W2, wv.begin() + (size_t)(r + 1) * W2);
-        }
-      }
-    o->wi_boff.push_back((uint16_t)k);
-    o->wi_q.push_back((int32_t)o->q_row.size());
+    o->wi_tile.push_back(tl);
+    push_chunk(rows, bo, 0, nq);
   }
+  o->n_wi = (int64_t)o->wi_tile.size();
+  o->chunk_tile = o->wi_tile;
+  // staged tiles: segments of adj_run consecutive tiles in the visiting order
+  const int run = t.adj_dense_mode == 2 ? t.adj_run : 1;
+  for (int64_t w = 0; w < o->n_wi; w += run) {
+    o->seg_tile.push_back(o->wi_tile[(size_t)w]);
+    o->seg_chunk.push_back((int32_t)w);
+    o->seg_slot.push_back(-1);
+  }
+  o->n_sseg = (int64_t)o->seg_tile.size();
+  // dense tiles: chunks of nearly equal size (<= QMAX samples), segments of nearly equal chunk
+  // counts (<= adj_seg_chunks); a tile with several segments is summed from partial tiles
+  int32_t chunk = (int32_t)o->n_wi, slot = 0;
+  o->red_slot.push_back(0);
+  for (const int tl : dense_tiles) {
+    tile_samples(tl / NT, tl % NT, &rows, &bo);
+    const int64_t nq = (int64_t)rows.size();
+    const int64_t nch = (nq + o->QMAX - 1) / o->QMAX;
+    const int64_t nseg = (nch + t.adj_seg_chunks - 1) / t.adj_seg_chunks;
+    for (int64_t c = 0; c < nch; ++c) {
+      push_chunk(rows, bo, nq * c / nch, nq * (c + 1) / nch);
+      o->chunk_tile.push_back(tl);
+    }
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+      o->seg_tile.push_back(tl);
+      o->seg_chunk.push_back(chunk + (int32_t)(nch * sg / nseg));
+      o->seg_slot.push_back(nseg > 1 ? slot++ : -1);
+    }
+    chunk += (int32_t)nch;
+    if (nseg > 1) {
+      o->red_tile.push_back(tl);
+      o->red_slot.push_back(slot);
+    }
+  }
+  o->seg_chunk.push_back(chunk);
   if (o->q_row.size() >= (size_t)INT32_MAX) return fail(TOMO_EINVAL, "staged adjoint layout too large");
   return TOMO_OK;
 }
@@ -606,30 +659,67 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
   {  // staged adjoint (window form) and the row kernels on its dense cells
     HostAdjWin a;
     TOMO_TRY(build_adj_win(g, sdag, centres, t, &a));
-    const int RS = a.RS, h = g.h, kw = a.KW, NBO = RS * RS + 1;
+    const int RS = a.RS, h = g.h, kw = a.KW, NBO = RS * RS + 1, T2 = a.TS * a.TS;
     std::vector<double> out(M, std::nan(""));
-    for (size_t w = 0; w < a.wi_tile.size(); ++w) {
-      const int tl = a.wi_tile[w], t1 = tl / a.NT, t2 = tl % a.NT;
+    // the cell sums of one chunk added to acc[TS*TS], in the kernels' order
+    auto chunk_sums = [&](size_t w, std::vector<double>& acc) -> tomo_status {
       const int32_t q0 = a.wi_q[w];
       const uint16_t* bo = a.wi_boff.data() + w * (size_t)NBO;
       if (a.wi_q[w + 1] - q0 > a.QMAX || bo[NBO - 1] != a.wi_q[w + 1] - q0)
         return fail(TOMO_EINVAL, "internal: staged tile sample count");
       for (int m1 = 0; m1 < a.TS; ++m1)
-        for (int m2 = 0; m2 < a.TS; ++m2) {
-          const int j1 = -oG + t1 * a.TS + m1, j2 = -oG + t2 * a.TS + m2;
-          if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
-          double acc = 0;
+        for (int m2 = 0; m2 < a.TS; ++m2)
           for (int p1 = 0; p1 < kw; ++p1) {
             const int rb = (m1 + 2 * h - p1) * RS + m2;   // one run per window row
             for (int k = bo[rb]; k < bo[rb + kw]; ++k) {
               int t = 0;
               while (t + 1 < kw && k >= bo[rb + t + 1]) ++t;
               const int p2 = 2 * h - t;
-              acc += a.q_val[(size_t)(q0 + k) * a.W2 + p1 * kw + p2] * y[a.q_row[(size_t)(q0 + k)]];
+              acc[(size_t)(m1 * a.TS + m2)] +=
+                  a.q_val[(size_t)(q0 + k) * a.W2 + p1 * kw + p2] * y[a.q_row[(size_t)(q0 + k)]];
             }
           }
-          out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc;
+      return TOMO_OK;
+    };
+    auto store_tile = [&](int tl, const std::vector<double>& acc) {
+      const int t1 = tl / a.NT, t2 = tl % a.NT;
+      for (int m1 = 0; m1 < a.TS; ++m1)
+        for (int m2 = 0; m2 < a.TS; ++m2) {
+          const int j1 = -oG + t1 * a.TS + m1, j2 = -oG + t2 * a.TS + m2;
+          if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
+          out[(int64_t)((j1 % G + G) % G) * G + ((j2 % G + G) % G)] = acc[(size_t)(m1 * a.TS + m2)];
         }
+    };
+    // every segment (runs of staged tiles and dense-tile segments): chunks in order, a tile's
+    // sums stored when the next chunk belongs to another tile; then the split tiles' reductions
+    const size_t nseg = a.seg_tile.size();
+    if (a.seg_chunk.size() != nseg + 1 || a.wi_q.size() != (size_t)a.seg_chunk.back() + 1 ||
+        a.chunk_tile.size() + 1 != a.wi_q.size())
+      return fail(TOMO_EINVAL, "internal: segment list");
+    std::vector<std::vector<double>> slots;
+    for (size_t sg = 0; sg < nseg; ++sg) {
+      std::vector<double> acc((size_t)T2, 0.0);
+      const int32_t c0 = a.seg_chunk[sg], c1 = a.seg_chunk[sg + 1];
+      if (c1 - c0 > kMaxSegChunks) return fail(TOMO_EINVAL, "internal: segment too long");
+      for (int32_t c = c0; c < c1; ++c) {
+        TOMO_TRY(chunk_sums((size_t)c, acc));
+        if (c + 1 < c1 && a.chunk_tile[(size_t)c + 1] == a.chunk_tile[(size_t)c]) continue;
+        if (a.seg_slot[sg] < 0) {
+          store_tile(a.chunk_tile[(size_t)c], acc);
+        } else {
+          if ((size_t)a.seg_slot[sg] != slots.size() || c0 + 1 > c1 ||
+              a.chunk_tile[(size_t)c0] != a.chunk_tile[(size_t)c])
+            return fail(TOMO_EINVAL, "internal: partial slot order");
+          slots.push_back(acc);
+        }
+        std::fill(acc.begin(), acc.end(), 0.0);
+      }
+    }
+    for (size_t i = 0; i < a.red_tile.size(); ++i) {
+      std::vector<double> acc((size_t)T2, 0.0);
+      for (int32_t sl = a.red_slot[i]; sl < a.red_slot[i + 1]; ++sl)
+        for (int c = 0; c < T2; ++c) acc[(size_t)c] += slots[(size_t)sl][(size_t)c];
+      store_tile(a.red_tile[i], acc);
     }
     HostAdj hd;
     build_adj_layout(s, t, &hd, &a.dense_cell);

@@ -1,5 +1,6 @@
 // The detector-direction transforms of Eq. (2) fused with the layout steps around them, for a
-// power-of-two number L of polar samples per angle (16..4096):
+// power-of-two number L of polar samples per angle (16..4096), or any other L up to 4096 through
+// Bluestein's identity at the power-of-two length M >= 2L - 1 (fft_lds.h):
 //
 //   project tail:     Ys[C][nt][L] (the polar data after the tiled transpose from the forward
 //                     SpMM's channel-fastest output) -> inverse DFT of each row -> rotation-axis
@@ -30,39 +31,43 @@ using namespace fftk;
 
 // Ys[C][nt][L] (channel-slowest rows after the polar transpose) -> inverse DFT of each row ->
 // axis shift, scale, crop, slices 2c / 2c+1.  One block per (channel, AG consecutive angles):
-// its rows are one contiguous stretch of memory.
-template <int L, int AG>
+// its rows are one contiguous stretch of memory.  L = t.N: M for power-of-two L (BL = false),
+// else the DFTs go through Bluestein's identity at length M; LDS rows have stride M.
+template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restrict__ Ys,
-                                                          float* __restrict__ y,
-                                                          const float2* __restrict__ tw, int B,
-                                                          int nt, int np, int cdet, float scale) {
-  __shared__ float2 buf[lds_size<AG * L>()];
+                                                          float* __restrict__ y, DftTables t,
+                                                          int B, int nt, int np, int cdet, float scale) {
+  __shared__ float2 buf[lds_size<AG * M>()];
+  const int L = BL ? t.N : M;
   const int agroups = (nt + AG - 1) / AG;
   const int c = blockIdx.x / agroups, a0 = (blockIdx.x % agroups) * AG;
   const int na = min(AG, nt - a0);
   const float2* src = Ys + ((int64_t)c * nt + a0) * L;
   {
-    constexpr int NE = (AG * L + kFB - 1) / kFB;  // loads per thread, issued as one batch
+    constexpr int NE = (AG * M + kFB - 1) / kFB;  // loads per thread, issued as one batch
     float2 v[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
+      const int q = i / M, m = i % M;
       v[u] = make_float2(0.f, 0.f);
-      if (i < na * L) v[u] = src[i];
+      if (i < AG * M && q < na && m < L) v[u] = src[(int64_t)q * L + m];
     }
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
-      if (i < AG * L) buf[lds(i)] = v[u];
+      if (i < AG * M) buf[lds(i)] = v[u];
     }
   }
   __syncthreads();
-  fft_lds<L, AG, true>(buf, tw);
+  dft_lds<M, AG, true, BL>(buf, t);
   const int64_t plane = (int64_t)nt * np;
   const bool odd = 2 * c + 1 < B;
   for (int i = threadIdx.x; i < na * np; i += kFB) {
     const int q = i / np, b = i % np;
-    const float2 v = buf[lds(q * L + ((b - cdet) & (L - 1)))];
+    int m = b - cdet;                                 // bin b reads radial index (b - c) mod L
+    m += (m < 0) ? L : 0;
+    const float2 v = buf[lds(q * M + m)];
     const int64_t off = (int64_t)(a0 + q) * np + b;
     y[(int64_t)(2 * c) * plane + off] = v.x * scale;
     if (odd) y[(int64_t)(2 * c + 1) * plane + off] = v.y * scale;
@@ -71,27 +76,28 @@ __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restri
 
 // y[B][nt][np] -> pad with the axis shift, slices paired -> forward DFT of each row ->
 // Ys[C][nt][L] (channel-slowest rows; the polar transpose follows).
-template <int L, int AG>
+template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict__ y,
-                                                         float2* __restrict__ Ys,
-                                                         const float2* __restrict__ tw, int B,
-                                                         int nt, int np, int cdet) {
-  __shared__ float2 buf[lds_size<AG * L>()];
+                                                         float2* __restrict__ Ys, DftTables t,
+                                                         int B, int nt, int np, int cdet) {
+  __shared__ float2 buf[lds_size<AG * M>()];
+  const int L = BL ? t.N : M;
   const int agroups = (nt + AG - 1) / AG;
   const int c = blockIdx.x / agroups, a0 = (blockIdx.x % agroups) * AG;
   const int na = min(AG, nt - a0);
   const int64_t plane = (int64_t)nt * np;
   const bool odd = 2 * c + 1 < B;
   // elements per thread, loaded as one batch (all loads issued before the first LDS store)
-  constexpr int NE = (AG * L + kFB - 1) / kFB;
+  constexpr int NE = (AG * M + kFB - 1) / kFB;
   float2 v[NE];
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int i = threadIdx.x + u * kFB;
-    const int q = i / L, m = i % L;
-    const int b = (m + cdet) & (L - 1);
+    const int q = i / M, m = i % M;
+    int b = m + cdet;                                 // radial index m holds bin (m + c) mod L
+    b -= (b >= L) ? L : 0;
     v[u] = make_float2(0.f, 0.f);
-    if (i < AG * L && q < na && b < np) {
+    if (i < AG * M && q < na && m < L && b < np) {
       const int64_t off = (int64_t)(a0 + q) * np + b;
       v[u].x = y[(int64_t)(2 * c) * plane + off];
       if (odd) v[u].y = y[(int64_t)(2 * c + 1) * plane + off];
@@ -100,54 +106,50 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int i = threadIdx.x + u * kFB;
-    if (i < AG * L) buf[lds(i)] = v[u];
+    if (i < AG * M) buf[lds(i)] = v[u];
   }
   __syncthreads();
-  fft_lds<L, AG, false>(buf, tw);
+  dft_lds<M, AG, false, BL>(buf, t);
   float2* dst = Ys + ((int64_t)c * nt + a0) * L;
-  for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[lds(i)];
+  for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[lds((i / L) * M + i % L)];
 }
 
-template <int L>
+template <int M, bool BL>
 tomo_status det_launch(bool inverse, const tomo_op* op, const float2* Ysin, float2* Ysout,
                        const float* yin, float* yout, int B, float scale, hipStream_t st) {
   // about 32 KB of LDS per block, so that four blocks share a CU
-  constexpr int AG = L >= 2048 ? 2 : (4096 / L > 16 ? 16 : 4096 / L);
+  constexpr int AG = M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   const dim3 grid((unsigned)(C * ((g.nt + AG - 1) / AG)));
   if (inverse)
-    hipLaunchKernelGGL((k_det_inverse_crop<L, AG>), grid, dim3(kFB), 0, st, Ysin, yout, op->tw1,
+    hipLaunchKernelGGL((k_det_inverse_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Ysin, yout, op->dft1,
                        B, g.nt, g.np, g.cdet, scale);
   else
-    hipLaunchKernelGGL((k_det_pad_forward<L, AG>), grid, dim3(kFB), 0, st, yin, Ysout, op->tw1, B,
-                       g.nt, g.np, g.cdet);
+    hipLaunchKernelGGL((k_det_pad_forward<M, AG, BL>), grid, dim3(kFB), 0, st, yin, Ysout, op->dft1,
+                       B, g.nt, g.np, g.cdet);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
 
 tomo_status det_dispatch(bool inverse, const tomo_op* op, const float2* Yin, float2* Yout,
                          const float* yin, float* yout, int B, float scale, hipStream_t st) {
-  switch (op->g.L) {
-    case 16: return det_launch<16>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 32: return det_launch<32>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 64: return det_launch<64>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 128: return det_launch<128>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 256: return det_launch<256>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 512: return det_launch<512>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 1024: return det_launch<1024>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 2048: return det_launch<2048>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    case 4096: return det_launch<4096>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
-    default: return fail(TOMO_EUNSUPPORTED, "fused detector FFT needs L = 2^m in [16, 4096]");
+  const bool bl = op->dft1.M != op->g.L;
+#define TOMO_DET(M_)                                                                             \
+  case M_:                                                                                      \
+    return bl ? det_launch<M_, true>(inverse, op, Yin, Yout, yin, yout, B, scale, st)           \
+              : det_launch<M_, false>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
+  switch (op->dft1.M) {
+    TOMO_DET(16) TOMO_DET(32) TOMO_DET(64) TOMO_DET(128) TOMO_DET(256) TOMO_DET(512) TOMO_DET(1024)
+    TOMO_DET(2048) TOMO_DET(4096) TOMO_DET(8192)
+    default: return fail(TOMO_EUNSUPPORTED, "fused detector DFT: no kernel for length %d", op->dft1.M);
   }
+#undef TOMO_DET
 }
 
 }  // namespace
 
-bool det_fft_supported(const tomo_op* op) {
-  const int L = op->g.L;
-  return op->tw1 != nullptr && L >= 16 && L <= 4096 && (L & (L - 1)) == 0;
-}
+bool det_fft_supported(const tomo_op* op) { return op->dft1.tw != nullptr; }
 
 tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Ys, float* y, int B,
                                     float scale, hipStream_t st) {

@@ -1,5 +1,6 @@
-// The Cartesian 2D DFT of Eq. (2) fused with the steps around it, for a power-of-two grid side
-// G (16..4096), on the channel-slowest grid Xs[C][G][G]:
+// The Cartesian 2D DFT of Eq. (2) fused with the steps around it, on the channel-slowest grid
+// Xs[C][G][G], for a power-of-two grid side G (16..4096), or any other G up to 4096 through
+// Bluestein's identity at the power-of-two length M >= 2G - 1 (fft_lds.h):
 //
 //   k_rows_embed     x[B][n][n] -> deapodise (k*), centre (pixel i at grid index (i - n/2) mod
 //                    G), pair slices 2c / 2c+1 into channel c, zero padding -> DFT of each grid
@@ -31,29 +32,32 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
   return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
-// rows per row block: about 32 KB of LDS, so that four blocks share a CU
-template <int G>
+// rows per row block: about 32 KB of LDS, so that four blocks share a CU (M = the transform length
+// held in LDS: G itself, or the Bluestein length for other G)
+template <int M>
 constexpr int rows_per_block() {
-  return G >= 2048 ? 2 : (4096 / G > 16 ? 16 : 4096 / G);
+  return M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
 }
 
 // columns per column block: 4 adjacent columns (32-byte runs of a row) while they fit 64 KB
 // (measured at G = 2048: 2 columns with twice the blocks per CU took 510 us, 4 columns 410 us)
-template <int G>
+template <int M>
 constexpr int cols_per_block() {
-  return G >= 4096 ? 2 : (G >= 2048 ? 4 : (8192 / G > 16 ? 16 : 8192 / G));
+  return M >= 8192 ? 1 : (M >= 4096 ? 2 : (M >= 2048 ? 4 : (8192 / M > 16 ? 16 : 8192 / M)));
 }
 
-template <int G, int AG>
+// The grid side G is t.N: M for power-of-two grids (BL = false), else the DFTs go through
+// Bluestein's identity at length M.  Indices below t.N are grid indices; LDS rows have stride M.
+template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
                                                     float2* __restrict__ Xs,
-                                                    const float* __restrict__ kd,
-                                                    const float2* __restrict__ tw, int B, int n,
-                                                    int on) {
-  __shared__ float2 buf[lds_size<AG * G>()];
-  constexpr int groups = G / AG;
+                                                    const float* __restrict__ kd, DftTables t,
+                                                    int B, int n, int on) {
+  __shared__ float2 buf[lds_size<AG * M>()];
+  const int G = BL ? t.N : M;
+  const int groups = (G + AG - 1) / AG;
   // elements per thread, loaded as one batch (all loads issued before the first LDS store)
-  constexpr int NE = (AG * G + kFB - 1) / kFB;
+  constexpr int NE = (AG * M + kFB - 1) / kFB;
   const int c = blockIdx.x / groups, g1_0 = (blockIdx.x % groups) * AG;
   const int64_t plane = (int64_t)n * n;
   const bool odd = 2 * c + 1 < B;
@@ -61,12 +65,14 @@ __global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int i = threadIdx.x + u * kFB;
-    const int q = i / G, g2 = i % G;
-    const int i1 = (g1_0 + q + on) & (G - 1), i2 = (g2 + on) & (G - 1);
+    const int q = i / M, g2 = i % M;
+    int i1 = g1_0 + q + on, i2 = g2 + on;          // pixel (i1, i2) sits at grid (i - on) mod G
+    i1 -= (i1 >= G) ? G : 0;
+    i2 -= (i2 >= G) ? G : 0;
     re[u] = 0.f;
     im[u] = 0.f;
     kk[u] = 0.f;
-    if (i < AG * G && i1 < n && i2 < n) {
+    if (i < AG * M && g1_0 + q < G && g2 < G && i1 < n && i2 < n) {
       const int64_t off = (int64_t)i1 * n + i2;
       kk[u] = kd[i1] * kd[i2];
       re[u] = x[(int64_t)(2 * c) * plane + off];
@@ -76,77 +82,86 @@ __global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int i = threadIdx.x + u * kFB;
-    if (i < AG * G) buf[lds(i)] = make_float2(re[u] * kk[u], im[u] * kk[u]);
+    if (i < AG * M) buf[lds(i)] = make_float2(re[u] * kk[u], im[u] * kk[u]);
   }
   __syncthreads();
-  fft_lds<G, AG, false>(buf, tw);
+  dft_lds<M, AG, false, BL>(buf, t);
+  const int nq = min(AG, G - g1_0);
   float2* dst = Xs + ((int64_t)c * G + g1_0) * G;
-  for (int i = threadIdx.x; i < AG * G; i += kFB) dst[i] = buf[lds(i)];
+  for (int i = threadIdx.x; i < nq * G; i += kFB) dst[i] = buf[lds((i / G) * M + i % G)];
 }
 
-template <int G, int W, bool INV>
-__global__ __launch_bounds__(kFB) void k_cols(float2* __restrict__ Xs,
-                                              const float2* __restrict__ tw) {
-  __shared__ float2 buf[lds_size<W * G>()];
-  constexpr int groups = G / W;
+template <int M, int W, bool INV, bool BL>
+__global__ __launch_bounds__(kFB) void k_cols(float2* __restrict__ Xs, DftTables t) {
+  __shared__ float2 buf[lds_size<W * M>()];
+  const int G = BL ? t.N : M;
+  const int groups = (G + W - 1) / W;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
   const int c = (int)(blk / groups), j2_0 = (int)(blk % groups) * W;
+  const int nw = min(W, G - j2_0);
   float2* base = Xs + (int64_t)c * G * G + j2_0;
   {
-    constexpr int NE = (W * G + kFB - 1) / kFB;   // loads per thread, issued as one batch
+    constexpr int NE = (W * M + kFB - 1) / kFB;   // loads per thread, issued as one batch
     float2 v[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
-      if (i < W * G) v[u] = base[(int64_t)(i / W) * G + i % W];
+      const int g1 = i / W, w = i % W;
+      v[u] = make_float2(0.f, 0.f);
+      if (i < W * M && g1 < G && w < nw) v[u] = base[(int64_t)g1 * G + w];
     }
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
-      if (i < W * G) buf[lds((i % W) * G + i / W)] = v[u];
+      if (i < W * M) buf[lds((i % W) * M + i / W)] = v[u];
     }
   }
   __syncthreads();
-  fft_lds<G, W, INV>(buf, tw);
+  dft_lds<M, W, INV, BL>(buf, t);
   for (int i = threadIdx.x; i < W * G; i += kFB) {
     const int g1 = i / W, w = i % W;
-    base[(int64_t)g1 * G + w] = buf[lds(w * G + g1)];
+    if (w < nw) base[(int64_t)g1 * G + w] = buf[lds(w * M + g1)];
   }
 }
 
-template <int G, int AG>
+template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict__ Xs,
                                                        float* __restrict__ x,
-                                                       const float* __restrict__ kd,
-                                                       const float2* __restrict__ tw, int B,
-                                                       int n, int on, float scale) {
-  __shared__ float2 buf[lds_size<AG * G>()];
-  constexpr int groups = G / AG;
+                                                       const float* __restrict__ kd, DftTables t,
+                                                       int B, int n, int on, float scale) {
+  __shared__ float2 buf[lds_size<AG * M>()];
+  const int G = BL ? t.N : M;
+  const int groups = (G + AG - 1) / AG;
   const int c = blockIdx.x / groups, g1_0 = (blockIdx.x % groups) * AG;
+  const int nq = min(AG, G - g1_0);
   const float2* src = Xs + ((int64_t)c * G + g1_0) * G;
   {
-    constexpr int NE = (AG * G + kFB - 1) / kFB;  // loads per thread, issued as one batch
+    constexpr int NE = (AG * M + kFB - 1) / kFB;  // loads per thread, issued as one batch
     float2 v[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
-      if (i < AG * G) v[u] = src[i];
+      const int q = i / M, g2 = i % M;
+      v[u] = make_float2(0.f, 0.f);
+      if (i < AG * M && q < nq && g2 < G) v[u] = src[(int64_t)q * G + g2];
     }
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
-      if (i < AG * G) buf[lds(i)] = v[u];
+      if (i < AG * M) buf[lds(i)] = v[u];
     }
   }
   __syncthreads();
-  fft_lds<G, AG, true>(buf, tw);
+  dft_lds<M, AG, true, BL>(buf, t);
   const int64_t plane = (int64_t)n * n;
   const bool odd = 2 * c + 1 < B;
-  for (int i = threadIdx.x; i < AG * n; i += kFB) {
+  for (int i = threadIdx.x; i < nq * n; i += kFB) {
     const int q = i / n, i2 = i % n;
-    const int i1 = (g1_0 + q + on) & (G - 1);
+    int i1 = g1_0 + q + on;
+    i1 -= (i1 >= G) ? G : 0;
     if (i1 >= n) continue;
-    const float2 v = buf[lds(q * G + ((i2 - on) & (G - 1)))];
+    const int g2 = i2 - on + ((i2 < on) ? G : 0);
+    const float2 v = buf[lds(q * M + g2)];
     const float k = scale * kd[i1] * kd[i2];
     const int64_t off = (int64_t)i1 * n + i2;
     x[(int64_t)(2 * c) * plane + off] = v.x * k;
@@ -156,27 +171,29 @@ __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict_
 
 enum class Step { RowsEmbed, ColsFwd, ColsInv, RowsInvCrop };
 
-template <int G>
+template <int M, bool BL>
 tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
                         int B, float scale, hipStream_t st) {
-  constexpr int AG = rows_per_block<G>(), W = cols_per_block<G>();
+  constexpr int AG = rows_per_block<M>(), W = cols_per_block<M>();
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
-  const dim3 grid((unsigned)(C * (G / AG))), cgrid((unsigned)(C * (G / W)));
+  const DftTables& t = op->dft2;
+  const int G = g.G;
+  const dim3 grid((unsigned)(C * ((G + AG - 1) / AG))), cgrid((unsigned)(C * ((G + W - 1) / W)));
   switch (s) {
     case Step::RowsEmbed:
-      hipLaunchKernelGGL((k_rows_embed<G, AG>), grid, dim3(kFB), 0, st, xin, Xs, op->kd_dev,
-                         op->tw2, B, g.n, g.on);
+      hipLaunchKernelGGL((k_rows_embed<M, AG, BL>), grid, dim3(kFB), 0, st, xin, Xs, op->kd_dev, t,
+                         B, g.n, g.on);
       break;
     case Step::ColsFwd:
-      hipLaunchKernelGGL((k_cols<G, W, false>), cgrid, dim3(kFB), 0, st, Xs, op->tw2);
+      hipLaunchKernelGGL((k_cols<M, W, false, BL>), cgrid, dim3(kFB), 0, st, Xs, t);
       break;
     case Step::ColsInv:
-      hipLaunchKernelGGL((k_cols<G, W, true>), cgrid, dim3(kFB), 0, st, Xs, op->tw2);
+      hipLaunchKernelGGL((k_cols<M, W, true, BL>), cgrid, dim3(kFB), 0, st, Xs, t);
       break;
     case Step::RowsInvCrop:
-      hipLaunchKernelGGL((k_rows_inv_crop<G, AG>), grid, dim3(kFB), 0, st, Xs, xout, op->kd_dev,
-                         op->tw2, B, g.n, g.on, scale);
+      hipLaunchKernelGGL((k_rows_inv_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Xs, xout, op->kd_dev,
+                         t, B, g.n, g.on, scale);
       break;
   }
   TOMO_HIP(hipGetLastError());
@@ -185,26 +202,22 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
 
 tomo_status grid_dispatch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
                           int B, float scale, hipStream_t st) {
-  switch (op->g.G) {
-    case 16: return grid_launch<16>(s, op, xin, Xs, xout, B, scale, st);
-    case 32: return grid_launch<32>(s, op, xin, Xs, xout, B, scale, st);
-    case 64: return grid_launch<64>(s, op, xin, Xs, xout, B, scale, st);
-    case 128: return grid_launch<128>(s, op, xin, Xs, xout, B, scale, st);
-    case 256: return grid_launch<256>(s, op, xin, Xs, xout, B, scale, st);
-    case 512: return grid_launch<512>(s, op, xin, Xs, xout, B, scale, st);
-    case 1024: return grid_launch<1024>(s, op, xin, Xs, xout, B, scale, st);
-    case 2048: return grid_launch<2048>(s, op, xin, Xs, xout, B, scale, st);
-    case 4096: return grid_launch<4096>(s, op, xin, Xs, xout, B, scale, st);
-    default: return fail(TOMO_EUNSUPPORTED, "hand-written grid DFT needs G = 2^m in [16, 4096]");
+  const bool bl = op->dft2.M != op->g.G;
+#define TOMO_GRID(M_)                                                                            \
+  case M_:                                                                                      \
+    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, st)                       \
+              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, st);
+  switch (op->dft2.M) {
+    TOMO_GRID(16) TOMO_GRID(32) TOMO_GRID(64) TOMO_GRID(128) TOMO_GRID(256) TOMO_GRID(512)
+    TOMO_GRID(1024) TOMO_GRID(2048) TOMO_GRID(4096) TOMO_GRID(8192)
+    default: return fail(TOMO_EUNSUPPORTED, "hand-written grid DFT: no kernel for length %d", op->dft2.M);
   }
+#undef TOMO_GRID
 }
 
 }  // namespace
 
-bool grid_fft_supported(const tomo_op* op) {
-  const int G = op->g.G;
-  return op->tw2 != nullptr && G >= 16 && G <= 4096 && (G & (G - 1)) == 0;
-}
+bool grid_fft_supported(const tomo_op* op) { return op->dft2.tw != nullptr; }
 
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
                                 hipStream_t st) {

@@ -1,5 +1,6 @@
 // Radix-8/4/2 Stockham DFTs of several length-L vectors held in LDS, for power-of-two L: the
-// shared core of the hand-written transforms (detector rows and Cartesian rows / columns).
+// shared core of the hand-written transforms (detector rows and Cartesian rows / columns); and
+// DFTs of any length N through Bluestein's chirp-z identity on top of them.
 // Every pass reads each butterfly's inputs into registers, synchronises the block, then writes
 // its outputs back, so the transform is in place in one buffer.  Forward: exp(-2 pi i jk / L);
 // inverse: exp(+2 pi i jk / L), unnormalised.  Twiddle table tw[j] = exp(-2 pi i j / L).
@@ -127,6 +128,62 @@ __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ 
   }
   if ((4 << logNs) <= L) stockham_pass<L, CH, 4, INV>(buf, logNs, tw);
   else if ((2 << logNs) <= L) stockham_pass<L, CH, 2, INV>(buf, logNs, tw);
+}
+
+// Length-N DFTs (N not a power of two) of CH vectors held in LDS with row stride M, a power of two
+// >= 2N - 1, elements N .. M-1 zero on entry (Bluestein 1970, the chirp-z transform).  With
+// w_m = exp(+i pi m^2 / N), n k = (n^2 + k^2 - (k - n)^2) / 2 gives
+//   forward: X_k = conj(w_k) sum_n (x_n conj(w_n)) w_{k-n},
+//   inverse: X_k =      w_k  sum_n (x_n w_n) conj(w_{k-n}),
+// a linear convolution of length < 2N - 1, done as a cyclic one of length M through the radix-8
+// transforms.  Tables (from double precision on the host): chirp[n] = conj(w_n), n < N; bhat = the
+// length-M DFT of the kernel w (forward) or conj(w) (inverse) wrapped to negative indices, times
+// 1/M; tw = the length-M twiddles.  Elements N .. M-1 hold garbage on exit.
+template <int M, int CH, bool INV>
+__device__ __forceinline__ void bluestein_lds(float2* buf, const float2* __restrict__ tw, int N,
+                                              const float2* __restrict__ chirp,
+                                              const float2* __restrict__ bhat) {
+  for (int i = threadIdx.x; i < CH * M; i += kFB) {
+    const int m = i % M;
+    if (m < N) {
+      float2 c = chirp[m];
+      if (INV) c.y = -c.y;
+      buf[lds(i)] = cmul(buf[lds(i)], c);
+    }
+  }
+  __syncthreads();
+  fft_lds<M, CH, false>(buf, tw);
+  for (int i = threadIdx.x; i < CH * M; i += kFB) buf[lds(i)] = cmul(buf[lds(i)], bhat[i % M]);
+  __syncthreads();
+  fft_lds<M, CH, true>(buf, tw);
+  for (int i = threadIdx.x; i < CH * M; i += kFB) {
+    const int m = i % M;
+    if (m < N) {
+      float2 c = chirp[m];
+      if (INV) c.y = -c.y;
+      buf[lds(i)] = cmul(buf[lds(i)], c);
+    }
+  }
+  __syncthreads();
+}
+
+// Tables of one transform length N for the kernels: the power-of-two case (M = N) needs only the
+// twiddles; otherwise M is the Bluestein length and chirp / bhat_f / bhat_i are set.
+struct DftTables {
+  int N = 0, M = 0;
+  const float2* tw = nullptr;
+  const float2* chirp = nullptr;
+  const float2* bhat_f = nullptr;
+  const float2* bhat_i = nullptr;
+};
+
+// The length-N DFT (forward or inverse, unnormalised) of CH vectors in LDS with row stride M.
+template <int M, int CH, bool INV, bool BL>
+__device__ __forceinline__ void dft_lds(float2* buf, const DftTables& t) {
+  if constexpr (BL)
+    bluestein_lds<M, CH, INV>(buf, t.tw, t.N, t.chirp, INV ? t.bhat_i : t.bhat_f);
+  else
+    fft_lds<M, CH, INV>(buf, t.tw);
 }
 
 }  // namespace fftk

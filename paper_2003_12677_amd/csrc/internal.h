@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/tomo.h"
+#include "fft_lds.h"
 
 namespace tomo {
 
@@ -76,9 +77,20 @@ struct Tuning {
   int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1, G = 2^m) or library (0)
   int sell_tiles = 1;         // sliced-ELL rows in 4 x 8 Cartesian tiles (1) or grid order (0)
   int tile_strip = 32;        // staged kernels visit tiles in strips this many tiles wide (0 = rows)
+  // the staged adjoint's dense tiles (regions holding more than adj_tile_points samples):
+  // 0 = row kernels on their cells; 1 = staged in chunks of <= adj_tile_points samples, one block
+  // per segment of <= adj_seg_chunks chunks (split tiles summed from partial tiles in a fixed
+  // order), on a second stream beside the staged tiles; 2 = the same segments and the staged
+  // tiles in one launch, dense segments first
+  int adj_dense_mode = 1;
+  int adj_seg_chunks = 8;
+  // in the one-launch form (adj_dense_mode 2): staged tiles per block, visited in order with the
+  // next tile's loads in flight while the current one is summed
+  int adj_run = 1;
 };
 
 constexpr int kSliceRows = 8;    // rows per slice of the sliced-ELL layout
+constexpr int kMaxSegChunks = 256;   // most chunks one segment of the staged adjoint may hold
 
 // S^dagger with a constant row stride W2 = k_w^2 (its rows never hold more): entry s of row r
 // at r * W2 + s, padded with column -1 (skipped) and value 0.
@@ -128,6 +140,17 @@ struct HostAdjWin {
   std::vector<int32_t> q_row;              // polar row of each tile sample
   std::vector<double> q_val;               // [Q][W2] window-ordered values
   std::vector<char> dense_cell;            // [M] library cell index -> 1 if in a dense tile
+  // Dense tiles staged in chunks (adj_dense_mode != 0).  Chunks extend the work-item arrays:
+  // chunk c >= n_wi covers samples [wi_q[c], wi_q[c+1]) with bucket offsets wi_boff[c] (relative
+  // to wi_q[c]).  Segment s covers chunks [seg_chunk[s], seg_chunk[s+1]) of tile seg_tile[s];
+  // segments 0 .. n_wi-1 are the staged tiles (one chunk each), the rest the dense tiles.  A
+  // segment writes its tile's cells to X when seg_slot[s] < 0, else partial tile seg_slot[s];
+  // split tile i sums partial tiles [red_slot[i], red_slot[i+1]) in order into tile red_tile[i].
+  int64_t n_wi = 0;                        // staged tiles (the first n_wi chunks)
+  int64_t n_sseg = 0;                      // segments of staged tiles (runs of adj_run tiles)
+  std::vector<int32_t> chunk_tile;         // [n_chunks] tile of every chunk
+  std::vector<int32_t> seg_tile, seg_chunk, seg_slot;
+  std::vector<int32_t> red_tile, red_slot;
 };
 
 tomo_status resolve_geometry(const tomo_geometry* in, Geom* g);
@@ -194,6 +217,12 @@ struct DevAdjWin {
   int32_t *wi_tile = nullptr, *wi_q = nullptr, *q_row = nullptr;
   uint16_t* wi_boff = nullptr;
   void* q_val[3] = {nullptr, nullptr, nullptr};
+  // dense tiles in chunked segments (HostAdjWin): n_seg segments in all, the first n_sseg of them
+  // runs of staged tiles; n_red split tiles reduced from n_slot partial tiles
+  int64_t n_seg = 0, n_sseg = 0, n_red = 0, n_slot = 0;
+  int max_seg_chunks = 0;         // most chunks of any segment
+  int32_t *seg_tile = nullptr, *seg_chunk = nullptr, *seg_slot = nullptr, *chunk_tile = nullptr;
+  int32_t *red_tile = nullptr, *red_slot = nullptr;
 };
 
 struct FFTPlans {
@@ -232,8 +261,9 @@ struct tomo_op {
   tomo::DevEll fwd;
   tomo::DevAdj adj;
   float* kd_dev = nullptr;        // [n]
-  float2* tw1 = nullptr;          // [L] exp(-2 pi i j / L) when L is a power of two (fused 1D DFTs)
-  float2* tw2 = nullptr;          // [G] exp(-2 pi i j / G) when G is a power of two (fused 2D DFTs)
+  // tables of the hand-written DFTs: detector length L and grid side G (twiddles of the length M
+  // held in LDS; chirp and convolution kernels when M is the Bluestein length of L or G)
+  tomo::fftk::DftTables dft1, dft2;
   float* dens = nullptr;          // [L*nt] density-filter weights (tomo_density_filter)
   float* filt_dev[4] = {nullptr, nullptr, nullptr, nullptr};   // D per tomo_filter, [L]
   int cmax = 0;                   // complex channels the workspace holds
@@ -248,6 +278,7 @@ struct tomo_op {
   tomo::DevFwdTiles ftile;        // LDS-staged forward layout
   tomo::DevAdjWin awin;           // LDS-staged adjoint layout
   tomo::DevAdj adj_dense;         // row layout of the staged adjoint's dense cells
+  float2* seg_partials = nullptr; // [n_slot][TS*TS][cmax] partial tiles of split dense tiles
   bool tiles_ready = false;
   std::map<int, tomo::FFTPlans> plans;   // keyed by channel count C
   tomo::SolverBuffers sb;
@@ -296,18 +327,44 @@ tomo_status launch_to_channel_slowest(const float2* src, float2* dst, int64_t P,
 // polar: Yf[kf][a][C] <-> Ys[C][a][kf]
 tomo_status launch_polar_to_slowest(const float2* Yf, float2* Ys, int L, int nt, int C, hipStream_t st);
 tomo_status launch_polar_to_fastest(const float2* Ys, float2* Yf, int L, int nt, int C, hipStream_t st);
+// `slow` (only when spmm_fwd_slowest_ok / spmm_adj_slowest_ok): the Cartesian grid is the
+// channel-slowest [C][G][G] FFT-side buffer, read or written by the staged kernels directly, and
+// the forward writes the channel-slowest polar rows [C][nt][L]
 tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
-                            hipStream_t st);
+                            hipStream_t st, bool slow = false);
+bool spmm_fwd_slowest_ok(const tomo_op* op, int C, int vt);
+bool spmm_adj_slowest_ok(const tomo_op* op, int C, int vt);
 tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
-                            const float* dscale, hipStream_t st);
+                            const float* dscale, hipStream_t st, bool slow = false);
 
+// `slow`: the Cartesian grid is channel-slowest [C][G][G] (the FFT side) instead of [G*G][C], and
+// for the forward the polar output too ([C][nt][L] instead of [L*nt][C])
 tomo_status launch_fwd_tile(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
-                            hipStream_t st);
+                            bool slow, hipStream_t st);
 tomo_status launch_adj_tile(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
-                            const float* dscale, hipStream_t st);
+                            const float* dscale, bool slow, hipStream_t st);
+// staged adjoint segments: the dense tiles' segments (+ their reduction) when `dense`, the
+// staged tiles as one-chunk segments when `staged` (both: one launch, dense segments first)
+tomo_status launch_adj_seg(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
+                           const float* dscale, bool dense, bool staged, bool slow, hipStream_t st);
 size_t fwd_tile_lds_bytes(const tomo_op* op, int C);
 bool fwd_tile_supported(const tomo_op* op);
 size_t adj_tile_lds_bytes(const tomo_op* op, int C);
+size_t adj_seg_lds_bytes(const tomo_op* op, int C);
+
+// Persistent SpMM pairs over a stack of operators (tiles.hip): one forward kernel and one adjoint
+// kernel (+ a reduction of split tiles) walk device work lists covering every item.
+struct StackItemSpec {
+  const tomo_op* op;
+  int batch;
+  const float* in;   // Xc, the item's Cartesian input
+  float* out;        // Yp = S^dagger Xc
+  float* aux;        // Xc' = S Yp
+};
+struct StackPlan;
+tomo_status stack_plan_create(const StackItemSpec* items, int n, int vt, StackPlan** out);
+tomo_status stack_plan_launch(const StackPlan* p, hipStream_t st);
+void stack_plan_destroy(StackPlan* p);   // the segment kernel's LDS per block
 bool adj_tile_supported(const tomo_op* op);
 constexpr size_t kMaxTileLds = 65536;   // staged kernels are used when their LDS fits this
 

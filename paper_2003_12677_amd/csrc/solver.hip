@@ -287,6 +287,43 @@ __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, 
   }
 }
 
+// The same for n % 4 == 0, four pixels of one row per thread: 16-byte loads of p and q at the
+// pixels and at the rows above and below, the left and right neighbours as single loads (the
+// one-pixel form issued five 4-byte loads and a division per pixel and ran at ~2.3 TB/s).
+__global__ __launch_bounds__(256) void k_sb_addlap4(const float* __restrict__ p, float* __restrict__ q,
+                                                    float mu, float lam, int n) {
+  const int64_t base = (int64_t)blockIdx.y * n * n;
+  const int quads = n * n / 4;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < quads; t += gridDim.x * 256) {
+    const int pix = 4 * t;
+    const int i1 = pix / n, i2 = pix - i1 * n;
+    const int64_t i = base + pix;
+    const float4 c = *reinterpret_cast<const float4*>(p + i);
+    const float4 qq = *reinterpret_cast<const float4*>(q + i);
+    const float4 dn = (i1 < n - 1) ? *reinterpret_cast<const float4*>(p + i + n) : c;
+    const float4 up = (i1 > 0) ? *reinterpret_cast<const float4*>(p + i - n) : c;
+    const float lf = (i2 > 0) ? p[i - 1] : c.x;
+    const float rt = (i2 + 4 < n) ? p[i + 4] : c.w;
+    // -(D1 p)(i) + (D1 p)(i - row) = (up - c) + (dn - c) with zero differences past the edges;
+    // the same along the row with the left / right neighbours
+    const float cv[4] = {c.x, c.y, c.z, c.w};
+    const float uv[4] = {up.x, up.y, up.z, up.w};
+    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
+    const float lv[4] = {lf, c.x, c.y, c.z};
+    const float rv[4] = {c.y, c.z, c.w, rt};
+    const float qv[4] = {qq.x, qq.y, qq.z, qq.w};
+    float o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float v = -(dv[k] - cv[k]) - (rv[k] - cv[k]);   // the one-pixel form's order of operations
+      v += cv[k] - uv[k];
+      v += cv[k] - lv[k];
+      o[k] = mu * qv[k] + lam * v;
+    }
+    *reinterpret_cast<float4*>(q + i) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+
 // s = D u + b; d = shrink(s, 1/lam) (isotropic); b = s - d
 __global__ __launch_bounds__(256) void k_sb_shrink(const float* __restrict__ u, float* __restrict__ d1,
                                                    float* __restrict__ d2, float* __restrict__ b1,
@@ -492,7 +529,11 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
       TOMO_TRY(apply_project(c.op, v, w.q, c.B, vt, c.st));
       TOMO_TRY(apply_backproject(c.op, w.q, q, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
     }
-    hipLaunchKernelGGL(k_sb_addlap, grid, dim3(256), 0, c.st, v, q, (float)mu, (float)lam, n);
+    if (n % 4 == 0)
+      hipLaunchKernelGGL(k_sb_addlap4, dim3(grid_for((int64_t)n * n / 4), (unsigned)c.B), dim3(256),
+                         0, c.st, v, q, (float)mu, (float)lam, n);
+    else
+      hipLaunchKernelGGL(k_sb_addlap, grid, dim3(256), 0, c.st, v, q, (float)mu, (float)lam, n);
     TOMO_HIP(hipGetLastError());
     return TOMO_OK;
   };

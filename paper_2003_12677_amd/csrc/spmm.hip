@@ -544,7 +544,9 @@ tomo_status fwd_cpl(const tomo_op* op, const void* val, const float2* X, float2*
     case 1: return fwd_impl<1, V>(op, val, X, Y, C, st);
     case 2: return fwd_impl<2, V>(op, val, X, Y, C, st);
     case 4: return fwd_impl<4, V>(op, val, X, Y, C, st);
-    default: return fail(TOMO_EINVAL, "channel count %d not supported", C);
+    default:
+      return fail(TOMO_EUNSUPPORTED, "the row kernels take at most 64 lane groups: odd channel "
+                  "counts above 64 (%d) need the staged forward (fwd_tiled)", C);
   }
 }
 
@@ -555,20 +557,35 @@ tomo_status adj_cpl(const tomo_op* op, const DevAdj& d, int vt, const float2* Y,
     case 1: return adj_impl<1, V>(op, d, vt, Y, X, C, dscale, st);
     case 2: return adj_impl<2, V>(op, d, vt, Y, X, C, dscale, st);
     case 4: return adj_impl<4, V>(op, d, vt, Y, X, C, dscale, st);
-    default: return fail(TOMO_EINVAL, "channel count %d not supported", C);
+    default:
+      return fail(TOMO_EUNSUPPORTED, "the row kernels take at most 64 lane groups: odd channel "
+                  "counts above 64 (%d) need the staged adjoint with staged dense tiles "
+                  "(adj_tiled, adj_dense_mode 1 or 2)", C);
   }
 }
 
 }  // namespace
 
+// The staged kernels run for this channel count and value type (and, for the adjoint, stage its
+// dense tiles too): only then can the Cartesian grid be the channel-slowest FFT-side buffer.
+bool spmm_fwd_slowest_ok(const tomo_op* op, int C, int vt) {
+  return vt >= 0 && vt <= 2 && ((op->tune.fwd_tiled >> vt) & 1) && op->tiles_ready &&
+         fwd_tile_supported(op) && fwd_tile_lds_bytes(op, C) <= kMaxTileLds;
+}
+
+bool spmm_adj_slowest_ok(const tomo_op* op, int C, int vt) {
+  return vt >= 0 && vt <= 2 && op->adj_ready && ((op->tune.adj_tiled >> vt) & 1) &&
+         op->tiles_ready && adj_tile_supported(op) && adj_seg_lds_bytes(op, C) <= kMaxTileLds &&
+         op->tune.adj_dense_mode != 0;
+}
+
 tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
-                            hipStream_t st) {
+                            hipStream_t st, bool slow) {
   if (vt < 0 || vt > 2 || !op->fwd.val[vt])
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (C < 1 || C > op->cmax) return fail(TOMO_EINVAL, "channel count %d out of range", C);
-  if (((op->tune.fwd_tiled >> vt) & 1) && op->tiles_ready && fwd_tile_supported(op) &&
-      fwd_tile_lds_bytes(op, C) <= kMaxTileLds)
-    return launch_fwd_tile(op, X, Y, C, vt, st);
+  if (spmm_fwd_slowest_ok(op, C, vt)) return launch_fwd_tile(op, X, Y, C, vt, slow, st);
+  if (slow) return fail(TOMO_EINVAL, "internal: channel-slowest grid without the staged forward");
   switch (vt) {
     case TOMO_VAL_F32: return fwd_cpl<float>(op, op->fwd.val[vt], X, Y, C, st);
     case TOMO_VAL_BF16: return fwd_cpl<bf16_t>(op, op->fwd.val[vt], X, Y, C, st);
@@ -577,7 +594,7 @@ tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C
 }
 
 tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
-                            const float* dscale, hipStream_t st) {
+                            const float* dscale, hipStream_t st, bool slow) {
   if (vt < 0 || vt > 2 || !(op->values & (1u << vt)))
     return fail(TOMO_ESTATE, "value type %d was not built for this operator", vt);
   if (!op->adj_ready) return fail(TOMO_ESTATE, "adjoint layout unavailable (failed re-tuning)");
@@ -589,6 +606,19 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
       default: return adj_cpl<_Float16>(op, d, vt, Y, X, C, dscale, s);
     }
   };
+  if (spmm_adj_slowest_ok(op, C, vt)) {
+    if (op->tune.adj_dense_mode == 2)
+      return launch_adj_seg(op, Y, X, C, vt, dscale, true, true, slow, st);
+    // the dense tiles' segments on a second stream beside the staged tiles (disjoint cells)
+    TOMO_HIP(hipEventRecord(op->ev_fork, st));
+    TOMO_HIP(hipStreamWaitEvent(op->aux, op->ev_fork, 0));
+    TOMO_TRY(launch_adj_seg(op, Y, X, C, vt, dscale, true, false, slow, op->aux));
+    TOMO_HIP(hipEventRecord(op->ev_join, op->aux));
+    TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, slow, st));
+    TOMO_HIP(hipStreamWaitEvent(st, op->ev_join, 0));
+    return TOMO_OK;
+  }
+  if (slow) return fail(TOMO_EINVAL, "internal: channel-slowest grid without the staged adjoint");
   if (((op->tune.adj_tiled >> vt) & 1) && op->tiles_ready && adj_tile_supported(op) &&
       adj_tile_lds_bytes(op, C) <= kMaxTileLds) {
     // the dense cells' row kernels on two more streams (sliced-ELL rows; wave-per-row and
@@ -604,7 +634,7 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
     TOMO_HIP(hipEventRecord(op->ev_join, op->aux));
     TOMO_TRY(rows(tail, op->aux2));
     TOMO_HIP(hipEventRecord(op->ev_join2, op->aux2));
-    TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, st));
+    TOMO_TRY(launch_adj_tile(op, Y, X, C, vt, dscale, false, st));
     TOMO_HIP(hipStreamWaitEvent(st, op->ev_join, 0));
     TOMO_HIP(hipStreamWaitEvent(st, op->ev_join2, 0));
     return TOMO_OK;

@@ -28,6 +28,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 
 namespace tomo {
@@ -100,9 +103,11 @@ struct FwdTileArgs {
   const int32_t* wi_beg;
   const int32_t* pt_row;
   const int32_t* pt_base;
-  const float2* X;
-  float2* Y;
+  const float2* X;            // plane == 0: [G*G][C] channel-fastest; else [C][G*G] (plane = G*G)
+  float2* Y;                  // yplane == 0: [L*nt][C], row kf*nt + a; else [C][nt][L] (yplane = nt*L)
   int C, G, oG, TS, NT, TP;
+  int64_t plane, yplane;
+  int nt, L;
 };
 
 // Staging is written as batches of independent loads into registers followed by LDS stores, so
@@ -113,21 +118,20 @@ constexpr int kMaxTilePoints = 128;
 template <int KW>
 constexpr int window_stride() { return (KW * KW + 3) / 4 * 4; }   // LDS floats per sample
 
-// MAXP: the most samples a work item may hold (a compile-time bound, so that the staging loops
-// issue only the loads a block of that capacity can need)
+// One forward work item wi (channels c0 .. c0 + 8*CPL - 1) of a block; smem holds the patch, the
+// values and the sample records.  MAXP: the most samples a work item may hold (a compile-time
+// bound, so that the staging loops issue only the loads a block of that capacity can need).
 template <int CPL, typename V, int KW, int PS, int MAXP>
-__global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __restrict__ val) {
+__device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __restrict__ val,
+                                              int wi, int c0, float2* smem) {
   constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
   constexpr int PP = PS * PS;
   constexpr int NPL = (PP * kLanes + kBlock - 1) / kBlock;            // patch loads per thread
   constexpr int NVL = (MAXP * W2 + kBlock - 1) / kBlock;              // value loads per thread
-  extern __shared__ float2 smem[];
   float2* patch = smem;                                                      // [PP][CH]
   float* s_val = reinterpret_cast<float*>(patch + PP * CH);                  // [TP][WP]
   int* s_row = reinterpret_cast<int*>(s_val + a.TP * WP);                    // [TP]
   int* s_base = s_row + a.TP;                                                // [TP]
-  const int wi = (int)xcd_remap(blockIdx.x, gridDim.x);
-  const int c0 = blockIdx.y * CH;
   const int nch = min(CH, a.C - c0);
   const int tl = a.wi_tile[wi];
   const int b0 = a.wi_beg[wi], ns = a.wi_beg[wi + 1] - b0;
@@ -136,10 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __r
   // issue every load of the block (sample records, then the patch) before the first LDS store
   uint32_t v[NVL];
 #pragma unroll
-  for (int u = 0; u < NVL; ++u) {
+  for (int u = 0; u < NVL; ++u) {   // every load issued; entries past the item are never stored
     const int k = threadIdx.x + u * kBlock;
-    v[u] = 0;
-    if (k < ns * W2) v[u] = ldraw(val, (int64_t)b0 * W2 + k);
+    v[u] = ldraw(val, (k < ns * W2) ? (int64_t)b0 * W2 + k : 0);
   }
   int rw = 0, bs = 0;
   if ((int)threadIdx.x < ns) {
@@ -147,22 +150,50 @@ __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __r
     bs = a.pt_base[b0 + threadIdx.x];
   }
   constexpr int NB = NPL < kStageBatch ? NPL : kStageBatch;
-  for (int base = 0; base < NPL; base += NB) {
-    Vec<CPL> x[NB];
+  if (a.plane == 0) {
+    for (int base = 0; base < NPL; base += NB) {
+      Vec<CPL> x[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int idx = threadIdx.x + (base + u) * kBlock;
-      const int p = idx / kLanes, l = (idx % kLanes) * CPL;
-      if (idx < PP * kLanes && l < nch) {
-        const int g1 = wrap(j01 + p / PS, a.G), g2 = wrap(j02 + p % PS, a.G);
-        x[u] = vload<CPL>(a.X + ((int64_t)g1 * a.G + g2) * a.C + c0 + l);
+      for (int u = 0; u < NB; ++u) {
+        const int idx = threadIdx.x + (base + u) * kBlock;
+        const int p = idx / kLanes, l = (idx % kLanes) * CPL;
+        if (idx < PP * kLanes && l < nch) {
+          const int g1 = wrap(j01 + p / PS, a.G), g2 = wrap(j02 + p % PS, a.G);
+          x[u] = vload<CPL>(a.X + ((int64_t)g1 * a.G + g2) * a.C + c0 + l);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int idx = threadIdx.x + (base + u) * kBlock;
+        const int p = idx / kLanes, l = (idx % kLanes) * CPL;
+        if (idx < PP * kLanes && l < nch) vstore<CPL>(patch + p * CH + l, x[u]);
       }
     }
+  } else {
+    // channel-slowest grid: point fastest across threads, so that each patch row is one run of
+    // PS points in every channel plane
+    for (int base = 0; base < NPL; base += NB) {
+      Vec<CPL> x[NB];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int idx = threadIdx.x + (base + u) * kBlock;
-      const int p = idx / kLanes, l = (idx % kLanes) * CPL;
-      if (idx < PP * kLanes && l < nch) vstore<CPL>(patch + p * CH + l, x[u]);
+      for (int u = 0; u < NB; ++u) {
+        const int idx = threadIdx.x + (base + u) * kBlock;
+        const int p = idx % PP, l = (idx / PP) * CPL;
+        if (idx < PP * kLanes && l < nch) {
+          const int64_t cell = (int64_t)wrap(j01 + p / PS, a.G) * a.G + wrap(j02 + p % PS, a.G);
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) {
+            const float2 v = a.X[(int64_t)(c0 + l + k) * a.plane + cell];
+            x[u].v[2 * k] = v.x;
+            x[u].v[2 * k + 1] = v.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int idx = threadIdx.x + (base + u) * kBlock;
+        const int p = idx % PP, l = (idx / PP) * CPL;
+        if (idx < PP * kLanes && l < nch) vstore<CPL>(patch + p * CH + l, x[u]);
+      }
     }
   }
 #pragma unroll
@@ -177,23 +208,42 @@ __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __r
   __syncthreads();
   const int g = threadIdx.x / kLanes;
   const int cl = (threadIdx.x % kLanes) * CPL;
-  if (cl >= nch) return;
-  for (int i = g; i < ns; i += kGroups) {
-    const float2* p = patch + s_base[i] * CH + cl;
-    const float* w = s_val + i * WP;
-    Vec<CPL> acc;
-    vzero(acc);
+  if (cl < nch) {
+    for (int i = g; i < ns; i += kGroups) {
+      const float2* p = patch + s_base[i] * CH + cl;
+      const float* w = s_val + i * WP;
+      Vec<CPL> acc;
+      vzero(acc);
 #pragma unroll
-    for (int s1 = 0; s1 < KW; ++s1)
+      for (int s1 = 0; s1 < KW; ++s1)
 #pragma unroll
-      for (int s2 = 0; s2 < KW; ++s2) {
-        const Vec<CPL> x = vload<CPL>(p + (s1 * PS + s2) * CH);
-        const float ws = w[s1 * KW + s2];
+        for (int s2 = 0; s2 < KW; ++s2) {
+          const Vec<CPL> x = vload<CPL>(p + (s1 * PS + s2) * CH);
+          const float ws = w[s1 * KW + s2];
 #pragma unroll
-        for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += ws * x.v[k];
+          for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += ws * x.v[k];
+        }
+      if (a.yplane == 0) {
+        vstore<CPL>(a.Y + (int64_t)s_row[i] * a.C + c0 + cl, acc);
+      } else {
+        // channel-slowest polar rows: sample (kf, a) at a*L + kf of every channel plane; the
+        // samples of a tile are ordered by angle, then radius, so neighbouring lane groups write
+        // runs of consecutive radii
+        const int r = s_row[i], kf = r / a.nt;
+        const int64_t at = (int64_t)(r - kf * a.nt) * a.L + kf;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+          a.Y[(int64_t)(c0 + cl + k) * a.yplane + at] = make_float2(acc.v[2 * k], acc.v[2 * k + 1]);
       }
-    vstore<CPL>(a.Y + (int64_t)s_row[i] * a.C + c0 + cl, acc);
+    }
   }
+}
+
+template <int CPL, typename V, int KW, int PS, int MAXP>
+__global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __restrict__ val) {
+  extern __shared__ float2 smem[];
+  fwd_tile_body<CPL, V, KW, PS, MAXP>(a, val, (int)xcd_remap(blockIdx.x, gridDim.x),
+                                      blockIdx.y * kLanes * CPL, smem);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -205,83 +255,219 @@ struct AdjWinArgs {
   const uint16_t* wi_boff;
   const int32_t* q_row;
   const float2* Y;
-  float2* X;
+  float2* X;                  // plane == 0: [G*G][C] channel-fastest; else [C][G*G] (plane = G*G)
   const float* dscale;        // per FFT-ordered radial index, or null
   int C, G, oG, NT, nt, QMAX;
+  int64_t plane;
+};
+
+// Store the CPL channels ch0 .. of grid cell `cell`: one 8*CPL-byte store into the channel-
+// fastest grid, or one float2 per channel plane of the channel-slowest grid (the 8 cells of a
+// tile row, held by neighbouring lane groups, then form one 64-byte run per plane).
+template <int CPL>
+__device__ __forceinline__ void store_cell(float2* X, int64_t cell, int C, int ch0, int64_t plane,
+                                           const Vec<CPL>& v) {
+  if (plane == 0) {
+    vstore<CPL>(X + cell * C + ch0, v);
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) X[(int64_t)(ch0 + k) * plane + cell] = make_float2(v.v[2 * k], v.v[2 * k + 1]);
+  }
+}
+
+// Chunked segments of the dense tiles (and, in one launch, the staged tiles as one-chunk
+// segments).  Blocks b < n_first run segments seg0 + b in dispatch order (the long dense
+// segments start first, spread over the XCDs); the others run segments seg1 + j, j the
+// XCD-aware remap of b - n_first (neighbouring tiles on one XCD).
+struct AdjSegArgs {
+  AdjWinArgs w;               // chunk arrays (wi_q, wi_boff indexed by chunk), Y, X, scale
+  const int32_t* seg_tile;
+  const int32_t* seg_chunk;
+  const int32_t* seg_slot;
+  const int32_t* chunk_tile;  // tile of every chunk
+  float2* part;               // [n_slot][TS*TS][C] partial tiles
+  int seg0, n_first, seg1;
+  int max_chunks;             // most chunks of any segment
 };
 
 constexpr int kMaxAdjPoints = 256;
+
+template <int KW, int TS>
+struct AdjShape {
+  static constexpr int W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
+  static constexpr int RS = TS + 2 * H, NBO = RS * RS + 1;
+};
+
+// Registers of one chunk between its loads and its LDS stores: bucket offsets, raw window values,
+// polar rows and the rows of Y they name.
+template <int CPL, int KW, int TS, int MAXP>
+struct ChunkRegs {
+  using S = AdjShape<KW, TS>;
+  static constexpr int NBL = (S::NBO + kBlock - 1) / kBlock;             // bucket offsets
+  static constexpr int NVL = (MAXP * S::W2 + kBlock - 1) / kBlock;        // value loads
+  static constexpr int NYL = (MAXP * kLanes + kBlock - 1) / kBlock;       // row loads
+  int bo[NBL];
+  uint32_t v[NVL];
+  int r[NYL];
+  Vec<CPL> y[NYL];
+  int nq;
+};
+
+// Issue the loads of chunk w's bucket offsets, values and polar rows (samples q0 .. q0+nq-1).
+template <int CPL, typename V, int KW, int TS, int MAXP>
+__device__ __forceinline__ void chunk_meta(const AdjWinArgs& a, const V* __restrict__ val, int w,
+                                           int q0, int nq, int nch, ChunkRegs<CPL, KW, TS, MAXP>& R) {
+  using S = AdjShape<KW, TS>;
+  using CR = ChunkRegs<CPL, KW, TS, MAXP>;
+  R.nq = nq;
+#pragma unroll
+  for (int u = 0; u < CR::NBL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    R.bo[u] = (k < S::NBO) ? (int)a.wi_boff[(int64_t)w * S::NBO + k] : 0;
+  }
+  // every value load is issued (entries past the chunk read entry 0 and are never stored): a
+  // predicated 16-bit load was compiled into a load-and-wait per value, serialising them
+#pragma unroll
+  for (int u = 0; u < CR::NVL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    R.v[u] = ldraw(val, (k < nq * S::W2) ? (int64_t)q0 * S::W2 + k : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < CR::NYL; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    const int l = (idx % kLanes) * CPL;
+    R.r[u] = (idx < nq * kLanes && l < nch) ? a.q_row[q0 + idx / kLanes] : -1;
+  }
+}
+
+// Issue the loads of the rows of Y the chunk's samples name.
+template <int CPL, int KW, int TS, int MAXP>
+__device__ __forceinline__ void chunk_rows(const AdjWinArgs& a, int c0, ChunkRegs<CPL, KW, TS, MAXP>& R) {
+  using CR = ChunkRegs<CPL, KW, TS, MAXP>;
+#pragma unroll
+  for (int u = 0; u < CR::NYL; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    const int l = (idx % kLanes) * CPL;
+    if (R.r[u] >= 0) R.y[u] = vload<CPL>(a.Y + (int64_t)R.r[u] * a.C + c0 + l);
+  }
+}
+
+// Scale the rows by D (SCALE) and store the chunk to LDS.
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+__device__ __forceinline__ void chunk_store(const AdjWinArgs& a, const V* __restrict__ val,
+                                            ChunkRegs<CPL, KW, TS, MAXP>& R, float2* sy, float* sv,
+                                            int* sb) {
+  using S = AdjShape<KW, TS>;
+  using CR = ChunkRegs<CPL, KW, TS, MAXP>;
+  constexpr int CH = kLanes * CPL;
+  if constexpr (SCALE) {
+#pragma unroll
+    for (int u = 0; u < CR::NYL; ++u)
+      if (R.r[u] >= 0) {
+        const float d = a.dscale[R.r[u] / a.nt];
+#pragma unroll
+        for (int k = 0; k < 2 * CPL; ++k) R.y[u].v[k] *= d;
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < CR::NBL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    if (k < S::NBO) sb[k] = R.bo[u];
+  }
+#pragma unroll
+  for (int u = 0; u < CR::NVL; ++u) {
+    const int k = threadIdx.x + u * kBlock;
+    if (k < R.nq * S::W2) sv[(k / S::W2) * S::WP + k % S::W2] = cvt(val, R.v[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < CR::NYL; ++u) {
+    const int idx = threadIdx.x + u * kBlock;
+    if (R.r[u] >= 0) vstore<CPL>(sy + (idx / kLanes) * CH + (idx % kLanes) * CPL, R.y[u]);
+  }
+}
+
+// Stage one chunk (work item) w into LDS: its bucket offsets, window values and the rows of Y
+// its samples name (times D when SCALE).  All loads of a kind are issued before the LDS stores.
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+__device__ __forceinline__ void adj_stage(const AdjWinArgs& a, const V* __restrict__ val, int w,
+                                          int c0, int nch, float2* sy, float* sv, int* sb) {
+  ChunkRegs<CPL, KW, TS, MAXP> R;
+  const int q0 = a.wi_q[w];
+  chunk_meta<CPL, V, KW, TS, MAXP>(a, val, w, q0, a.wi_q[w + 1] - q0, nch, R);
+  chunk_rows<CPL, KW, TS, MAXP>(a, c0, R);
+  chunk_store<CPL, V, KW, TS, SCALE, MAXP>(a, val, R, sy, sv, sb);
+}
+
+// Add to acc the staged chunk's contributions to tile cell (m1, m2), channels cl .. cl+CPL-1:
+// for window row p1 the k_w buckets (centre cells (m1 + 2h - p1, m2 + t), t < k_w) are
+// consecutive in the region, so their samples form one run; bucket t holds window column
+// p2 = 2h - t.  One loop per window row instead of one per bucket.
+template <int CPL, int KW, int TS>
+__device__ __forceinline__ void adj_cell(Vec<CPL>& acc, const float2* sy, const float* sv,
+                                         const int* sb, int m1, int m2, int cl) {
+  using S = AdjShape<KW, TS>;
+  constexpr int CH = kLanes * CPL, WP = S::WP, H = S::H, RS = S::RS;
+#pragma unroll
+  for (int p1 = 0; p1 < KW; ++p1) {
+    const int rb = (m1 + 2 * H - p1) * RS + m2;
+    int o[KW + 1];
+#pragma unroll
+    for (int t = 0; t <= KW; ++t) o[t] = sb[rb + t];
+    const float* wrow = sv + p1 * KW + 2 * H;
+    for (int k = o[0]; k < o[KW]; ++k) {
+      int t = 0;
+#pragma unroll
+      for (int u = 1; u < KW; ++u) t += (k >= o[u]) ? 1 : 0;
+      const float w = wrow[k * WP - t];
+      const Vec<CPL> x = vload<CPL>(sy + k * CH + cl);
+#pragma unroll
+      for (int q = 0; q < 2 * CPL; ++q) acc.v[q] += w * x.v[q];
+    }
+  }
+}
+
+// adj_cell summing into float64 totals: each product rounded once in float32, the sums exact to
+// float64 (cells near the Fourier origin sum thousands of same-sign terms)
+template <int CPL, int KW, int TS>
+__device__ __forceinline__ void adj_cell_f64(double (&tot)[2 * CPL], const float2* sy,
+                                             const float* sv, const int* sb, int m1, int m2, int cl) {
+  using S = AdjShape<KW, TS>;
+  constexpr int CH = kLanes * CPL, WP = S::WP, H = S::H, RS = S::RS;
+#pragma unroll
+  for (int p1 = 0; p1 < KW; ++p1) {
+    const int rb = (m1 + 2 * H - p1) * RS + m2;
+    int o[KW + 1];
+#pragma unroll
+    for (int t = 0; t <= KW; ++t) o[t] = sb[rb + t];
+    const float* wrow = sv + p1 * KW + 2 * H;
+    for (int k = o[0]; k < o[KW]; ++k) {
+      int t = 0;
+#pragma unroll
+      for (int u = 1; u < KW; ++u) t += (k >= o[u]) ? 1 : 0;
+      const float w = wrow[k * WP - t];
+      const Vec<CPL> x = vload<CPL>(sy + k * CH + cl);
+#pragma unroll
+      for (int q = 0; q < 2 * CPL; ++q) tot[q] += (double)(w * x.v[q]);
+    }
+  }
+}
 
 // One block per staged tile, placed by an XCD-aware remap so that neighbouring tiles share an
 // L2.  The block loads its list offsets, then its sample rows, values and bucket offsets, then
 // the rows of Y those samples name.
 template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
 __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __restrict__ val) {
-  constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
-  constexpr int RS = TS + 2 * H, NBO = RS * RS + 1;
-  constexpr int NBL = (NBO + kBlock - 1) / kBlock;                      // bucket offsets
-  constexpr int NVL = (MAXP * W2 + kBlock - 1) / kBlock;                // value loads
-  constexpr int NYL = (MAXP * kLanes + kBlock - 1) / kBlock;            // row loads
+  using S = AdjShape<KW, TS>;
+  constexpr int CH = kLanes * CPL;
   extern __shared__ float2 smem[];
   float2* sy = smem;                                                     // [QMAX][CH]
   float* sv = reinterpret_cast<float*>(sy + a.QMAX * CH);                // [QMAX][WP]
-  int* sb = reinterpret_cast<int*>(sv + a.QMAX * WP);                    // [NBO]
+  int* sb = reinterpret_cast<int*>(sv + a.QMAX * S::WP);                 // [NBO]
   const int wi = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int c0 = blockIdx.y * CH;
   const int nch = min(CH, a.C - c0);
   const int tl = a.wi_tile[wi];
-  const int q0 = a.wi_q[wi], nq = a.wi_q[wi + 1] - q0;
-  int bo[NBL];
-#pragma unroll
-  for (int u = 0; u < NBL; ++u) {
-    const int k = threadIdx.x + u * kBlock;
-    bo[u] = (k < NBO) ? (int)a.wi_boff[(int64_t)wi * NBO + k] : 0;
-  }
-  uint32_t v[NVL];
-#pragma unroll
-  for (int u = 0; u < NVL; ++u) {
-    const int k = threadIdx.x + u * kBlock;
-    v[u] = 0;
-    if (k < nq * W2) v[u] = ldraw(val, (int64_t)q0 * W2 + k);
-  }
-  int r[NYL];
-#pragma unroll
-  for (int u = 0; u < NYL; ++u) {
-    const int idx = threadIdx.x + u * kBlock;
-    const int l = (idx % kLanes) * CPL;
-    r[u] = (idx < nq * kLanes && l < nch) ? a.q_row[q0 + idx / kLanes] : -1;
-  }
-  Vec<CPL> y[NYL];
-#pragma unroll
-  for (int u = 0; u < NYL; ++u) {
-    const int idx = threadIdx.x + u * kBlock;
-    const int l = (idx % kLanes) * CPL;
-    if (r[u] >= 0) y[u] = vload<CPL>(a.Y + (int64_t)r[u] * a.C + c0 + l);
-  }
-  if constexpr (SCALE) {
-#pragma unroll
-    for (int u = 0; u < NYL; ++u)
-      if (r[u] >= 0) {
-        const float d = a.dscale[r[u] / a.nt];
-#pragma unroll
-        for (int k = 0; k < 2 * CPL; ++k) y[u].v[k] *= d;
-      }
-  }
-#pragma unroll
-  for (int u = 0; u < NBL; ++u) {
-    const int k = threadIdx.x + u * kBlock;
-    if (k < NBO) sb[k] = bo[u];
-  }
-#pragma unroll
-  for (int u = 0; u < NVL; ++u) {
-    const int k = threadIdx.x + u * kBlock;
-    if (k < nq * W2) sv[(k / W2) * WP + k % W2] = cvt(val, v[u]);
-  }
-#pragma unroll
-  for (int u = 0; u < NYL; ++u) {
-    const int idx = threadIdx.x + u * kBlock;
-    if (r[u] >= 0) vstore<CPL>(sy + (idx / kLanes) * CH + (idx % kLanes) * CPL, y[u]);
-  }
+  adj_stage<CPL, V, KW, TS, SCALE, MAXP>(a, val, wi, c0, nch, sy, sv, sb);
   __syncthreads();
   const int g = threadIdx.x / kLanes;
   const int cl = (threadIdx.x % kLanes) * CPL;
@@ -293,37 +479,217 @@ __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __res
     if (j1 > a.G - 1 - a.oG || j2 > a.G - 1 - a.oG) continue;   // past the grid's end
     Vec<CPL> acc;
     vzero(acc);
-    // for window row p1 the k_w buckets (centre cells (m1 + 2h - p1, m2 + t), t < k_w) are
-    // consecutive in the region, so their samples form one run; bucket t holds window column
-    // p2 = 2h - t.  One loop per window row instead of one per bucket.
+    adj_cell<CPL, KW, TS>(acc, sy, sv, sb, m1, m2, cl);
+    store_cell<CPL>(a.X, (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G), a.C, c0 + cl, a.plane, acc);
+  }
+}
+
+// Segment sg (channels c0 .. c0 + 8*CPL - 1) of a block: its chunks in order, each staged in
+// LDS and summed into the cells' registers.  When the next chunk belongs to another tile (a run
+// of staged tiles), or at the end, the tile's sums go to X, or to the segment's partial slot when
+// its tile is split over several segments; sums run over chunks in order (run-to-run identical).
+// (Loading the next chunk while summing the current one needs a second register set; at 106
+// VGPRs that halved the blocks per CU and was slower.)
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+__device__ __forceinline__ void adj_seg_body(const AdjSegArgs& s, const V* __restrict__ val, int sg,
+                                             int c0, float2* smem) {
+  using S = AdjShape<KW, TS>;
+  constexpr int CH = kLanes * CPL, NC = (TS * TS + kGroups - 1) / kGroups;
+  const AdjWinArgs& a = s.w;
+  float2* sy = smem;
+  float* sv = reinterpret_cast<float*>(sy + a.QMAX * CH);
+  int* sb = reinterpret_cast<int*>(sv + a.QMAX * S::WP);
+  const int nch = min(CH, a.C - c0);
+  const int k0 = s.seg_chunk[sg], n = s.seg_chunk[sg + 1] - k0;
+  const int slot = s.seg_slot[sg];
+  const int g = threadIdx.x / kLanes;
+  const int cl = (threadIdx.x % kLanes) * CPL;
+  // every cell's sum in float64 over all its chunks (products rounded once in float32): the cell
+  // at the Fourier origin sums 4,743 same-sign terms, up to ~130 of them from one chunk, and
+  // float32 sums there (running over the chunks: 3.8e-5; within each chunk: 5e-6) moved a 2048^2
+  // back-projection through the DC coefficient by more than the row kernels' tree sums do
+  double tot[NC][2 * CPL];
 #pragma unroll
-    for (int p1 = 0; p1 < KW; ++p1) {
-      const int rb = (m1 + 2 * H - p1) * RS + m2;
-      int o[KW + 1];
+  for (int u = 0; u < NC; ++u)
 #pragma unroll
-      for (int t = 0; t <= KW; ++t) o[t] = sb[rb + t];
-      const float* wrow = sv + p1 * KW + 2 * H;
-      for (int k = o[0]; k < o[KW]; ++k) {
-        int t = 0;
+    for (int q = 0; q < 2 * CPL; ++q) tot[u][q] = 0.0;
+  // chunk bounds and tiles are uniform across the block (scalar loads, issued per chunk)
+  int tl = s.chunk_tile[k0];
+  for (int i = 0; i < n; ++i) {
+    if (i > 0) __syncthreads();                    // the previous chunk's reads are done
+    const int q0 = a.wi_q[k0 + i], q1 = a.wi_q[k0 + i + 1];
+    const int next_tl = (i + 1 < n) ? s.chunk_tile[k0 + i + 1] : -1;
+    {
+      ChunkRegs<CPL, KW, TS, MAXP> R;
+      chunk_meta<CPL, V, KW, TS, MAXP>(a, val, k0 + i, q0, q1 - q0, nch, R);
+      chunk_rows<CPL, KW, TS, MAXP>(a, c0, R);
+      chunk_store<CPL, V, KW, TS, SCALE, MAXP>(a, val, R, sy, sv, sb);
+    }
+    __syncthreads();
+    if (cl < nch) {
 #pragma unroll
-        for (int u = 1; u < KW; ++u) t += (k >= o[u]) ? 1 : 0;
-        const float w = wrow[k * WP - t];
-        const Vec<CPL> x = vload<CPL>(sy + k * CH + cl);
-#pragma unroll
-        for (int q = 0; q < 2 * CPL; ++q) acc.v[q] += w * x.v[q];
+      for (int u = 0; u < NC; ++u) {
+        const int c = g + u * kGroups;
+        if (c < TS * TS) adj_cell_f64<CPL, KW, TS>(tot[u], sy, sv, sb, c / TS, c % TS, cl);
       }
     }
-    vstore<CPL>(a.X + ((int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G)) * a.C + c0 + cl, acc);
+    if (next_tl == tl) continue;
+    if (cl < nch) {
+      const int jb1 = -a.oG + (tl / a.NT) * TS, jb2 = -a.oG + (tl % a.NT) * TS;
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int c = g + u * kGroups;
+        if (c >= TS * TS) continue;
+        Vec<CPL> out;
+#pragma unroll
+        for (int q = 0; q < 2 * CPL; ++q) out.v[q] = (float)tot[u][q];
+        if (slot >= 0) {
+          vstore<CPL>(s.part + ((int64_t)slot * TS * TS + c) * a.C + c0 + cl, out);
+        } else {
+          const int j1 = jb1 + c / TS, j2 = jb2 + c % TS;
+          if (j1 <= a.G - 1 - a.oG && j2 <= a.G - 1 - a.oG)   // else past the grid's end
+            store_cell<CPL>(a.X, (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G), a.C, c0 + cl, a.plane,
+                            out);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u)
+#pragma unroll
+      for (int q = 0; q < 2 * CPL; ++q) tot[u][q] = 0.0;
+    tl = next_tl;
+  }
+}
+
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+__global__ __launch_bounds__(kBlock) void k_adj_seg(AdjSegArgs s, const V* __restrict__ val) {
+  extern __shared__ float2 smem[];
+  const int b = blockIdx.x;
+  const int sg = (b < s.n_first) ? s.seg0 + b
+                                 : s.seg1 + (int)xcd_remap(b - s.n_first, gridDim.x - s.n_first);
+  adj_seg_body<CPL, V, KW, TS, SCALE, MAXP>(s, val, sg, blockIdx.y * kLanes * CPL, smem);
+}
+
+// Split dense tiles: block i sums partial tiles red_slot[i] .. red_slot[i+1]-1 in order into tile
+// red_tile[i] of X; a thread owns one (cell, channel) pair at a time.
+__global__ __launch_bounds__(kBlock) void k_adj_seg_reduce(const int32_t* __restrict__ red_tile,
+                                                           const int32_t* __restrict__ red_slot,
+                                                           const float2* __restrict__ part,
+                                                           float2* __restrict__ X, int C, int G,
+                                                           int oG, int NT, int TS, int64_t plane) {
+  const int i = blockIdx.x;
+  const int tl = red_tile[i], s0 = red_slot[i], s1 = red_slot[i + 1];
+  const int jb1 = -oG + (tl / NT) * TS, jb2 = -oG + (tl % NT) * TS;
+  const int n = TS * TS * C;
+  for (int e = threadIdx.x; e < n; e += kBlock) {
+    const int c = e / C, ch = e % C;
+    const int j1 = jb1 + c / TS, j2 = jb2 + c % TS;
+    if (j1 > G - 1 - oG || j2 > G - 1 - oG) continue;
+    double ax = 0.0, ay = 0.0;                      // float64 sum of the partial tiles
+    for (int sl = s0; sl < s1; ++sl) {
+      const float2 p = part[(int64_t)sl * TS * TS * C + e];
+      ax += p.x;
+      ay += p.y;
+    }
+    const int64_t cell = (int64_t)wrap(j1, G) * G + wrap(j2, G);
+    X[plane == 0 ? cell * C + ch : (int64_t)ch * plane + cell] = make_float2((float)ax, (float)ay);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// persistent launches over a stack of operators (one SpMM-pair item per operator and batch)
+// ------------------------------------------------------------------------------------------
+// Work entry (item, index): forward index = work item * n_cc + channel chunk; adjoint index =
+// segment * n_cc + channel chunk; reduction index = split tile.  Blocks walk the list with a
+// grid stride; entries [0, n_first) go to blocks in dispatch order (long dense segments spread
+// over the XCDs), the rest through the XCD-aware remap (neighbouring tiles on one XCD).
+struct StackFwdItem {
+  FwdTileArgs a;
+  const void* val;
+  int cpl, n_cc;
+};
+
+struct StackAdjItem {
+  AdjSegArgs s;
+  const void* val;
+  const int32_t* red_tile;
+  const int32_t* red_slot;
+  int cpl, n_cc;
+};
+
+__device__ __forceinline__ int64_t stack_pos(int64_t phys, int64_t n_first, int64_t n_work) {
+  return phys < n_first ? phys : n_first + xcd_remap(phys - n_first, n_work - n_first);
+}
+
+template <typename V, int KW, int PS, int MAXP>
+__global__ __launch_bounds__(kBlock) void k_stack_fwd(const StackFwdItem* __restrict__ items,
+                                                      const int2* __restrict__ work, int n_work) {
+  extern __shared__ float2 smem[];
+  for (int64_t phys = blockIdx.x; phys < n_work; phys += gridDim.x) {
+    const int2 e = work[stack_pos(phys, 0, n_work)];
+    const StackFwdItem& it = items[e.x];
+    const int wi = e.y / it.n_cc, cc = e.y % it.n_cc;
+    if (it.cpl == 2)
+      fwd_tile_body<2, V, KW, PS, MAXP>(it.a, (const V*)it.val, wi, cc * kLanes * 2, smem);
+    else
+      fwd_tile_body<1, V, KW, PS, MAXP>(it.a, (const V*)it.val, wi, cc * kLanes, smem);
+    __syncthreads();                                   // LDS is reused by the next entry
+  }
+}
+
+template <typename V, int KW, int TS, int MAXP>
+__global__ __launch_bounds__(kBlock) void k_stack_adj(const StackAdjItem* __restrict__ items,
+                                                      const int2* __restrict__ work, int n_work,
+                                                      int n_first) {
+  extern __shared__ float2 smem[];
+  for (int64_t phys = blockIdx.x; phys < n_work; phys += gridDim.x) {
+    const int2 e = work[stack_pos(phys, n_first, n_work)];
+    const StackAdjItem& it = items[e.x];
+    const int sg = e.y / it.n_cc, cc = e.y % it.n_cc;
+    if (it.cpl == 2)
+      adj_seg_body<2, V, KW, TS, false, MAXP>(it.s, (const V*)it.val, sg, cc * kLanes * 2, smem);
+    else
+      adj_seg_body<1, V, KW, TS, false, MAXP>(it.s, (const V*)it.val, sg, cc * kLanes, smem);
+    __syncthreads();
+  }
+}
+
+// split dense tiles of every item: partial tiles summed in order into X
+__global__ __launch_bounds__(kBlock) void k_stack_reduce(const StackAdjItem* __restrict__ items,
+                                                         const int2* __restrict__ work, int n_work,
+                                                         int TS) {
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int2 e = work[w];
+    const StackAdjItem& it = items[e.x];
+    const AdjWinArgs& a = it.s.w;
+    const int i = e.y;
+    const int tl = it.red_tile[i], s0 = it.red_slot[i], s1 = it.red_slot[i + 1];
+    const int jb1 = -a.oG + (tl / a.NT) * TS, jb2 = -a.oG + (tl % a.NT) * TS;
+    const int n = TS * TS * a.C;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+      const int c = k / a.C, ch = k % a.C;
+      const int j1 = jb1 + c / TS, j2 = jb2 + c % TS;
+      if (j1 > a.G - 1 - a.oG || j2 > a.G - 1 - a.oG) continue;
+      double ax = 0.0, ay = 0.0;                    // float64 sum of the partial tiles
+      for (int sl = s0; sl < s1; ++sl) {
+        const float2 p = it.s.part[(int64_t)sl * TS * TS * a.C + k];
+        ax += p.x;
+        ay += p.y;
+      }
+      a.X[((int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G)) * a.C + ch] = make_float2((float)ax, (float)ay);
+    }
   }
 }
 
 template <int CPL, typename V>
-tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y, int C,
+tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y, int C, bool slow,
                           hipStream_t st) {
   const DevFwdTiles& d = op->ftile;
   constexpr int CH = kLanes * CPL;
   FwdTileArgs a{d.wi_tile, d.wi_beg, d.pt_row, d.pt_base, X, Y,
-                C, op->g.G, op->g.G / 2, d.TS, d.NT, op->tune.tile_points};
+                C, op->g.G, op->g.G / 2, d.TS, d.NT, op->tune.tile_points,
+                slow ? (int64_t)op->g.G * op->g.G : 0, slow ? (int64_t)op->g.nt * op->g.L : 0,
+                op->g.nt, op->g.L};
   const size_t lds = fwd_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
   const V* v = (const V*)d.val[vt];
@@ -347,12 +713,12 @@ tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y,
 
 template <int CPL, typename V>
 tomo_status adj_tile_impl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
-                          const float* dscale, hipStream_t st) {
+                          const float* dscale, bool slow, hipStream_t st) {
   const DevAdjWin& d = op->awin;
   if (d.n_wi == 0) return TOMO_OK;
   constexpr int CH = kLanes * CPL;
   AdjWinArgs a{d.wi_tile, d.wi_q, d.wi_boff, d.q_row, Y, X, dscale,
-               C, op->g.G, op->g.G / 2, d.NT, op->g.nt, d.QMAX};
+               C, op->g.G, op->g.G / 2, d.NT, op->g.nt, d.QMAX, slow ? (int64_t)op->g.G * op->g.G : 0};
   const size_t lds = adj_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
   const V* v = (const V*)d.q_val[vt];
@@ -377,6 +743,52 @@ tomo_status adj_tile_impl(const tomo_op* op, int vt, const float2* Y, float2* X,
 #undef TOMO_ADJ_WIN_P
   return fail(TOMO_EUNSUPPORTED, "staged adjoint kernel has no variant for k_w %d, tile %d", d.KW,
               d.TS);
+}
+
+template <int CPL, typename V>
+tomo_status adj_seg_impl(const tomo_op* op, int vt, const float2* Y, float2* X, int C,
+                         const float* dscale, bool dense, bool staged, bool slow, hipStream_t st) {
+  const DevAdjWin& d = op->awin;
+  const int n_dense = (int)(d.n_seg - d.n_sseg);
+  const int n_first = dense ? n_dense : 0;
+  const int nblk = n_first + (staged ? (int)d.n_sseg : 0);
+  if (nblk == 0) return TOMO_OK;
+  constexpr int CH = kLanes * CPL;
+  const int64_t plane = slow ? (int64_t)op->g.G * op->g.G : 0;
+  AdjSegArgs a{{d.wi_tile, d.wi_q, d.wi_boff, d.q_row, Y, X, dscale, C, op->g.G, op->g.G / 2, d.NT,
+                op->g.nt, d.QMAX, plane},
+               d.seg_tile, d.seg_chunk, d.seg_slot, d.chunk_tile, op->seg_partials,
+               (int)d.n_sseg, n_first, 0, d.max_seg_chunks};
+  const size_t lds = adj_seg_lds_bytes(op, C);
+  dim3 grid((unsigned)nblk, (unsigned)((C + CH - 1) / CH));
+  const V* v = (const V*)d.q_val[vt];
+  const bool small = d.QMAX <= 128;
+#define TOMO_ADJ_SEG_P(KW_, TS_, P_)                                                             \
+  if (dscale)                                                                                   \
+    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, true, P_>), grid, dim3(kBlock), lds, st, a, v); \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, false, P_>), grid, dim3(kBlock), lds, st, a, v);
+#define TOMO_ADJ_SEG(KW_, TS_)                                                                   \
+  if (d.KW == KW_ && d.TS == TS_) {                                                             \
+    if (small) {                                                                                \
+      TOMO_ADJ_SEG_P(KW_, TS_, 128)                                                             \
+    } else {                                                                                    \
+      TOMO_ADJ_SEG_P(KW_, TS_, kMaxAdjPoints)                                                   \
+    }                                                                                           \
+    TOMO_HIP(hipGetLastError());                                                                \
+    if (dense && d.n_red > 0) {                                                                 \
+      hipLaunchKernelGGL(k_adj_seg_reduce, dim3((unsigned)d.n_red), dim3(kBlock), 0, st,         \
+                         d.red_tile, d.red_slot, op->seg_partials, X, C, op->g.G, op->g.G / 2,  \
+                         d.NT, d.TS, plane);                                                    \
+      TOMO_HIP(hipGetLastError());                                                              \
+    }                                                                                           \
+    return TOMO_OK;                                                                             \
+  }
+  TOMO_ADJ_SEG(3, 8) TOMO_ADJ_SEG(3, 16) TOMO_ADJ_SEG(5, 8) TOMO_ADJ_SEG(5, 16)
+#undef TOMO_ADJ_SEG
+#undef TOMO_ADJ_SEG_P
+  return fail(TOMO_EUNSUPPORTED, "staged adjoint segment kernel has no variant for k_w %d, tile %d",
+              d.KW, d.TS);
 }
 
 }  // namespace
@@ -408,30 +820,245 @@ size_t adj_tile_lds_bytes(const tomo_op* op, int C) {
          (size_t)(d.RS * d.RS + 1) * sizeof(int);
 }
 
+size_t adj_seg_lds_bytes(const tomo_op* op, int C) { return adj_tile_lds_bytes(op, C); }
+
 tomo_status launch_fwd_tile(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
-                            hipStream_t st) {
+                            bool slow, hipStream_t st) {
   const bool even = (C % 2 == 0);
   switch (vt) {
     case TOMO_VAL_F32:
-      return even ? fwd_tile_impl<2, float>(op, vt, X, Y, C, st) : fwd_tile_impl<1, float>(op, vt, X, Y, C, st);
+      return even ? fwd_tile_impl<2, float>(op, vt, X, Y, C, slow, st) : fwd_tile_impl<1, float>(op, vt, X, Y, C, slow, st);
     case TOMO_VAL_BF16:
-      return even ? fwd_tile_impl<2, bf16_t>(op, vt, X, Y, C, st) : fwd_tile_impl<1, bf16_t>(op, vt, X, Y, C, st);
+      return even ? fwd_tile_impl<2, bf16_t>(op, vt, X, Y, C, slow, st) : fwd_tile_impl<1, bf16_t>(op, vt, X, Y, C, slow, st);
     default:
-      return even ? fwd_tile_impl<2, _Float16>(op, vt, X, Y, C, st) : fwd_tile_impl<1, _Float16>(op, vt, X, Y, C, st);
+      return even ? fwd_tile_impl<2, _Float16>(op, vt, X, Y, C, slow, st) : fwd_tile_impl<1, _Float16>(op, vt, X, Y, C, slow, st);
+  }
+}
+
+tomo_status launch_adj_seg(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
+                           const float* dscale, bool dense, bool staged, bool slow, hipStream_t st) {
+  const bool even = (C % 2 == 0);
+  switch (vt) {
+    case TOMO_VAL_F32:
+      return even ? adj_seg_impl<2, float>(op, vt, Y, X, C, dscale, dense, staged, slow, st)
+                  : adj_seg_impl<1, float>(op, vt, Y, X, C, dscale, dense, staged, slow, st);
+    case TOMO_VAL_BF16:
+      return even ? adj_seg_impl<2, bf16_t>(op, vt, Y, X, C, dscale, dense, staged, slow, st)
+                  : adj_seg_impl<1, bf16_t>(op, vt, Y, X, C, dscale, dense, staged, slow, st);
+    default:
+      return even ? adj_seg_impl<2, _Float16>(op, vt, Y, X, C, dscale, dense, staged, slow, st)
+                  : adj_seg_impl<1, _Float16>(op, vt, Y, X, C, dscale, dense, staged, slow, st);
   }
 }
 
 tomo_status launch_adj_tile(const tomo_op* op, const float2* Y, float2* X, int C, int vt,
-                            const float* dscale, hipStream_t st) {
+                            const float* dscale, bool slow, hipStream_t st) {
   const bool even = (C % 2 == 0);
   switch (vt) {
     case TOMO_VAL_F32:
-      return even ? adj_tile_impl<2, float>(op, vt, Y, X, C, dscale, st) : adj_tile_impl<1, float>(op, vt, Y, X, C, dscale, st);
+      return even ? adj_tile_impl<2, float>(op, vt, Y, X, C, dscale, slow, st) : adj_tile_impl<1, float>(op, vt, Y, X, C, dscale, slow, st);
     case TOMO_VAL_BF16:
-      return even ? adj_tile_impl<2, bf16_t>(op, vt, Y, X, C, dscale, st) : adj_tile_impl<1, bf16_t>(op, vt, Y, X, C, dscale, st);
+      return even ? adj_tile_impl<2, bf16_t>(op, vt, Y, X, C, dscale, slow, st) : adj_tile_impl<1, bf16_t>(op, vt, Y, X, C, dscale, slow, st);
     default:
-      return even ? adj_tile_impl<2, _Float16>(op, vt, Y, X, C, dscale, st) : adj_tile_impl<1, _Float16>(op, vt, Y, X, C, dscale, st);
+      return even ? adj_tile_impl<2, _Float16>(op, vt, Y, X, C, dscale, slow, st) : adj_tile_impl<1, _Float16>(op, vt, Y, X, C, dscale, slow, st);
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// stack plans
+// ------------------------------------------------------------------------------------------
+struct StackPlan {
+  int device = -1, vt = 0, KW = 0, TS = 0;
+  bool fwd_big = false, adj_big = false;        // work-item capacities above 64 / 128 samples
+  StackFwdItem* d_fwd = nullptr;
+  StackAdjItem* d_adj = nullptr;
+  int2 *d_wf = nullptr, *d_wa = nullptr, *d_wr = nullptr;
+  int n_wf = 0, n_wa = 0, n_first = 0, n_wr = 0;
+  size_t lds_f = 0, lds_a = 0;
+  int grid_f = 0, grid_a = 0, grid_r = 0;
+  std::vector<float2*> partials;                // per item: its split tiles' partial tiles
+};
+
+namespace {
+
+template <typename V, int KW, int TS, int MPF, int MPA>
+tomo_status stack_kernels(StackPlan* p, hipStream_t st, bool size_only, int n_cu) {
+  constexpr int PS = TS + 2 * (KW / 2) + 1;
+  auto kf = k_stack_fwd<V, KW, PS, MPF>;
+  auto ka = k_stack_adj<V, KW, TS, MPA>;
+  if (size_only) {
+    // one grid of resident blocks per kernel (a multiple of the 8 XCDs), no larger than the work
+    auto grid = [&](const void* k, size_t lds, int n_work, int* out) -> tomo_status {
+      int per_cu = 0;
+      TOMO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, lds));
+      int g = std::max(8, per_cu * n_cu / 8 * 8);
+      *out = std::max(1, std::min(g, n_work));
+      return TOMO_OK;
+    };
+    TOMO_TRY(grid((const void*)kf, p->lds_f, p->n_wf, &p->grid_f));
+    TOMO_TRY(grid((const void*)ka, p->lds_a, p->n_wa, &p->grid_a));
+    p->grid_r = std::max(1, std::min(p->n_wr, 8 * n_cu));
+    return TOMO_OK;
+  }
+  if (p->n_wf > 0) {
+    hipLaunchKernelGGL(kf, dim3((unsigned)p->grid_f), dim3(kBlock), p->lds_f, st, p->d_fwd, p->d_wf,
+                       p->n_wf);
+    TOMO_HIP(hipGetLastError());
+  }
+  if (p->n_wa > 0) {
+    hipLaunchKernelGGL(ka, dim3((unsigned)p->grid_a), dim3(kBlock), p->lds_a, st, p->d_adj, p->d_wa,
+                       p->n_wa, p->n_first);
+    TOMO_HIP(hipGetLastError());
+  }
+  if (p->n_wr > 0) {
+    hipLaunchKernelGGL(k_stack_reduce, dim3((unsigned)p->grid_r), dim3(kBlock), 0, st, p->d_adj,
+                       p->d_wr, p->n_wr, TS);
+    TOMO_HIP(hipGetLastError());
+  }
+  return TOMO_OK;
+}
+
+template <typename V>
+tomo_status stack_dispatch_v(StackPlan* p, hipStream_t st, bool size_only, int n_cu) {
+#define TOMO_STACK(KW_, TS_)                                                                     \
+  if (p->KW == KW_ && p->TS == TS_) {                                                           \
+    if (!p->fwd_big && !p->adj_big) return stack_kernels<V, KW_, TS_, 64, 128>(p, st, size_only, n_cu); \
+    if (p->fwd_big && !p->adj_big)                                                              \
+      return stack_kernels<V, KW_, TS_, kMaxTilePoints, 128>(p, st, size_only, n_cu);            \
+    if (!p->fwd_big) return stack_kernels<V, KW_, TS_, 64, kMaxAdjPoints>(p, st, size_only, n_cu); \
+    return stack_kernels<V, KW_, TS_, kMaxTilePoints, kMaxAdjPoints>(p, st, size_only, n_cu);    \
+  }
+  TOMO_STACK(3, 8) TOMO_STACK(3, 16) TOMO_STACK(5, 8) TOMO_STACK(5, 16)
+#undef TOMO_STACK
+  return fail(TOMO_EUNSUPPORTED, "no stack kernels for k_w %d, tile %d", p->KW, p->TS);
+}
+
+tomo_status stack_dispatch(StackPlan* p, hipStream_t st, bool size_only, int n_cu) {
+  switch (p->vt) {
+    case TOMO_VAL_F32: return stack_dispatch_v<float>(p, st, size_only, n_cu);
+    case TOMO_VAL_BF16: return stack_dispatch_v<bf16_t>(p, st, size_only, n_cu);
+    default: return stack_dispatch_v<_Float16>(p, st, size_only, n_cu);
+  }
+}
+
+template <typename T>
+tomo_status to_device(T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return TOMO_OK;
+  if (hipMalloc((void**)dst, v.size() * sizeof(T)) != hipSuccess) {
+    *dst = nullptr;
+    return fail(TOMO_ENOMEM, "stack plan: %zu bytes", v.size() * sizeof(T));
+  }
+  TOMO_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return TOMO_OK;
+}
+
+}  // namespace
+
+void stack_plan_destroy(StackPlan* p) {
+  if (!p) return;
+  (void)hipFree(p->d_fwd);
+  (void)hipFree(p->d_adj);
+  (void)hipFree(p->d_wf);
+  (void)hipFree(p->d_wa);
+  (void)hipFree(p->d_wr);
+  for (float2* q : p->partials) (void)hipFree(q);
+  delete p;
+}
+
+tomo_status stack_plan_create(const StackItemSpec* items, int n, int vt, StackPlan** out) {
+  *out = nullptr;
+  auto* p = new StackPlan();
+  p->vt = vt;
+  p->device = items[0].op->device;
+  std::vector<StackFwdItem> fi;
+  std::vector<StackAdjItem> ai;
+  std::vector<int2> wf, dense, sparse, wr;
+  std::vector<int> dense_len;
+  tomo_status status = TOMO_OK;
+  for (int i = 0; i < n && status == TOMO_OK; ++i) {
+    const tomo_op* op = items[i].op;
+    const DevFwdTiles& f = op->ftile;
+    const DevAdjWin& d = op->awin;
+    const int C = (items[i].batch + 1) / 2;
+    const int cpl = (C % 2 == 0) ? 2 : 1, CH = kLanes * cpl, n_cc = (C + CH - 1) / CH;
+    if (i == 0) {
+      p->KW = f.KW;
+      p->TS = f.TS;
+    }
+    if (f.KW != p->KW || f.TS != p->TS || d.TS != p->TS) {
+      status = fail(TOMO_EINVAL, "stack items must share the kernel width and the tile side");
+      break;
+    }
+    p->fwd_big = p->fwd_big || op->tune.tile_points > 64;
+    p->adj_big = p->adj_big || d.QMAX > 128;
+    p->lds_f = std::max(p->lds_f, fwd_tile_lds_bytes(op, C));
+    p->lds_a = std::max(p->lds_a, adj_seg_lds_bytes(op, C));
+    FwdTileArgs fa{f.wi_tile, f.wi_beg, f.pt_row, f.pt_base, (const float2*)items[i].in,
+                   (float2*)items[i].out, C, op->g.G, op->g.G / 2, f.TS, f.NT, op->tune.tile_points, 0, 0,
+                   op->g.nt, op->g.L};
+    fi.push_back(StackFwdItem{fa, f.val[vt], cpl, n_cc});
+    for (int64_t w = 0; w < f.n_wi; ++w)
+      for (int cc = 0; cc < n_cc; ++cc) wf.push_back(make_int2(i, (int)(w * n_cc + cc)));
+    float2* part = nullptr;
+    if (d.n_slot > 0) {
+      const size_t pb = (size_t)d.n_slot * d.TS * d.TS * C * sizeof(float2);
+      if (hipMalloc((void**)&part, pb) != hipSuccess) {
+        status = fail(TOMO_ENOMEM, "stack partial tiles (%zu B)", pb);
+        break;
+      }
+    }
+    p->partials.push_back(part);
+    AdjSegArgs sa{{d.wi_tile, d.wi_q, d.wi_boff, d.q_row, (const float2*)items[i].out,
+                   (float2*)items[i].aux, nullptr, C, op->g.G, op->g.G / 2, d.NT, op->g.nt, d.QMAX, 0},
+                  d.seg_tile, d.seg_chunk, d.seg_slot, d.chunk_tile, part, 0, 0, 0, d.max_seg_chunks};
+    ai.push_back(StackAdjItem{sa, d.q_val[vt], d.red_tile, d.red_slot, cpl, n_cc});
+    // chunk counts of the dense segments, to start the longest first
+    std::vector<int32_t> sc((size_t)d.n_seg + 1);
+    if (d.n_seg > d.n_sseg)
+      TOMO_HIP(hipMemcpy(sc.data(), d.seg_chunk, sc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t sg = 0; sg < d.n_seg; ++sg)
+      for (int cc = 0; cc < n_cc; ++cc) {
+        const int2 e = make_int2(i, (int)(sg * n_cc + cc));
+        if (sg >= d.n_sseg) {
+          dense.push_back(e);
+          dense_len.push_back(sc[(size_t)sg + 1] - sc[(size_t)sg]);
+        } else {
+          sparse.push_back(e);
+        }
+      }
+    for (int64_t r = 0; r < d.n_red; ++r) wr.push_back(make_int2(i, (int)r));
+  }
+  if (status == TOMO_OK && (p->lds_f > kMaxTileLds || p->lds_a > kMaxTileLds))
+    status = fail(TOMO_EUNSUPPORTED, "stack items need more LDS than a block has");
+  if (status == TOMO_OK) {
+    std::vector<size_t> ord(dense.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return dense_len[x] > dense_len[y]; });
+    std::vector<int2> wa;
+    for (size_t k : ord) wa.push_back(dense[k]);
+    wa.insert(wa.end(), sparse.begin(), sparse.end());
+    p->n_wf = (int)wf.size();
+    p->n_wa = (int)wa.size();
+    p->n_first = (int)dense.size();
+    p->n_wr = (int)wr.size();
+    status = to_device(&p->d_fwd, fi);
+    if (status == TOMO_OK) status = to_device(&p->d_adj, ai);
+    if (status == TOMO_OK) status = to_device(&p->d_wf, wf);
+    if (status == TOMO_OK) status = to_device(&p->d_wa, wa);
+    if (status == TOMO_OK) status = to_device(&p->d_wr, wr);
+    if (status == TOMO_OK) status = stack_dispatch(p, nullptr, true, items[0].op->n_cu);
+  }
+  if (status != TOMO_OK) {
+    stack_plan_destroy(p);
+    return status;
+  }
+  *out = p;
+  return TOMO_OK;
+}
+
+tomo_status stack_plan_launch(const StackPlan* p, hipStream_t st) {
+  return stack_dispatch(const_cast<StackPlan*>(p), st, false, 0);
 }
 
 }  // namespace tomo

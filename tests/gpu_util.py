@@ -79,3 +79,49 @@ def krylov_tolerance(run, x64, realizations: int = 6, factor: float = 2.0, floor
     ``realizations`` such runs, plus ``floor``."""
     devs = [rel_l2(run(np.random.default_rng(i)), x64) for i in range(realizations)]
     return factor * max(devs) + floor
+
+
+U32 = 2.0 ** -24
+
+
+def summation_bound_check(name, got, S_o, out_map, in_lib, in_inv, l2_tol=1e-5, value_tol=1e-12):
+    """Compare an SpMM output with the oracle's CSR product element by element.
+
+    got: library-ordered (rows, C, 2) float32 product; S_o: oracle CSR (float64 values, or values
+    already rounded to the kernel's 16-bit type); in_lib: the library-ordered (rows_in, C, 2)
+    float32 input, whose oracle-ordered form is in_lib[in_inv]; out_map: library row -> oracle row.
+    An output element summing k products v_e x_e of float32 inputs (a float32 value is the float64
+    one rounded, relative error <= u; 16-bit values convert exactly) with one rounding per product
+    and k - 1 additions in any order satisfies |computed - exact| <= gamma_{k+1} sum_e |v_e||x_e|,
+    gamma_j = j u / (1 - j u), u = 2^-24 (Higham, Accuracy and Stability of Numerical
+    Algorithms, Sec. 3.1 and 4.2), for the real and imaginary parts separately.  The library builds
+    its matrix in float64 on its own: its entries agree with the oracle's to value_tol (exact
+    window ties flip entries of size ~1e-13 between the builds; the host-builder tests hold both
+    CSRs to 1e-12 per entry), which adds at most value_tol (k + 1) max|x| to an element (a row
+    made only of such entries has a summation bound near zero).  Asserts that bound for every
+    element (the binding check) and the relative L2 below l2_tol (default: the operators' parity
+    tolerance, 1e-5; sums that cancel put some fp16 products near 1e-6); returns (rel L2,
+    max|d|/max|ref|, worst error / bound)."""
+    Xo = in_lib[in_inv].astype(np.float64)
+    ref = S_o @ (Xo[..., 0] + 1j * Xo[..., 1])
+    mag = abs(S_o) @ (np.abs(Xo[..., 0]) + 1j * np.abs(Xo[..., 1]))
+    k = np.diff(S_o.indptr)
+    ref, mag, k = ref[out_map], mag[out_map], k[out_map]
+    ku = (k + 1).astype(np.float64) * U32
+    gam = (ku / (1.0 - ku))[:, None]
+    d_re = np.abs(got[..., 0] - ref.real)
+    d_im = np.abs(got[..., 1] - ref.imag)
+    xmax = float(np.max(np.abs(Xo))) if Xo.size else 0.0
+    b_ties = value_tol * (k + 1).astype(np.float64)[:, None] * xmax
+    b_re, b_im = gam * mag.real + b_ties, gam * mag.imag + b_ties
+    ratio = max(float(np.max(d_re / np.maximum(b_re, 1e-300), initial=0.0)),
+                float(np.max(d_im / np.maximum(b_im, 1e-300), initial=0.0)))
+    gc = got[..., 0].astype(np.float64) + 1j * got[..., 1]
+    l2 = rel_l2(gc, ref)
+    mx = float(np.max(np.abs(gc - ref)) / np.max(np.abs(ref)))
+    bad = int(np.count_nonzero(d_re > b_re) + np.count_nonzero(d_im > b_im))
+    print(f"{name}: {got.shape[0]} rows x {got.shape[1]} channels: rel L2 {l2:.2e}, "
+          f"max|d|/max|ref| {mx:.2e}, worst error / summation bound {ratio:.3f}, violations {bad}")
+    assert bad == 0, (name, ratio)
+    assert l2 < l2_tol, (name, l2)
+    return l2, mx, ratio

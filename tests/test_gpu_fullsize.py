@@ -21,14 +21,11 @@ import torch
 
 from oracle import round_values
 from synth import phantom_stack
-from tests.gpu_util import cart_map, oracle_op, polar_row_map, rel_l2
+from tests.gpu_util import cart_map, oracle_op, polar_row_map, rel_l2, summation_bound_check
 
 pytestmark = pytest.mark.gpu
 
 N, NT, NP, B = 2048, 1501, 2048, 32
-U32 = 2.0 ** -24
-
-
 @pytest.fixture(scope="module")
 def big(tomo):
     op = tomo.Operator(N, NT, NP, max_batch=B, values=("f32", "bf16"), device=0)
@@ -59,38 +56,6 @@ def _vals(S, values):
     return S if values == "f32" else round_values(S, values)
 
 
-def _gamma(k):
-    ku = k.astype(np.float64) * U32
-    return ku / (1.0 - ku)
-
-
-def _check_all_rows(name, got, S_o, out_map, in_lib, in_inv):
-    """got: library-ordered (rows, C, 2) float32 product; S_o: oracle CSR (values already in the
-    kernel's value type); the library input in_lib (rows_in, C, 2) float32, whose oracle-ordered
-    form is in_lib[in_inv].  Compares every row with the float32 summation bound."""
-    Xo = in_lib[in_inv].astype(np.float64)
-    ref = S_o @ (Xo[..., 0] + 1j * Xo[..., 1])                    # oracle row order
-    Sabs = abs(S_o)
-    mag = Sabs @ (np.abs(Xo[..., 0]) + 1j * np.abs(Xo[..., 1]))
-    k = np.diff(S_o.indptr)
-    ref, mag, k = ref[out_map], mag[out_map], k[out_map]          # library row order
-    gam = _gamma(k + 1)[:, None]
-    d_re = np.abs(got[..., 0] - ref.real)
-    d_im = np.abs(got[..., 1] - ref.imag)
-    b_re = gam * mag.real
-    b_im = gam * mag.imag
-    ratio = max(float(np.max(d_re / np.maximum(b_re, 1e-300), initial=0.0)),
-                float(np.max(d_im / np.maximum(b_im, 1e-300), initial=0.0)))
-    gc = got[..., 0] + 1j * got[..., 1]
-    l2 = rel_l2(gc, ref)
-    mx = float(np.max(np.abs(gc - ref)) / np.max(np.abs(ref)))
-    bad = int(np.count_nonzero(d_re > b_re) + np.count_nonzero(d_im > b_im))
-    print(f"{name}: {got.shape[0]} rows x {got.shape[1]} channels: rel L2 {l2:.2e}, "
-          f"max|d|/max|ref| {mx:.2e}, worst error / summation bound {ratio:.3f}, violations {bad}")
-    assert bad == 0, (name, ratio)
-    assert l2 < 1e-6 and mx < 1e-6, (name, l2, mx)
-
-
 @pytest.mark.parametrize("values", ["f32", "bf16"])
 def test_fullsize_forward_spmm_every_row(big, ref, maps, values):
     cm, pm, cm_inv, pm_inv = maps
@@ -103,7 +68,7 @@ def test_fullsize_forward_spmm_every_row(big, ref, maps, values):
     Yg = big.slice_fwd(torch.from_numpy(Xc).cuda(), B, values=values)
     torch.cuda.synchronize()
     got = Yg.cpu().numpy()
-    _check_all_rows(f"forward {values}", got, _vals(ref.S_dag, values), pm, Xc, cm_inv)
+    summation_bound_check(f"forward {values}", got, _vals(ref.S_dag, values), pm, Xc, cm_inv, l2_tol=1e-6)
     assert torch.equal(big.slice_fwd(torch.from_numpy(Xc).cuda(), B, values=values), Yg)
 
 
@@ -121,7 +86,7 @@ def test_fullsize_adjoint_spmm_every_row(big, ref, maps, values):
     Xg = big.slice_adj(torch.from_numpy(Yc).cuda(), B, values=values)
     torch.cuda.synchronize()
     got = Xg.cpu().numpy()
-    _check_all_rows(f"adjoint {values}", got, _vals(ref.S, values), cm, Yc, pm_inv)
+    summation_bound_check(f"adjoint {values}", got, _vals(ref.S, values), cm, Yc, pm_inv, l2_tol=1e-6)
     assert torch.equal(big.slice_adj(torch.from_numpy(Yc).cuda(), B, values=values), Xg)
 
 

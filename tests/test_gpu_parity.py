@@ -124,14 +124,26 @@ POW2_SHAPES = [
     (64, 6, 4096, {}),                     # two channels per block
 ]
 
+# other lengths go through Bluestein's identity at the power-of-two length M >= 2N - 1: the
+# 91 / 724 / 1448 / 362 / 2896 grids of the benchmark configurations (M = 256 .. 8192; 8192 holds
+# one row or column per block), a prime, a padded grid and an off-centre axis
+NONPOW2_SHAPES = [
+    (64, 90, 91, {}),
+    (17, 11, 23, {"center": 9.0}),
+    (24, 20, 33, {"grid": 40}),
+    (30, 17, 45, {"kw": 5}),
+    (200, 16, 283, {}),                    # prime length
+]
+CONFIG_LENGTHS = [(256, 24, 362, {}), (512, 36, 724, {}), (1024, 30, 1448, {}), (2048, 12, 2896, {})]
 
-@pytest.mark.parametrize("shape", POW2_SHAPES, ids=_ids)
+
+@pytest.mark.parametrize("shape", POW2_SHAPES + NONPOW2_SHAPES, ids=_ids)
 @pytest.mark.parametrize("fft", [(1, 1), (0, 0), (1, 0), (0, 1)], ids=lambda f: f"det{f[0]}_grid{f[1]}")
 @pytest.mark.parametrize("batch", [1, 5])
 def test_hand_written_transform_paths(tomo, shape, fft, batch):
     """The hand-written transforms (detector rows with crop / pad; Cartesian rows with embed /
-    crop and columns) and the rocFFT paths all give the oracle's operators for power-of-two
-    sizes."""
+    crop and columns) and the rocFFT paths all give the oracle's operators, for power-of-two
+    lengths and, through Bluestein's identity, for others."""
     n, nt, npb, extra = shape
     op = _gpu_op(tomo, n, nt, npb, extra)
     op.set_tuning(det_fft=fft[0], grid_fft=fft[1])
@@ -147,6 +159,81 @@ def test_hand_written_transform_paths(tomo, shape, fft, batch):
         assert rel_l2(yg[s], ref.project(xs)) < TOL, s
         assert rel_l2(xg[s], ref.backproject(ys)) < TOL, s
         assert rel_l2(xf[s], ref.irradon(ys, "ramlak")) < TOL, s
+    op.close()
+
+
+@pytest.mark.parametrize("shape", CONFIG_LENGTHS, ids=_ids)
+def test_hand_written_transforms_at_configuration_lengths(tomo, shape):
+    """The default (hand-written, Bluestein) transforms at the grid / detector lengths of the
+    benchmark configurations (362, 724, 1448, 2896 = 2^k * 181; few angles to keep the oracle
+    cheap): project, backproject and iRadon of two slices (one complex channel) against the
+    oracle, relative L2 and the largest element error against the largest reference element."""
+    n, nt, npb, extra = shape
+    op = _gpu_op(tomo, n, nt, npb, extra, max_batch=2)
+    assert op.get_tuning()["det_fft"] == 1 and op.get_tuning()["grid_fft"] == 1
+    ref = _oracle(n, nt, npb, extra)
+    x = _rand((2, n, n), 710)
+    y = _rand((2, nt, npb), 810)
+    yg = _host(op.project(_dev(x)))
+    xg = _host(op.backproject(_dev(y)))
+    xf = _host(op.irradon(_dev(y), filter="ramlak"))
+    for s in range(2):
+        xs = x[s].astype(np.float32).astype(np.float64)
+        ys = y[s].astype(np.float32).astype(np.float64)
+        for got, want in ((yg[s], ref.project(xs)), (xg[s], ref.backproject(ys)),
+                          (xf[s], ref.irradon(ys, "ramlak"))):
+            l2 = rel_l2(got, want)
+            mx = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+            print(f"{shape[:3]} slice {s}: rel L2 {l2:.2e}, max {mx:.2e}")
+            assert l2 < TOL and mx < TOL, (s, l2, mx)
+    op.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 90, 91, {}), (100, 60, 256, {}), (24, 20, 33, {"grid": 40}),
+                                   (30, 17, 45, {"kw": 5})], ids=_ids)
+@pytest.mark.parametrize("dense", [0, 1, 2])
+@pytest.mark.parametrize("vt", ["f32", "bf16"])
+def test_operators_with_each_adjoint_form(tomo, shape, dense, vt):
+    """The composed operators with the staged SpMMs on the FFT-side (channel-slowest) grid: the
+    forward reads its patches there, and with the dense tiles staged (forms 1 and 2) the adjoint
+    writes its tiles there (form 0 keeps the row kernels and the transpose); project,
+    backproject and the filtered iRadon against the oracle, odd and even batches."""
+    n, nt, npb, extra = shape
+    op = _gpu_op(tomo, n, nt, npb, extra, values=("f32", "bf16"))
+    op.set_tuning(adj_dense_mode=dense, adj_seg_chunks=2, adj_tile_points=64)
+    base = _oracle(n, nt, npb, extra)
+    ref = base if vt == "f32" else OracleOperator(base.geom, S=round_values(base.S, vt))
+    for batch in (3, 4):
+        x = _rand((batch, n, n), 720 + batch)
+        y = _rand((batch, nt, npb), 820 + batch)
+        yg = _host(op.project(_dev(x), values=vt))
+        xg = _host(op.backproject(_dev(y), values=vt))
+        xf = _host(op.irradon(_dev(y), values=vt, filter="hamming"))
+        for s in range(batch):
+            xs = x[s].astype(np.float32).astype(np.float64)
+            ys = y[s].astype(np.float32).astype(np.float64)
+            assert rel_l2(yg[s], ref.project(xs)) < TOL, (batch, s)
+            assert rel_l2(xg[s], ref.backproject(ys)) < TOL, (batch, s)
+            assert rel_l2(xf[s], ref.irradon(ys, "hamming")) < TOL, (batch, s)
+    op.close()
+
+
+def test_odd_channel_count_above_64(tomo):
+    """133 slices (67 complex channels, odd, above the row kernels' 64 lane groups) run through the
+    staged kernels, which split channels over blocks; the row kernels refuse such a batch."""
+    n, nt, npb, B = 16, 12, 23, 133
+    op = tomo.Operator(n, nt, npb, max_batch=B, device=0)
+    ref = oracle_op(n, nt, npb)
+    x = _rand((B, n, n), 740)
+    y = _rand((B, nt, npb), 840)
+    yg = _host(op.project(_dev(x)))
+    xg = _host(op.backproject(_dev(y)))
+    for s in (0, 1, 64, 131, 132):
+        assert rel_l2(yg[s], ref.project(x[s].astype(np.float32).astype(np.float64))) < TOL, s
+        assert rel_l2(xg[s], ref.backproject(y[s].astype(np.float32).astype(np.float64))) < TOL, s
+    op.set_tuning(adj_dense_mode=0)
+    with pytest.raises(tomo.TomoError, match="EUNSUPPORTED"):
+        op.backproject(_dev(y))
     op.close()
 
 
@@ -249,6 +336,15 @@ TUNINGS = [
     dict(ROW, adj_sell_xcd_rows=0, adj_medium_xcd_rows=0),        # one contiguous range per XCD
     dict(ROW, fwd_rows_per_group=2),                              # pipelined forward
     dict(ROW, fwd_rows_per_group=4),
+    # dense tiles staged in chunked segments: one chunk per segment (every dense tile split and
+    # reduced from partial tiles), a few, and one launch for every tile
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, adj_tile_points=32, adj_dense_mode=1, adj_seg_chunks=1),
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, adj_tile_points=64, adj_dense_mode=1, adj_seg_chunks=8),
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, adj_tile_points=128, adj_dense_mode=2, adj_seg_chunks=4),
+    dict(fwd_tiled=7, adj_tiled=7, tile=16, adj_tile_points=256, adj_dense_mode=2, adj_seg_chunks=2),
+    # staged tiles in runs per block (odd and even run lengths: both register sets end a run)
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, adj_tile_points=64, adj_dense_mode=2, adj_seg_chunks=3, adj_run=5),
+    dict(fwd_tiled=7, adj_tiled=7, tile=8, adj_tile_points=128, adj_dense_mode=2, adj_seg_chunks=8, adj_run=8),
 ]
 
 
@@ -288,12 +384,15 @@ def test_slice_spmm_tunings(tomo, tuning, batch):
 
 @pytest.mark.parametrize("shape", SHAPES, ids=_ids)
 @pytest.mark.parametrize("tile", [8, 16])
-def test_staged_kernels_on_every_geometry(tomo, shape, tile):
+@pytest.mark.parametrize("dense", [0, 1, 2])
+def test_staged_kernels_on_every_geometry(tomo, shape, tile, dense):
     """The LDS-staged SpMMs at ragged sizes, padded and off-centre geometries and k_w = 5
-    (windows on the grid's upper edge, tiles past the grid's end)."""
+    (windows on the grid's upper edge, tiles past the grid's end), with the adjoint's dense tiles
+    on the row kernels (0) or staged in segments of two chunks (1: second stream, 2: one launch)."""
     n, nt, npb, extra = shape
     op = _gpu_op(tomo, n, nt, npb, extra, max_batch=6)
-    op.set_tuning(fwd_tiled=7, adj_tiled=7, tile=tile, tile_points=64, adj_tile_points=64)
+    op.set_tuning(fwd_tiled=7, adj_tiled=7, tile=tile, tile_points=64, adj_tile_points=64,
+                  adj_dense_mode=dense, adj_seg_chunks=2, adj_run=3)
     ref = _oracle(n, nt, npb, extra)
     g = ref.geom
     cm, pm = cart_map(g), polar_row_map(g)
@@ -319,17 +418,19 @@ def test_staged_adjoint_on_a_side_stream_matches_the_default_stream(tomo):
     g = oracle_op(n, nt, npb).geom
     C = batch // 2
     Y = _dev(_rand((g.L * nt, C, 2), 950))
-    ref = {vt: op.slice_adj(Y, batch, values=vt).clone() for vt in ("f32", "bf16")}
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        outs = {vt: op.slice_adj(Y, batch, values=vt) for vt in ("f32", "bf16")}
-        again = op.slice_adj(Y, batch, values="bf16")
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    for vt in ("f32", "bf16"):
-        assert torch.equal(outs[vt], ref[vt]), vt
-    assert torch.equal(again, ref["bf16"])
+    for mode in (0, 1, 2):
+        op.set_tuning(adj_dense_mode=mode, adj_seg_chunks=2)
+        ref = {vt: op.slice_adj(Y, batch, values=vt).clone() for vt in ("f32", "bf16")}
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            outs = {vt: op.slice_adj(Y, batch, values=vt) for vt in ("f32", "bf16")}
+            again = op.slice_adj(Y, batch, values="bf16")
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        for vt in ("f32", "bf16"):
+            assert torch.equal(outs[vt], ref[vt]), (mode, vt)
+        assert torch.equal(again, ref["bf16"]), mode
     op.close()
 
 

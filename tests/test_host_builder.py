@@ -107,7 +107,8 @@ def test_tuning_rejects_out_of_range():
     before = op.get_tuning()
     for bad in (dict(fwd_channels_per_lane=3), dict(adj_sell_max=-1), dict(adj_chunk=4),
                 dict(adj_medium_max=10, adj_sell_max=20), dict(adj_sell_sigma=0),
-                dict(tile_strip=-1), dict(tile_strip=4097)):
+                dict(tile_strip=-1), dict(tile_strip=4097), dict(adj_dense_mode=3),
+                dict(adj_seg_chunks=0), dict(adj_seg_chunks=257), dict(adj_run=0), dict(adj_run=257)):
         with pytest.raises(tomo.TomoError):
             op.set_tuning(**bad)
         assert op.get_tuning() == before
@@ -161,11 +162,16 @@ def test_host_only_operator_rejects_apply():
                                     dict(adj_sell_max=4, adj_medium_max=20, adj_chunk=8, adj_sell_sigma=3),
                                     dict(adj_sell_tiles=1, adj_sell_max=24),
                                     dict(tile_strip=0), dict(tile_strip=3, adj_tile_points=64),
-                                    dict(tile=16, tile_strip=5)])
+                                    dict(tile=16, tile_strip=5),
+                                    dict(adj_tile_points=32, adj_dense_mode=1, adj_seg_chunks=1),
+                                    dict(adj_tile_points=64, adj_dense_mode=2, adj_seg_chunks=3),
+                                    dict(adj_tile_points=64, adj_dense_mode=2, adj_seg_chunks=2, adj_run=7),
+                                    dict(tile=16, adj_tile_points=128, adj_dense_mode=1)])
 def test_kernel_layouts_replay_the_csr_products(d, tuning):
     """Every device layout (fixed-stride forward, sliced-ELL / wave / chunked adjoint, LDS-staged
-    window-form tiles, and the row layout of the staged adjoint's dense cells) replayed on the
-    host equals the CSR products."""
+    window-form tiles, the row layout of the staged adjoint's dense cells, or those tiles in
+    chunked segments with split tiles summed from partial tiles) replayed on the host equals the
+    CSR products."""
     op = tomo.Operator(device=-1, max_batch=2, **d)
     op.set_tuning(**tuning)
     err = op.check_layouts()
