@@ -268,9 +268,13 @@ tomo_status tomo_solve(tomo_op* op, const float* b, float* x, int32_t batch,
  * Exact for this discretisation when n_det == grid (L) and the centre is an integer: then
  *   A^T D A x = (1/L) k* . F2D^H W F2D (k* . x),   W = S diag(D) S^dagger,
  * and W is a fixed (2kw-1)^2 stencil of weights per Cartesian frequency (no column indices).
- * filter: tomo_filter, D in the polar domain (TOMO_FILTER_NONE: A^T A).  The first call per
- * filter builds W on the host in float64 and uploads it in every value type the operator holds
- * (synchronous; kept until tomo_destroy_operator).
+ * filter: tomo_filter, D in the polar domain (TOMO_FILTER_NONE: A^T A).  `values` selects the
+ * matrix whose normal operator is applied: with 16-bit values it is A_v^T D A_v for the forward
+ * operator A_v with S's values rounded to that type (the composition of tomo_project and
+ * tomo_backproject with those values), its W = S_v diag(D) S_v^dagger formed in float64 and
+ * stored in float32, which keeps it positive semidefinite.  The first call per filter builds W on
+ * the host in float64 for every value type the operator holds and uploads it (synchronous; kept
+ * until tomo_destroy_operator).
  * x: device [batch][n][n] f32 (read); out: device [batch][n][n] f32 (written), 16-byte aligned.
  * Errors: as tomo_project, plus TOMO_EUNSUPPORTED (n_det != grid, or kw > 5). */
 tomo_status tomo_normal(tomo_op* op, const float* x, float* out, int32_t batch, int32_t values,

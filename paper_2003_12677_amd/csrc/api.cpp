@@ -448,15 +448,31 @@ tomo_status ensure_normal(tomo_op* op, int filter) {
   nrm.stride = (S2 + 7) / 8 * 8;
   std::vector<double> d;
   if (filter != TOMO_FILTER_NONE) filter_diagonal(g, filter, &d);
-  std::vector<double> w;
-  TOMO_TRY(build_normal_values(g, op->s, op->sdag, d.empty() ? nullptr : d.data(), nrm.stride, &w));
-  void* dst[3] = {nullptr, nullptr, nullptr};
-  const tomo_status st = upload_values(w, op->values, dst);
-  if (st != TOMO_OK) {
-    for (auto& v : dst) dfree(v);
-    return st;
+  // one float32 stencil per value type, each the normal operator of the forward operator with
+  // those values: W = S_v D S_v^dagger from the matrix with its values rounded to the type (so
+  // it stays positive semidefinite; rounding W itself to 16 bits does not, and CG on it diverged)
+  for (int vt = 0; vt < 3; ++vt) {
+    if (!(op->values & (1u << vt))) continue;
+    HostCSR sv = op->s, sdv = op->sdag;
+    if (vt != TOMO_VAL_F32)
+      for (HostCSR* m : {&sv, &sdv})
+        for (double& v : m->val) {
+          const float f = (float)v;
+          if (vt == TOMO_VAL_BF16) {
+            const uint32_t b = (uint32_t)f32_to_bf16_rne(f) << 16;
+            float r;
+            std::memcpy(&r, &b, 4);
+            v = r;
+          } else {
+            v = (double)(float)(_Float16)f;
+          }
+        }
+    std::vector<double> w;
+    TOMO_TRY(build_normal_values(g, sv, sdv, d.empty() ? nullptr : d.data(), nrm.stride, &w));
+    void* dst[3] = {nullptr, nullptr, nullptr};
+    TOMO_TRY(upload_values(w, TOMO_VALUES_F32, dst));
+    nrm.val[filter][vt] = dst[TOMO_VAL_F32];
   }
-  for (int vt = 0; vt < 3; ++vt) nrm.val[filter][vt] = dst[vt];
   return TOMO_OK;
 }
 

@@ -265,12 +265,9 @@ tomo_status launch_normal_stencil(const tomo_op* op, const float2* in, float2* o
                                   int filter, hipStream_t st) {
   if (filter < 0 || filter > 3 || vt < 0 || vt > 2 || !op->nrm.val[filter][vt])
     return fail(TOMO_ESTATE, "normal-operator stencil (filter %d, values %d) not built", filter, vt);
-  const void* w = op->nrm.val[filter][vt];
-  switch (vt) {
-    case TOMO_VAL_F32: return normal_impl<float>(op, w, in, out, C, st);
-    case TOMO_VAL_BF16: return normal_impl<bf16_t>(op, w, in, out, C, st);
-    default: return normal_impl<_Float16>(op, w, in, out, C, st);
-  }
+  // every value type's stencil is stored in float32 (the normal operator of the matrix with that
+  // value type; see ensure_normal)
+  return normal_impl<float>(op, op->nrm.val[filter][vt], in, out, C, st);
 }
 
 }  // namespace tomo

@@ -3,9 +3,10 @@ combined with its adjoint without the 1D FFTs) and of the solvers built on it, a
 float64 oracle's definition (the full forward operator followed by its exact adjoint).
 
 Float32 values: <= 1e-5 relative L2 per slice (the same bar as the operators).  bfloat16 /
-float16 stencil values: against the oracle's reduced form with S S^dagger rounded the same
-way (float64 -> float32 -> 16 bit), <= 1e-5.  Solvers: tolerances from repeated oracle solves
-with float32 storage and float32-level operator noise, as for CGLS."""
+float16 values: the normal operator of the forward operator with S's values rounded the same way
+(float64 -> float32 -> 16 bit), i.e. the oracle's project then backproject with the rounded
+matrix, <= 1e-5.  Solvers: tolerances from repeated oracle solves with float32 storage and
+float32-level operator noise, as for CGLS."""
 
 import numpy as np
 import pytest
@@ -51,17 +52,29 @@ def test_normal_matches_oracle(tomo, geom, B, tiled):
 
 @pytest.mark.parametrize("fmt", ["bf16", "f16"])
 def test_normal_low_precision_values(tomo, fmt):
+    """A_v^T A_v for the matrix with 16-bit values: the oracle's project then backproject with the
+    same rounded values (and its factored form with W built from them), and positive
+    semidefinite: x . A_v^T A_v x = |A_v x|^2 >= 0 for random and for high-frequency images."""
+    from oracle import Operator as OracleOperator
+
     n, nt, npb = 64, 90, 91
     op = tomo.Operator(n, nt, npb, max_batch=4, values=("f32", fmt), device=0)
     ref = oracle_op(n, nt, npb)
-    Wr = round_values(interpolation_product(ref), fmt)
+    lo = OracleOperator(ref.geom, S=round_values(ref.S, fmt))
     x = r32(np.random.default_rng(7).uniform(0, 1, (4, n, n)))
     got = _host(op.normal(_dev(x), values=fmt))
     for s in range(4):
-        e = rel_l2(got[s], normal_factored(ref, x[s], Wr))
-        print(f"{fmt} slice {s}: vs rounded-W oracle {e:.2e}; vs exact "
-              f"{rel_l2(got[s], normal(ref, x[s])):.2e}")
-        assert e <= 1e-5
+        e = rel_l2(got[s], normal(lo, x[s]))
+        ef = rel_l2(got[s], normal_factored(lo, x[s], interpolation_product(lo)))
+        print(f"{fmt} slice {s}: vs the rounded matrix's A^T A {e:.2e} (factored {ef:.2e}); vs "
+              f"the float64 operator {rel_l2(got[s], normal(ref, x[s])):.2e}")
+        assert e <= 1e-5 and ef <= 1e-5
+    # high-frequency (checkerboard-modulated) images probe the near-null space
+    i = np.arange(n)
+    hf = r32(np.random.default_rng(8).standard_normal((4, n, n)) * ((-1.0) ** (i[:, None] + i[None, :])))
+    q = _host(op.normal(_dev(hf), values=fmt))
+    for s in range(4):
+        assert float(np.vdot(hf[s], q[s])) >= -1e-6 * np.linalg.norm(hf[s]) * np.linalg.norm(q[s])
     op.close()
 
 
@@ -127,6 +140,34 @@ def test_cgnr_early_iterates_match_cgls_oracle(tomo):
     for s in range(B):
         xr = cgls(ref.project, ref.backproject, r32(b[s]), iters)
         assert rel_l2(xg[s], xr) < 1e-4, s
+    op.close()
+
+
+def test_cgnr_bf16_refinement_matches_cgls_refinement_oracle(tomo):
+    """Refinement with float32 outer residuals and CG on the normal equations of the operator
+    with bfloat16 values as the inner solve: in exact arithmetic the inner iterates equal CGLS's
+    on the same rounded matrix, so before float32 separation (short inner solves) the GPU agrees
+    with the oracle's CGLS refinement tightly, and the misfit decreases from one outer step to
+    the next (the inner normal operator is positive semidefinite)."""
+    from oracle import Operator as OracleOperator, refine
+
+    n, nt, npb, B, R, I = 64, 90, 91, 2, 3, 4
+    hi = oracle_op(n, nt, npb)
+    hi32 = OracleOperator(hi.geom, S=round_values(hi.S, "f32"))
+    lo = OracleOperator(hi.geom, S=round_values(hi.S, "bf16"))
+    b = _sinos(hi, B, 630)
+    op = tomo.Operator(n, nt, npb, max_batch=B, values=("f32", "bf16"), device=0)
+    mis = []
+    for r in range(1, R + 1):
+        xg = _host(op.solve(_dev(b), method="cgnr", iters=I, refine_outer=r, values="bf16"))
+        mis.append([np.linalg.norm(hi.project(xg[s]) - b[s]) for s in range(B)])
+    for s in range(B):
+        xr = refine(hi32.project, lo.project, lo.backproject, r32(b[s]), R, I)
+        err = rel_l2(xg[s], xr)
+        print(f"slice {s}: refinement {R}x{I} (bf16 CGNR inner) vs oracle CGLS refinement {err:.3e}; "
+              f"misfits {[f'{m[s]:.4e}' for m in mis]}")
+        assert err < 1e-4, s
+        assert all(mis[k + 1][s] < mis[k][s] for k in range(R - 1)), s
     op.close()
 
 

@@ -3,9 +3,10 @@ forward kernel and one adjoint kernel walk device work lists covering every (ope
 item.
 
 * Every item's products equal the FP64 oracle's CSR products with the same rounded values (every
-  element within the float32 summation bound), and the item's own staged
-  tomo_slice_fwd / tomo_slice_adj bit for bit (the same sums in the same order), for odd and even batches, f32 / bf16 / f16 values, and several tile
-  runs and segment lengths.
+  element within the float32 summation bound), and the item's own staged tomo_slice_fwd bit for
+  bit, and its tomo_slice_adj too when that runs the same segment body on every tile
+  (adj_dense_mode 2; with 1 the eager staged tiles sum in float32, the stack in float64); odd
+  and even batches, f32 / bf16 / f16 values, several tile runs and segment lengths.
 * At the uneven stack's two smallest shapes (256^2 / 192 / 362 and 512^2 / 384 / 724, fp16, odd
   batches) the stack, eager and captured in a HIP graph, matches the oracle on every replay.
 * Operators whose adjoint keeps its dense tiles on the row kernels, and items that mix kernel
@@ -73,7 +74,8 @@ def test_stack_matches_oracle_and_eager(tomo, vt, tuning):
             op, b = it["op"], it["batch"]
             _check_item(op, it["geom"], b, vt, it["inp"], it["out"], it["aux"])
             assert torch.equal(op.slice_fwd(it["inp"], b, values=vt), it["out"])
-            assert torch.equal(op.slice_adj(it["out"], b, values=vt), it["aux"])
+            if tuning["adj_dense_mode"] == 2:       # eager runs the same segment body on every tile
+                assert torch.equal(op.slice_adj(it["out"], b, values=vt), it["aux"])
     st.close()
     for op in keep:
         op.close()
