@@ -152,12 +152,16 @@ typedef struct {
   int32_t adj_medium_xcd_rows;    /* the same for the one-wavefront-per-row kernel           */
   int32_t fwd_rows_per_group;     /* forward SpMM (3x3 stencil, >= 8 lanes per row): rows one lane
                                      group handles in a software pipeline (1, 2 or 4)           */
-  int32_t det_fft;                /* detector-direction DFTs of project / backproject: 1 = one
-                                     fused kernel (layout + radix-4 DFT in LDS + crop / pad)
-                                     when L is a power of two in [16, 4096]; 0 = rocFFT        */
+  int32_t det_fft;                /* detector-direction DFTs of project / backproject: one fused
+                                     kernel per direction (crop / pad + radix-8 DFT in LDS, other
+                                     lengths through Bluestein's identity) on channel-slowest
+                                     rows.  1 = backproject's kernel writes the adjoint SpMM's
+                                     channel-fastest polar layout itself when the transform length
+                                     is at most 4096 (else as 2); 2 = it writes channel-slowest
+                                     rows, then a tiled transpose; 0 = rocFFT                   */
   int32_t grid_fft;               /* Cartesian 2D DFTs: 1 = hand-written row and column kernels
-                                     fused with the embed / crop steps when the grid side is a
-                                     power of two in [16, 4096]; 0 = rocFFT                    */
+                                     fused with the embed / crop steps (power-of-two sides
+                                     directly, others through Bluestein's identity); 0 = rocFFT */
   int32_t adj_sell_tiles;         /* order of the sliced-ELL rows: 1 = Cartesian cells in 4 x 8
                                      tiles (a block's rows are neighbouring cells, which share
                                      most of their gathered polar rows); 0 = grid order, sorted

@@ -399,18 +399,24 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
-  if (op->tune.det_fft && det_fft_supported(op)) {
-    TOMO_TRY(launch_det_pad_forward(op, y, op->Ys, B, st));
+  if (op->tune.det_fft == 1 && det_cf_supported(op)) {
+    // the fused transform writes the adjoint SpMM's channel-fastest polar layout itself
+    TOMO_TRY(launch_det_pad_forward(op, y, op->Y, B, true, st));
   } else {
-    TOMO_TRY(launch_pad_sino(op, y, op->Ys, B, st));
-    TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
+    if (op->tune.det_fft && det_fft_supported(op)) {
+      TOMO_TRY(launch_det_pad_forward(op, y, op->Ys, B, false, st));
+    } else {
+      TOMO_TRY(launch_pad_sino(op, y, op->Ys, B, st));
+      TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
+    }
+    TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
   }
-  TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
   const float* ds = nullptr;
   if (filter == TOMO_FILTER_DENSITY)
     TOMO_TRY(launch_scale_rows(op->Y, op->dens, (int64_t)g.L * g.nt, C, st));
   else if (filter != TOMO_FILTER_NONE)
     ds = op->filt_dev[filter];
+  const float scale = extra_scale / (float)g.L;
   if (spmm_adj_slowest_ok(op, C, vt)) {
     // the staged adjoint writes its tiles into the FFT-side grid itself
     TOMO_TRY(launch_spmm_adj(op, op->Y, op->Xs, C, vt, ds, st, true));
@@ -419,9 +425,9 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
     TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
   }
   if (op->tune.grid_fft && grid_fft_supported(op))
-    return launch_grid_inverse(op, op->Xs, x, B, extra_scale / (float)g.L, st);
+    return launch_grid_inverse(op, op->Xs, x, B, scale, st);
   TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
-  TOMO_TRY(launch_crop_image(op, op->Xs, x, B, extra_scale / (float)g.L, st));
+  TOMO_TRY(launch_crop_image(op, op->Xs, x, B, scale, st));
   return TOMO_OK;
 }
 

@@ -240,7 +240,7 @@ tomo_status check_tuning(const Tuning& t) {
   if (t.sell_xcd_rows < 0 || t.sell_xcd_rows > (1 << 24) || t.medium_xcd_rows < 0 ||
       t.medium_xcd_rows > (1 << 24))
     return fail(TOMO_EINVAL, "XCD interleave rows must be in [0, 2^24]");
-  if (t.det_fft != 0 && t.det_fft != 1) return fail(TOMO_EINVAL, "det_fft must be 0 or 1");
+  if (t.det_fft < 0 || t.det_fft > 2) return fail(TOMO_EINVAL, "det_fft must be 0, 1 or 2");
   if (t.grid_fft != 0 && t.grid_fft != 1) return fail(TOMO_EINVAL, "grid_fft must be 0 or 1");
   if (t.sell_tiles != 0 && t.sell_tiles != 1) return fail(TOMO_EINVAL, "adj_sell_tiles must be 0 or 1");
   if (t.tile_strip < 0 || t.tile_strip > 4096) return fail(TOMO_EINVAL, "tile_strip must be in [0, 4096]");

@@ -2,22 +2,28 @@
 // power-of-two number L of polar samples per angle (16..4096), or any other L up to 4096 through
 // Bluestein's identity at the power-of-two length M >= 2L - 1 (fft_lds.h):
 //
-//   project tail:     Ys[C][nt][L] (the polar data after the tiled transpose from the forward
-//                     SpMM's channel-fastest output) -> inverse DFT of each row -> rotation-axis
+//   project tail:     Ys[C][nt][L] (written by the staged forward SpMM itself, or a tiled
+//                     transpose of its channel-fastest output) -> inverse DFT of each row -> rotation-axis
 //                     shift, 1/L, crop to n_p bins, real / imaginary parts to slices 2c / 2c+1
 //                     of y[B][nt][np];
 //   adjoint front:    y[B][nt][np] -> pad to L with the axis shift, slices paired into complex
-//                     channels -> forward DFT of each row -> Ys[C][nt][L] (then transposed for
-//                     the adjoint SpMM).
+//                     channels -> forward DFT of each row -> Yf[L][nt][C], the adjoint SpMM's
+//                     channel-fastest input (transform lengths up to 4096), or Ys[C][nt][L]
+//                     followed by a tiled transpose.
 //
-// One block per (channel, AG consecutive angles), a contiguous stretch of Ys: the rows are
+// The project tail and the Ys form of the adjoint front take one block per (channel, AG
+// consecutive angles), a contiguous stretch of Ys.  The Yf form takes one block per (angle, CW
+// channels) and writes each transformed sample's CW channels as one run; the blocks of one angle
+// run side by side on one XCD, so their runs meet in its L2 as whole cache lines.  The rows are
 // transformed in LDS with radix-8 Stockham passes (plus one radix-4 or radix-2 pass for the
 // remaining factor; each pass reads every butterfly's inputs into registers, synchronises, then
 // writes its outputs, so one buffer suffices; the twiddle powers of a butterfly are formed by
 // multiplication from one table entry).  This replaces a library FFT and a crop / pad kernel by one
-// pass over the data.  (Gathering straight from the channel-fastest SpMM layout instead reads
-// only 4 channels' 32 bytes of each 128-byte row per block and was slower than a separate
-// transpose.)  Twiddles exp(-2 pi i j / L), j < L, come from a table computed in double.
+// pass over the data.  Writing the channel-fastest layout in 64-byte runs pays (at 2048 bins x
+// 1501 angles x 16 channels: 246 us against 138 + 154 us for the row kernel and the transpose);
+// reading it in such runs does not (an 8-channel project tail took 302 us against 141 + 153 us),
+// so the project tail keeps channel-slowest rows.  Twiddles exp(-2 pi i j / L), j < L, come
+// from a table computed in double.
 
 #include <hip/hip_runtime.h>
 
@@ -114,17 +120,71 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
   for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[lds((i / L) * M + i % L)];
 }
 
+// Channels per block of the Yf form: 8 (64-byte runs) while their rows fit 128 KB of LDS.
+template <int M>
+constexpr int det_cw() { return M >= 16384 ? 1 : (16384 / M > 8 ? 8 : 16384 / M); }
+
+// y[B][nt][np] -> pad with the axis shift, slices paired -> forward DFT of each row ->
+// Yf[L][nt][C] (polar row k * nt + a, channel fastest).  One block per (angle a, channels
+// c0 .. c0 + CW - 1), XCD-remapped so that the channel groups of one angle are neighbours.
+template <int M, int CW, bool BL>
+__global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* __restrict__ y,
+                                                            float2* __restrict__ Yf, DftTables t,
+                                                            int B, int nt, int np, int cdet) {
+  constexpr int PAD = row_skew<M>();
+  __shared__ float2 buf[lds_rows_size<CW, M, PAD>()];
+  const int L = BL ? t.N : M;
+  const int C = (B + 1) / 2;
+  const int cgroups = (C + CW - 1) / CW;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int a = (int)(blk / cgroups), c0 = (int)(blk % cgroups) * CW;
+  const int nc = min(CW, C - c0);
+  const int64_t plane = (int64_t)nt * np;
+  constexpr int NE = (CW * M + kFB - 1) / kFB;   // loads per thread, issued as one batch
+  float2 v[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int i = threadIdx.x + u * kFB;
+    const int q = i / M, m = i % M;
+    int b = m + cdet;                                 // radial index m holds bin (m + c) mod L
+    b -= (b >= L) ? L : 0;
+    v[u] = make_float2(0.f, 0.f);
+    if (i < CW * M && q < nc && m < L && b < np) {
+      const int c = c0 + q;
+      const int64_t off = (int64_t)a * np + b;
+      v[u].x = y[(int64_t)(2 * c) * plane + off];
+      if (2 * c + 1 < B) v[u].y = y[(int64_t)(2 * c + 1) * plane + off];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int i = threadIdx.x + u * kFB;
+    if (i < CW * M) buf[ldsr<M, PAD>(i / M, i % M)] = v[u];
+  }
+  __syncthreads();
+  dft_lds<M, CW, false, BL, PAD>(buf, t);
+  for (int i = threadIdx.x; i < L * nc; i += kFB) {
+    const int k = i / nc, q = i % nc;
+    Yf[((int64_t)k * nt + a) * C + c0 + q] = buf[ldsr<M, PAD>(q, k)];
+  }
+}
+
 template <int M, bool BL>
-tomo_status det_launch(bool inverse, const tomo_op* op, const float2* Ysin, float2* Ysout,
+tomo_status det_launch(bool inverse, bool fastest, const tomo_op* op, const float2* Ysin, float2* Ysout,
                        const float* yin, float* yout, int B, float scale, hipStream_t st) {
   // about 32 KB of LDS per block, so that four blocks share a CU
   constexpr int AG = M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   const dim3 grid((unsigned)(C * ((g.nt + AG - 1) / AG)));
+  constexpr int CW = det_cw<M>();
+  const dim3 cfgrid((unsigned)(g.nt * ((C + CW - 1) / CW)));
   if (inverse)
     hipLaunchKernelGGL((k_det_inverse_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Ysin, yout, op->dft1,
                        B, g.nt, g.np, g.cdet, scale);
+  else if (fastest)
+    hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL>), cfgrid, dim3(kFB), 0, st, yin, Ysout,
+                       op->dft1, B, g.nt, g.np, g.cdet);
   else
     hipLaunchKernelGGL((k_det_pad_forward<M, AG, BL>), grid, dim3(kFB), 0, st, yin, Ysout, op->dft1,
                        B, g.nt, g.np, g.cdet);
@@ -132,13 +192,14 @@ tomo_status det_launch(bool inverse, const tomo_op* op, const float2* Ysin, floa
   return TOMO_OK;
 }
 
-tomo_status det_dispatch(bool inverse, const tomo_op* op, const float2* Yin, float2* Yout,
-                         const float* yin, float* yout, int B, float scale, hipStream_t st) {
+tomo_status det_dispatch(bool inverse, bool fastest, const tomo_op* op, const float2* Yin,
+                         float2* Yout, const float* yin, float* yout, int B, float scale,
+                         hipStream_t st) {
   const bool bl = op->dft1.M != op->g.L;
 #define TOMO_DET(M_)                                                                             \
   case M_:                                                                                      \
-    return bl ? det_launch<M_, true>(inverse, op, Yin, Yout, yin, yout, B, scale, st)           \
-              : det_launch<M_, false>(inverse, op, Yin, Yout, yin, yout, B, scale, st);
+    return bl ? det_launch<M_, true>(inverse, fastest, op, Yin, Yout, yin, yout, B, scale, st)  \
+              : det_launch<M_, false>(inverse, fastest, op, Yin, Yout, yin, yout, B, scale, st);
   switch (op->dft1.M) {
     TOMO_DET(16) TOMO_DET(32) TOMO_DET(64) TOMO_DET(128) TOMO_DET(256) TOMO_DET(512) TOMO_DET(1024)
     TOMO_DET(2048) TOMO_DET(4096) TOMO_DET(8192)
@@ -151,14 +212,16 @@ tomo_status det_dispatch(bool inverse, const tomo_op* op, const float2* Yin, flo
 
 bool det_fft_supported(const tomo_op* op) { return op->dft1.tw != nullptr; }
 
+bool det_cf_supported(const tomo_op* op) { return det_fft_supported(op) && op->dft1.M <= 4096; }
+
 tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Ys, float* y, int B,
                                     float scale, hipStream_t st) {
-  return det_dispatch(true, op, Ys, nullptr, nullptr, y, B, scale, st);
+  return det_dispatch(true, false, op, Ys, nullptr, nullptr, y, B, scale, st);
 }
 
-tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Ys, int B,
-                                   hipStream_t st) {
-  return det_dispatch(false, op, nullptr, Ys, y, nullptr, B, 1.0f, st);
+tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
+                                   bool channel_fastest, hipStream_t st) {
+  return det_dispatch(false, channel_fastest, op, nullptr, Y, y, nullptr, B, 1.0f, st);
 }
 
 }  // namespace tomo

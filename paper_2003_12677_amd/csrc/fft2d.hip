@@ -26,12 +26,6 @@ namespace {
 
 using namespace fftk;
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  const int64_t x = bid & 7, local = bid >> 3;
-  const int64_t q = nblocks >> 3, r = nblocks & 7;
-  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
 // rows per row block: about 32 KB of LDS, so that four blocks share a CU (M = the transform length
 // held in LDS: G itself, or the Bluestein length for other G)
 template <int M>

@@ -8,16 +8,43 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace tomo {
 namespace fftk {
 
 constexpr int kFB = 512;   // threads per block of every kernel that uses these passes
+
+}  // namespace fftk
+
+// Blocks are dispatched round robin over the 8 XCDs (block b to XCD b mod 8).  The remapped index
+// of hardware block `bid` makes each XCD walk one contiguous range of logical blocks, so that
+// neighbouring logical blocks (which share cache lines or gathered inputs) share one L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  const int64_t x = bid & 7, local = bid >> 3;
+  const int64_t q = nblocks >> 3, r = nblocks & 7;
+  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+namespace fftk {
 
 // LDS index of element i: one padding element after every 32 (256 bytes, one row of banks), so
 // the stride-R writes of the early passes spread over the banks instead of colliding.
 __device__ __forceinline__ int lds(int i) { return i + (i >> 5); }
 template <int N>
 constexpr int lds_size() { return N + N / 32 + 1; }
+// Rows of length L back to back, row ch shifted by ch * PAD further elements: PAD = 8 places the
+// same element of 8 consecutive rows in 8 different bank pairs, for reads across rows.  PAD = 0 is
+// the plain layout lds(ch * L + j).
+template <int L, int PAD>
+__device__ __forceinline__ int ldsr(int ch, int j) { return lds(ch * L + j) + ch * PAD; }
+template <int CH, int L, int PAD>
+constexpr int lds_rows_size() { return lds_size<CH * L>() + CH * PAD; }
+// The skew that makes the stride of length-M rows 8 (mod 32) elements: element k of 8
+// consecutive rows then lies in 8 different bank pairs, and a wave reading 8 rows x 8
+// consecutive k (the transposing loads and stores) is free of bank conflicts.
+template <int M>
+constexpr int row_skew() { return M >= 32 ? (8 - (M + M / 32) % 32 + 32) % 32 : 0; }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -70,7 +97,7 @@ __device__ __forceinline__ void dft2(float2 (&v)[2]) {
 
 // One Stockham pass of radix R on CH transforms of length L stored back to back in `buf`,
 // after which sub-transforms of length Ns*R are complete (Ns = 1 << logNs).
-template <int L, int CH, int R, bool INV>
+template <int L, int CH, int R, bool INV, int PAD = 0>
 __device__ __forceinline__ void stockham_pass(float2* buf, int logNs, const float2* __restrict__ tw) {
   constexpr int NJ = L / R;
   constexpr int TOTAL = CH * NJ;
@@ -84,14 +111,13 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int logNs, const floa
     if (w < TOTAL) {
       const int ch = w / NJ, j = w % NJ;
       const int k = j & (Ns - 1);
-      const int src = ch * L + j;
       // w = exp(-/+ 2 pi i k / (R Ns)) from the table, its powers by multiplication
       float2 w = tw[k * tstep];
       if (INV) w.y = -w.y;
       float2 wr = w;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 a = buf[lds(src + r * NJ)];
+        float2 a = buf[ldsr<L, PAD>(ch, j + r * NJ)];
         if (r > 0) {
           a = cmul(a, wr);
           wr = cmul(wr, w);
@@ -110,24 +136,23 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int logNs, const floa
     if (w < TOTAL) {
       const int ch = w / NJ, j = w % NJ;
       const int idx = ((j >> logNs) << logNs) * R + (j & (Ns - 1));
-      const int dst = ch * L + idx;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds(dst + r * Ns)] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[ldsr<L, PAD>(ch, idx + r * Ns)] = v[it][r];
     }
   }
   __syncthreads();
 }
 
 // radix-8 passes, then one radix-4 or radix-2 pass for the remaining factor
-template <int L, int CH, bool INV>
+template <int L, int CH, bool INV, int PAD = 0>
 __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw) {
   int logNs = 0;
   while ((8 << logNs) <= L) {
-    stockham_pass<L, CH, 8, INV>(buf, logNs, tw);
+    stockham_pass<L, CH, 8, INV, PAD>(buf, logNs, tw);
     logNs += 3;
   }
-  if ((4 << logNs) <= L) stockham_pass<L, CH, 4, INV>(buf, logNs, tw);
-  else if ((2 << logNs) <= L) stockham_pass<L, CH, 2, INV>(buf, logNs, tw);
+  if ((4 << logNs) <= L) stockham_pass<L, CH, 4, INV, PAD>(buf, logNs, tw);
+  else if ((2 << logNs) <= L) stockham_pass<L, CH, 2, INV, PAD>(buf, logNs, tw);
 }
 
 // Length-N DFTs (N not a power of two) of CH vectors held in LDS with row stride M, a power of two
@@ -139,29 +164,32 @@ __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ 
 // transforms.  Tables (from double precision on the host): chirp[n] = conj(w_n), n < N; bhat = the
 // length-M DFT of the kernel w (forward) or conj(w) (inverse) wrapped to negative indices, times
 // 1/M; tw = the length-M twiddles.  Elements N .. M-1 hold garbage on exit.
-template <int M, int CH, bool INV>
+template <int M, int CH, bool INV, int PAD = 0>
 __device__ __forceinline__ void bluestein_lds(float2* buf, const float2* __restrict__ tw, int N,
                                               const float2* __restrict__ chirp,
                                               const float2* __restrict__ bhat) {
   for (int i = threadIdx.x; i < CH * M; i += kFB) {
-    const int m = i % M;
+    const int m = i % M, e = ldsr<M, PAD>(i / M, m);
     if (m < N) {
       float2 c = chirp[m];
       if (INV) c.y = -c.y;
-      buf[lds(i)] = cmul(buf[lds(i)], c);
+      buf[e] = cmul(buf[e], c);
     }
   }
   __syncthreads();
-  fft_lds<M, CH, false>(buf, tw);
-  for (int i = threadIdx.x; i < CH * M; i += kFB) buf[lds(i)] = cmul(buf[lds(i)], bhat[i % M]);
-  __syncthreads();
-  fft_lds<M, CH, true>(buf, tw);
+  fft_lds<M, CH, false, PAD>(buf, tw);
   for (int i = threadIdx.x; i < CH * M; i += kFB) {
-    const int m = i % M;
+    const int e = ldsr<M, PAD>(i / M, i % M);
+    buf[e] = cmul(buf[e], bhat[i % M]);
+  }
+  __syncthreads();
+  fft_lds<M, CH, true, PAD>(buf, tw);
+  for (int i = threadIdx.x; i < CH * M; i += kFB) {
+    const int m = i % M, e = ldsr<M, PAD>(i / M, m);
     if (m < N) {
       float2 c = chirp[m];
       if (INV) c.y = -c.y;
-      buf[lds(i)] = cmul(buf[lds(i)], c);
+      buf[e] = cmul(buf[e], c);
     }
   }
   __syncthreads();
@@ -177,13 +205,14 @@ struct DftTables {
   const float2* bhat_i = nullptr;
 };
 
-// The length-N DFT (forward or inverse, unnormalised) of CH vectors in LDS with row stride M.
-template <int M, int CH, bool INV, bool BL>
+// The length-N DFT (forward or inverse, unnormalised) of CH vectors in LDS with row stride M
+// (element j of row ch at ldsr<M, PAD>(ch, j)).
+template <int M, int CH, bool INV, bool BL, int PAD = 0>
 __device__ __forceinline__ void dft_lds(float2* buf, const DftTables& t) {
   if constexpr (BL)
-    bluestein_lds<M, CH, INV>(buf, t.tw, t.N, t.chirp, INV ? t.bhat_i : t.bhat_f);
+    bluestein_lds<M, CH, INV, PAD>(buf, t.tw, t.N, t.chirp, INV ? t.bhat_i : t.bhat_f);
   else
-    fft_lds<M, CH, INV>(buf, t.tw);
+    fft_lds<M, CH, INV, PAD>(buf, t.tw);
 }
 
 }  // namespace fftk

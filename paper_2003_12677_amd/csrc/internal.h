@@ -73,8 +73,10 @@ struct Tuning {
   int sell_xcd_rows = 8192;   // sliced-ELL adjoint: rows per XCD interleave run (0 = contiguous)
   int medium_xcd_rows = 1024; // wave-per-row adjoint: rows per XCD interleave run
   int fwd_rows_per_group = 2; // forward: rows per lane group in the pipelined kernel (1, 2, 4)
-  int det_fft = 1;            // detector transforms: fused hand-written (1, L = 2^m) or library (0)
-  int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1, G = 2^m) or library (0)
+  int det_fft = 1;            // detector transforms: hand-written, the adjoint front writing the
+                              // SpMM's layout where the length allows (1) or channel-slowest
+                              // rows (2); library (0)
+  int grid_fft = 1;           // Cartesian 2D transforms: fused hand-written (1) or library (0)
   int sell_tiles = 1;         // sliced-ELL rows in 4 x 8 Cartesian tiles (1) or grid order (0)
   int tile_strip = 32;        // staged kernels visit tiles in strips this many tiles wide (0 = rows)
   // the staged adjoint's dense tiles (regions holding more than adj_tile_points samples):
@@ -389,13 +391,17 @@ void free_tv(tomo_op* op);
 
 // Normal operator on the channel-slowest Cartesian grid: Out[c][j] = sum over the stencil of
 // W[j][o] In[c][j + offset(o)] (offsets wrap mod G), W for `filter` in value type vt.
-// Detector transforms fused with the layout steps (L a power of two in [16, 4096]).
+// Detector transforms fused with the layout steps (any L with a DFT table: power-of-two lengths
+// directly, others through Bluestein's identity).  The inverse reads Ys[C][nt][L]; the forward
+// writes Ys or, for the adjoint SpMM, Yf[L][nt][C] (channel fastest; det_cf_supported:
+// transform length up to 4096).
 bool det_fft_supported(const tomo_op* op);
-tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Y, float* y, int B,
+bool det_cf_supported(const tomo_op* op);
+tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Ys, float* y, int B,
                                     float scale, hipStream_t st);
 tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
-                                   hipStream_t st);
-// Cartesian 2D DFT fused with embed (forward) and crop (inverse), G a power of two in [16, 4096]:
+                                   bool channel_fastest, hipStream_t st);
+// Cartesian 2D DFT fused with embed (forward) and crop (inverse), any G with a DFT table:
 // forward x -> Xs (channel-slowest), inverse Xs (overwritten) -> x.
 bool grid_fft_supported(const tomo_op* op);
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,

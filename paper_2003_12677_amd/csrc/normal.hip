@@ -22,12 +22,6 @@ constexpr int kNormBlock = 256;
 
 struct bf16_t { uint16_t bits; };
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  const int64_t x = bid & 7, local = bid >> 3;
-  const int64_t q = nblocks >> 3, r = nblocks & 7;
-  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
 template <int S2>
 __device__ __forceinline__ void load_weights(const float* row, float (&wt)[S2]) {
 #pragma unroll

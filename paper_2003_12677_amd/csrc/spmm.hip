@@ -33,14 +33,6 @@ constexpr int kRound = 8;   // entries per round in the adjoint paths
 
 struct bf16_t { uint16_t bits; };
 
-// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD walks a contiguous
-// range of rows and neighbouring rows (which share gathered columns) share one L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  const int64_t x = bid & 7, local = bid >> 3;
-  const int64_t q = nblocks >> 3, r = nblocks & 7;
-  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
 // Blocks interleaved over the XCDs in runs of `chunk`: XCD x takes runs x, x+8, x+16, ... of
 // `chunk` consecutive logical blocks, so neighbouring rows still share an L2 while every XCD
 // gets a share of each part of the row range (the adjoint's row lengths vary with radius).

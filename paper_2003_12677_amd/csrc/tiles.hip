@@ -55,12 +55,6 @@ __device__ __forceinline__ float cvt(const _Float16*, uint32_t r) {
   return (float)__builtin_bit_cast(_Float16, h);
 }
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  const int64_t x = bid & 7, local = bid >> 3;
-  const int64_t q = nblocks >> 3, r = nblocks & 7;
-  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
 template <int CPL>
 struct Vec {
   float v[2 * CPL];

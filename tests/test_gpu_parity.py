@@ -138,14 +138,19 @@ CONFIG_LENGTHS = [(256, 24, 362, {}), (512, 36, 724, {}), (1024, 30, 1448, {}), 
 
 
 @pytest.mark.parametrize("shape", POW2_SHAPES + NONPOW2_SHAPES, ids=_ids)
-@pytest.mark.parametrize("fft", [(1, 1), (0, 0), (1, 0), (0, 1)], ids=lambda f: f"det{f[0]}_grid{f[1]}")
-@pytest.mark.parametrize("batch", [1, 5])
+@pytest.mark.parametrize("fft", [(1, 1), (2, 1), (0, 0), (1, 0), (2, 0), (0, 1)],
+                         ids=lambda f: f"det{f[0]}_grid{f[1]}")
+@pytest.mark.parametrize("batch", [1, 5, 19])
 def test_hand_written_transform_paths(tomo, shape, fft, batch):
-    """The hand-written transforms (detector rows with crop / pad; Cartesian rows with embed /
-    crop and columns) and the rocFFT paths all give the oracle's operators, for power-of-two
-    lengths and, through Bluestein's identity, for others."""
+    """The hand-written transforms (detector rows with crop / pad, the adjoint front writing the
+    SpMM's channel-fastest polar layout (1) or channel-slowest rows (2); Cartesian rows with
+    embed / crop and columns) and the rocFFT paths (0) all give the oracle's operators, for
+    power-of-two lengths and, through Bluestein's identity, for others; batch 19 (10 channels)
+    leaves a ragged channel group of the 8-channel adjoint front."""
     n, nt, npb, extra = shape
-    op = _gpu_op(tomo, n, nt, npb, extra)
+    if batch > 8 and max(n, npb) > 512:
+        pytest.skip("the ragged channel group is covered on the smaller shapes")
+    op = _gpu_op(tomo, n, nt, npb, extra, max_batch=max(batch, 8))
     op.set_tuning(det_fft=fft[0], grid_fft=fft[1])
     ref = _oracle(n, nt, npb, extra)
     x = _rand((batch, n, n), 700 + batch)
@@ -153,7 +158,8 @@ def test_hand_written_transform_paths(tomo, shape, fft, batch):
     yg = _host(op.project(_dev(x)))
     xg = _host(op.backproject(_dev(y)))
     xf = _host(op.irradon(_dev(y), filter="ramlak"))
-    for s in range(batch):
+    # batch 19: the first group's edges and the ragged group (channels 8 and 9; slice 18 alone)
+    for s in (range(batch) if batch <= 8 else (0, 7, 15, 16, 17, 18)):
         xs = x[s].astype(np.float32).astype(np.float64)
         ys = y[s].astype(np.float32).astype(np.float64)
         assert rel_l2(yg[s], ref.project(xs)) < TOL, s

@@ -108,7 +108,8 @@ def test_tuning_rejects_out_of_range():
     for bad in (dict(fwd_channels_per_lane=3), dict(adj_sell_max=-1), dict(adj_chunk=4),
                 dict(adj_medium_max=10, adj_sell_max=20), dict(adj_sell_sigma=0),
                 dict(tile_strip=-1), dict(tile_strip=4097), dict(adj_dense_mode=3),
-                dict(adj_seg_chunks=0), dict(adj_seg_chunks=257), dict(adj_run=0), dict(adj_run=257)):
+                dict(adj_seg_chunks=0), dict(adj_seg_chunks=257), dict(adj_run=0), dict(adj_run=257),
+                dict(det_fft=3), dict(det_fft=-1), dict(grid_fft=2), dict(grid_fft=-1)):
         with pytest.raises(tomo.TomoError):
             op.set_tuning(**bad)
         assert op.get_tuning() == before
