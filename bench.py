@@ -28,7 +28,7 @@ N_IMG, N_ANG, N_DET, BATCH = 2048, 1501, 2048, 32
 WORKLOAD = "parallel-beam 2048x2048, 1501 angles in [0,pi), 2048 bins, batch 32 slices"
 COUNTERS = os.path.join(ROOT, "profiles", "spmm_2048_1501_b32_counters.json")
 SPMM_SOURCES = [os.path.join(ROOT, "paper_2003_12677_amd", "csrc", f)
-                for f in ("spmm.hip", "tiles.hip", "builder.cpp")]
+                for f in ("spmm.hip", "tiles.hip", "builder.cpp", "internal.h", "fft_lds.h")]
 
 
 def parse():
