@@ -364,8 +364,19 @@ tomo_status check_apply(const tomo_op* op, const void* in, const void* out, int3
 }
 
 
+int64_t project_sumsq_blocks(const tomo_op* op) {
+  return op->tune.det_fft ? det_inverse_blocks_per_channel(op) : 0;
+}
+
+int64_t backproject_sumsq_blocks(const tomo_op* op) {
+  return op->tune.grid_fft ? grid_inverse_blocks_per_channel(op) : 0;
+}
+
 // project: embed + deapodise -> F2D -> S^dagger -> F1D^-1 -> crop (Eq. (2), first line)
-tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st) {
+tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st,
+                          double* sumsq) {
+  if (sumsq && project_sumsq_blocks(op) == 0)
+    return fail(TOMO_EINVAL, "internal: output norms need the hand-written detector transform");
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
@@ -386,7 +397,7 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
     TOMO_TRY(launch_polar_to_slowest(op->Y, op->Ys, g.L, g.nt, C, st));
   }
   if (op->tune.det_fft && det_fft_supported(op))
-    return launch_det_inverse_crop(op, op->Ys, y, B, 1.0f / (float)g.L, st);
+    return launch_det_inverse_crop(op, op->Ys, y, B, 1.0f / (float)g.L, sumsq, st);
   TOMO_TRY(fft_exec(p->inv1, p, op->Ys, st));
   TOMO_TRY(launch_crop_sino(op, op->Ys, y, B, 1.0f / (float)g.L, st));
   return TOMO_OK;
@@ -394,7 +405,9 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
 
 // backproject: pad -> F1D -> S diag(D) -> F2D^H -> crop + deapodise (Eq. (2), second line)
 tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
-                              float extra_scale, hipStream_t st) {
+                              float extra_scale, hipStream_t st, double* sumsq) {
+  if (sumsq && backproject_sumsq_blocks(op) == 0)
+    return fail(TOMO_EINVAL, "internal: output norms need the hand-written grid transform");
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   FFTPlans* p = nullptr;
@@ -425,7 +438,7 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
     TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
   }
   if (op->tune.grid_fft && grid_fft_supported(op))
-    return launch_grid_inverse(op, op->Xs, x, B, scale, st);
+    return launch_grid_inverse(op, op->Xs, x, B, scale, sumsq, st);
   TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
   TOMO_TRY(launch_crop_image(op, op->Xs, x, B, scale, st));
   return TOMO_OK;
@@ -498,7 +511,7 @@ tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt,
     TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
   }
   TOMO_TRY(launch_normal_stencil(op, op->Xs, op->X, C, vt, filter, st));
-  if (hand) return launch_grid_inverse(op, op->X, out, B, 1.0f / (float)g.L, st);
+  if (hand) return launch_grid_inverse(op, op->X, out, B, 1.0f / (float)g.L, nullptr, st);
   TOMO_TRY(fft_exec(p->inv2, p, op->X, st));
   TOMO_TRY(launch_crop_image(op, op->X, out, B, 1.0f / (float)g.L, st));
   return TOMO_OK;

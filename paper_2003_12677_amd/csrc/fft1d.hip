@@ -39,10 +39,13 @@ using namespace fftk;
 // axis shift, scale, crop, slices 2c / 2c+1.  One block per (channel, AG consecutive angles):
 // its rows are one contiguous stretch of memory.  L = t.N: M for power-of-two L (BL = false),
 // else the DFTs go through Bluestein's identity at length M; LDS rows have stride M.
+// With sumsq set, the block also sums the squares of the values it writes (float64), per slice:
+// sumsq[s * agroups + j] for its group j of angles.
 template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restrict__ Ys,
                                                           float* __restrict__ y, DftTables t,
-                                                          int B, int nt, int np, int cdet, float scale) {
+                                                          int B, int nt, int np, int cdet, float scale,
+                                                          double* __restrict__ sumsq) {
   __shared__ float2 buf[lds_size<AG * M>()];
   const int L = BL ? t.N : M;
   const int agroups = (nt + AG - 1) / AG;
@@ -69,14 +72,26 @@ __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restri
   dft_lds<M, AG, true, BL>(buf, t);
   const int64_t plane = (int64_t)nt * np;
   const bool odd = 2 * c + 1 < B;
+  double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < na * np; i += kFB) {
     const int q = i / np, b = i % np;
     int m = b - cdet;                                 // bin b reads radial index (b - c) mod L
     m += (m < 0) ? L : 0;
     const float2 v = buf[lds(q * M + m)];
     const int64_t off = (int64_t)(a0 + q) * np + b;
-    y[(int64_t)(2 * c) * plane + off] = v.x * scale;
-    if (odd) y[(int64_t)(2 * c + 1) * plane + off] = v.y * scale;
+    const float re = v.x * scale, im = v.y * scale;
+    y[(int64_t)(2 * c) * plane + off] = re;
+    if (odd) y[(int64_t)(2 * c + 1) * plane + off] = im;
+    s0 += (double)re * (double)re;
+    s1 += (double)im * (double)im;
+  }
+  if (sumsq) {
+    block_sum2(s0, s1);
+    if (threadIdx.x == 0) {
+      const int j = blockIdx.x % agroups;
+      sumsq[(int64_t)(2 * c) * agroups + j] = s0;
+      if (odd) sumsq[(int64_t)(2 * c + 1) * agroups + j] = s1;
+    }
   }
 }
 
@@ -118,6 +133,12 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
   dft_lds<M, AG, false, BL>(buf, t);
   float2* dst = Ys + ((int64_t)c * nt + a0) * L;
   for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[lds((i / L) * M + i % L)];
+}
+
+// Rows (angles) per block of the channel-slowest kernels: about 32 KB of LDS, so that four blocks
+// share a CU.
+constexpr int det_rows_per_block(int M) {
+  return M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
 }
 
 // Channels per block of the Yf form: 8 (64-byte runs) while their rows fit 128 KB of LDS.
@@ -171,9 +192,9 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* __restr
 
 template <int M, bool BL>
 tomo_status det_launch(bool inverse, bool fastest, const tomo_op* op, const float2* Ysin, float2* Ysout,
-                       const float* yin, float* yout, int B, float scale, hipStream_t st) {
-  // about 32 KB of LDS per block, so that four blocks share a CU
-  constexpr int AG = M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
+                       const float* yin, float* yout, int B, float scale, double* sumsq,
+                       hipStream_t st) {
+  constexpr int AG = det_rows_per_block(M);
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   const dim3 grid((unsigned)(C * ((g.nt + AG - 1) / AG)));
@@ -181,7 +202,7 @@ tomo_status det_launch(bool inverse, bool fastest, const tomo_op* op, const floa
   const dim3 cfgrid((unsigned)(g.nt * ((C + CW - 1) / CW)));
   if (inverse)
     hipLaunchKernelGGL((k_det_inverse_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Ysin, yout, op->dft1,
-                       B, g.nt, g.np, g.cdet, scale);
+                       B, g.nt, g.np, g.cdet, scale, sumsq);
   else if (fastest)
     hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL>), cfgrid, dim3(kFB), 0, st, yin, Ysout,
                        op->dft1, B, g.nt, g.np, g.cdet);
@@ -194,12 +215,12 @@ tomo_status det_launch(bool inverse, bool fastest, const tomo_op* op, const floa
 
 tomo_status det_dispatch(bool inverse, bool fastest, const tomo_op* op, const float2* Yin,
                          float2* Yout, const float* yin, float* yout, int B, float scale,
-                         hipStream_t st) {
+                         double* sumsq, hipStream_t st) {
   const bool bl = op->dft1.M != op->g.L;
 #define TOMO_DET(M_)                                                                             \
   case M_:                                                                                      \
-    return bl ? det_launch<M_, true>(inverse, fastest, op, Yin, Yout, yin, yout, B, scale, st)  \
-              : det_launch<M_, false>(inverse, fastest, op, Yin, Yout, yin, yout, B, scale, st);
+    return bl ? det_launch<M_, true>(inverse, fastest, op, Yin, Yout, yin, yout, B, scale, sumsq, st) \
+              : det_launch<M_, false>(inverse, fastest, op, Yin, Yout, yin, yout, B, scale, sumsq, st);
   switch (op->dft1.M) {
     TOMO_DET(16) TOMO_DET(32) TOMO_DET(64) TOMO_DET(128) TOMO_DET(256) TOMO_DET(512) TOMO_DET(1024)
     TOMO_DET(2048) TOMO_DET(4096) TOMO_DET(8192)
@@ -214,14 +235,20 @@ bool det_fft_supported(const tomo_op* op) { return op->dft1.tw != nullptr; }
 
 bool det_cf_supported(const tomo_op* op) { return det_fft_supported(op) && op->dft1.M <= 4096; }
 
+int64_t det_inverse_blocks_per_channel(const tomo_op* op) {
+  if (!det_fft_supported(op)) return 0;
+  const int ag = det_rows_per_block(op->dft1.M);
+  return (op->g.nt + ag - 1) / ag;
+}
+
 tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Ys, float* y, int B,
-                                    float scale, hipStream_t st) {
-  return det_dispatch(true, false, op, Ys, nullptr, nullptr, y, B, scale, st);
+                                    float scale, double* sumsq, hipStream_t st) {
+  return det_dispatch(true, false, op, Ys, nullptr, nullptr, y, B, scale, sumsq, st);
 }
 
 tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
                                    bool channel_fastest, hipStream_t st) {
-  return det_dispatch(false, channel_fastest, op, nullptr, Y, y, nullptr, B, 1.0f, st);
+  return det_dispatch(false, channel_fastest, op, nullptr, Y, y, nullptr, B, 1.0f, nullptr, st);
 }
 
 }  // namespace tomo

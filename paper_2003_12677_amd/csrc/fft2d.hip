@@ -28,8 +28,7 @@ using namespace fftk;
 
 // rows per row block: about 32 KB of LDS, so that four blocks share a CU (M = the transform length
 // held in LDS: G itself, or the Bluestein length for other G)
-template <int M>
-constexpr int rows_per_block() {
+constexpr int rows_per_block(int M) {
   return M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
 }
 
@@ -118,11 +117,14 @@ __global__ __launch_bounds__(kFB) void k_cols(float2* __restrict__ Xs, DftTables
   }
 }
 
+// With sumsq set, the block also sums the squares of the values it writes (float64), per slice:
+// sumsq[s * groups + j] for its group j of grid rows.
 template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict__ Xs,
                                                        float* __restrict__ x,
                                                        const float* __restrict__ kd, DftTables t,
-                                                       int B, int n, int on, float scale) {
+                                                       int B, int n, int on, float scale,
+                                                       double* __restrict__ sumsq) {
   __shared__ float2 buf[lds_size<AG * M>()];
   const int G = BL ? t.N : M;
   const int groups = (G + AG - 1) / AG;
@@ -149,6 +151,7 @@ __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict_
   dft_lds<M, AG, true, BL>(buf, t);
   const int64_t plane = (int64_t)n * n;
   const bool odd = 2 * c + 1 < B;
+  double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nq * n; i += kFB) {
     const int q = i / n, i2 = i % n;
     int i1 = g1_0 + q + on;
@@ -158,8 +161,19 @@ __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict_
     const float2 v = buf[lds(q * M + g2)];
     const float k = scale * kd[i1] * kd[i2];
     const int64_t off = (int64_t)i1 * n + i2;
-    x[(int64_t)(2 * c) * plane + off] = v.x * k;
-    if (odd) x[(int64_t)(2 * c + 1) * plane + off] = v.y * k;
+    const float re = v.x * k, im = v.y * k;
+    x[(int64_t)(2 * c) * plane + off] = re;
+    if (odd) x[(int64_t)(2 * c + 1) * plane + off] = im;
+    s0 += (double)re * (double)re;
+    s1 += (double)im * (double)im;
+  }
+  if (sumsq) {
+    block_sum2(s0, s1);
+    if (threadIdx.x == 0) {
+      const int j = blockIdx.x % groups;
+      sumsq[(int64_t)(2 * c) * groups + j] = s0;
+      if (odd) sumsq[(int64_t)(2 * c + 1) * groups + j] = s1;
+    }
   }
 }
 
@@ -167,8 +181,8 @@ enum class Step { RowsEmbed, ColsFwd, ColsInv, RowsInvCrop };
 
 template <int M, bool BL>
 tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
-                        int B, float scale, hipStream_t st) {
-  constexpr int AG = rows_per_block<M>(), W = cols_per_block<M>();
+                        int B, float scale, double* sumsq, hipStream_t st) {
+  constexpr int AG = rows_per_block(M), W = cols_per_block<M>();
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
   const DftTables& t = op->dft2;
@@ -187,7 +201,7 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
       break;
     case Step::RowsInvCrop:
       hipLaunchKernelGGL((k_rows_inv_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Xs, xout, op->kd_dev,
-                         t, B, g.n, g.on, scale);
+                         t, B, g.n, g.on, scale, sumsq);
       break;
   }
   TOMO_HIP(hipGetLastError());
@@ -195,12 +209,12 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
 }
 
 tomo_status grid_dispatch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
-                          int B, float scale, hipStream_t st) {
+                          int B, float scale, double* sumsq, hipStream_t st) {
   const bool bl = op->dft2.M != op->g.G;
 #define TOMO_GRID(M_)                                                                            \
   case M_:                                                                                      \
-    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, st)                       \
-              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, st);
+    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, sumsq, st)                \
+              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, sumsq, st);
   switch (op->dft2.M) {
     TOMO_GRID(16) TOMO_GRID(32) TOMO_GRID(64) TOMO_GRID(128) TOMO_GRID(256) TOMO_GRID(512)
     TOMO_GRID(1024) TOMO_GRID(2048) TOMO_GRID(4096) TOMO_GRID(8192)
@@ -213,16 +227,22 @@ tomo_status grid_dispatch(Step s, const tomo_op* op, const float* xin, float2* X
 
 bool grid_fft_supported(const tomo_op* op) { return op->dft2.tw != nullptr; }
 
+int64_t grid_inverse_blocks_per_channel(const tomo_op* op) {
+  if (!grid_fft_supported(op)) return 0;
+  const int ag = rows_per_block(op->dft2.M);
+  return (op->g.G + ag - 1) / ag;
+}
+
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
                                 hipStream_t st) {
-  TOMO_TRY(grid_dispatch(Step::RowsEmbed, op, x, Xs, nullptr, B, 1.f, st));
-  return grid_dispatch(Step::ColsFwd, op, nullptr, Xs, nullptr, B, 1.f, st);
+  TOMO_TRY(grid_dispatch(Step::RowsEmbed, op, x, Xs, nullptr, B, 1.f, nullptr, st));
+  return grid_dispatch(Step::ColsFwd, op, nullptr, Xs, nullptr, B, 1.f, nullptr, st);
 }
 
 tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
-                                hipStream_t st) {
-  TOMO_TRY(grid_dispatch(Step::ColsInv, op, nullptr, Xs, nullptr, B, 1.f, st));
-  return grid_dispatch(Step::RowsInvCrop, op, nullptr, Xs, x, B, scale, st);
+                                double* sumsq, hipStream_t st) {
+  TOMO_TRY(grid_dispatch(Step::ColsInv, op, nullptr, Xs, nullptr, B, 1.f, nullptr, st));
+  return grid_dispatch(Step::RowsInvCrop, op, nullptr, Xs, x, B, scale, sumsq, st);
 }
 
 }  // namespace tomo

@@ -46,6 +46,28 @@ constexpr int lds_rows_size() { return lds_size<CH * L>() + CH * PAD; }
 template <int M>
 constexpr int row_skew() { return M >= 32 ? (8 - (M + M / 32) % 32 + 32) % 32 : 0; }
 
+// Sums a and b over the block in float64, in a fixed order (result in thread 0).  Every thread
+// of the block must call it.
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double red[2][kFB / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = b = 0.0;
+    for (int w = 0; w < kFB / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+  }
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

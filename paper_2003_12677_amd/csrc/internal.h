@@ -240,6 +240,8 @@ struct SolverBuffers {
   float *r = nullptr, *q = nullptr, *rb = nullptr;     // sinogram-sized [B][nt][np]
   double* scal = nullptr;                              // per-slice scalars [16][B]
   double* partial = nullptr;                           // dot partial sums [B][kDotBlocks]
+  double* norm_partial = nullptr;                      // output-norm partial sums [B][norm_blocks]
+  int64_t norm_blocks = 0;
   float* tvb = nullptr;                                // split-Bregman fields [6][B][n][n]
 };
 
@@ -371,9 +373,14 @@ bool adj_tile_supported(const tomo_op* op);
 constexpr size_t kMaxTileLds = 65536;   // staged kernels are used when their LDS fits this
 
 // composite operators on caller buffers
-tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st);
+// With sumsq set (project_sumsq_blocks(op) > 0, else an error), the last kernel also leaves the
+// float64 partial sums of each output slice's squared norm in sumsq ([B][blocks]).
+tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st,
+                          double* sumsq = nullptr);
+int64_t project_sumsq_blocks(const tomo_op* op);
+int64_t backproject_sumsq_blocks(const tomo_op* op);
 tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
-                              float extra_scale, hipStream_t st);
+                              float extra_scale, hipStream_t st, double* sumsq = nullptr);
 
 // solver
 tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_solve_opts* o,
@@ -398,7 +405,7 @@ void free_tv(tomo_op* op);
 bool det_fft_supported(const tomo_op* op);
 bool det_cf_supported(const tomo_op* op);
 tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Ys, float* y, int B,
-                                    float scale, hipStream_t st);
+                                    float scale, double* sumsq, hipStream_t st);
 tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
                                    bool channel_fastest, hipStream_t st);
 // Cartesian 2D DFT fused with embed (forward) and crop (inverse), any G with a DFT table:
@@ -407,7 +414,12 @@ bool grid_fft_supported(const tomo_op* op);
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
                                 hipStream_t st);
 tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
-                                hipStream_t st);
+                                double* sumsq, hipStream_t st);
+// The output kernels of the inverse transforms can also sum the squares of what they write, per
+// slice, as float64 partial sums sumsq[s * blocks + j] (blocks per channel below; 0 when the
+// operator has no hand-written transform of that kind).
+int64_t det_inverse_blocks_per_channel(const tomo_op* op);
+int64_t grid_inverse_blocks_per_channel(const tomo_op* op);
 tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
                          hipStream_t st);
 tomo_status normal_supported(const tomo_op* op);

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -372,7 +373,9 @@ void free_solver(tomo_op* op) {
   }
   if (b.scal) (void)hipFree(b.scal);
   if (b.partial) (void)hipFree(b.partial);
-  b.scal = b.partial = nullptr;
+  if (b.norm_partial) (void)hipFree(b.norm_partial);
+  b.scal = b.partial = b.norm_partial = nullptr;
+  b.norm_blocks = 0;
   b.B = 0;
 }
 
@@ -385,12 +388,16 @@ tomo_status ensure_solver(tomo_op* op) {
   const size_t B = (size_t)g.max_batch;
   const size_t img = B * g.n * g.n * sizeof(float);
   const size_t sino = B * g.nt * g.np * sizeof(float);
+  // output-norm partials of either inverse transform, whichever tuning is set later
+  const int64_t norm_blocks = std::max<int64_t>(
+      1, std::max(det_inverse_blocks_per_channel(op), grid_inverse_blocks_per_channel(op)));
   struct Req { void** p; size_t bytes; } req[] = {
       {(void**)&b.p, img},  {(void**)&b.s, img},  {(void**)&b.d, img},  {(void**)&b.t, img},
       {(void**)&b.tvb, 6 * img},
       {(void**)&b.r, sino}, {(void**)&b.q, sino}, {(void**)&b.rb, sino},
       {(void**)&b.scal, kSlots * B * sizeof(double)},
-      {(void**)&b.partial, 2 * B * kDotBlocks * sizeof(double)}};   // two reductions at once
+      {(void**)&b.partial, 2 * B * kDotBlocks * sizeof(double)},     // two reductions at once
+      {(void**)&b.norm_partial, B * (size_t)norm_blocks * sizeof(double)}};
   for (auto& r : req) {
     if (hipMalloc(r.p, r.bytes) != hipSuccess) {
       *r.p = nullptr;
@@ -399,6 +406,7 @@ tomo_status ensure_solver(tomo_op* op) {
     }
   }
   b.B = (int)B;
+  b.norm_blocks = norm_blocks;
   return TOMO_OK;
 }
 
@@ -410,6 +418,31 @@ struct Ctx {
   double* sc(int slot) const { return op->sb.scal + (int64_t)slot * op->g.max_batch; }
   tomo_status dot(const float* a, const float* b, int64_t len, int slot) const {
     return launch_dot(a, b, len, B, op->sb.partial, sc(slot), st);
+  }
+  // y = A_vt x and slot = |y|^2, the squares summed by the projection's last kernel as it writes
+  // y when it can (no separate pass over y), else by a dot product
+  tomo_status project_norm(const float* x, float* y, int vt, int slot) const {
+    const int64_t nb = project_sumsq_blocks(op);
+    if (nb == 0 || nb > op->sb.norm_blocks) {
+      TOMO_TRY(apply_project(op, x, y, B, vt, st));
+      return dot(y, y, sino, slot);
+    }
+    TOMO_TRY(apply_project(op, x, y, B, vt, st, op->sb.norm_partial));
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.norm_partial, (int)nb, sc(slot));
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
+  // x = A_vt^T y and slot = |x|^2, likewise
+  tomo_status backproject_norm(const float* y, float* x, int vt, int slot) const {
+    const int64_t nb = backproject_sumsq_blocks(op);
+    if (nb == 0 || nb > op->sb.norm_blocks) {
+      TOMO_TRY(apply_backproject(op, y, x, B, vt, TOMO_FILTER_NONE, 1.0f, st));
+      return dot(x, x, img, slot);
+    }
+    TOMO_TRY(apply_backproject(op, y, x, B, vt, TOMO_FILTER_NONE, 1.0f, st, op->sb.norm_partial));
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.norm_partial, (int)nb, sc(slot));
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
   }
   tomo_status lin(float* out, const float* a, const float* b, const double* ca, const double* cb,
                   double sa, double sb, int64_t len) const {
@@ -455,18 +488,15 @@ tomo_status cgls(const Ctx& c, const float* b, float* x, int vt, int iters, bool
     TOMO_TRY(launch_fill(x, 0.f, c.img * c.B, c.st));
     TOMO_TRY(c.lin(w.r, b, nullptr, nullptr, nullptr, 1.0, 0.0, c.sino));    // r = b
   }
-  TOMO_TRY(apply_backproject(c.op, w.r, w.s, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));   // s = A^T r
-  TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));     // p = s
   int cur = kGamma0, nxt = kGamma1;
-  TOMO_TRY(c.dot(w.s, w.s, c.img, cur));                                      // gamma = |s|^2
+  TOMO_TRY(c.backproject_norm(w.r, w.s, vt, cur));          // s = A^T r; gamma = |s|^2
+  TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));     // p = s
   for (int it = 0; it < iters; ++it) {
-    TOMO_TRY(apply_project(c.op, w.p, w.q, c.B, vt, c.st));                  // q = A p
-    TOMO_TRY(c.dot(w.q, w.q, c.sino, kDelta));                                // delta = |q|^2
+    TOMO_TRY(c.project_norm(w.p, w.q, vt, kDelta));         // q = A p; delta = |q|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
     TOMO_HIP(hipGetLastError());
     TOMO_TRY(c.lin(w.r, w.r, w.q, nullptr, c.sc(kAlpha), 1.0, -1.0, c.sino));// r -= alpha q
-    TOMO_TRY(apply_backproject(c.op, w.r, w.s, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
-    TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));                                    // gamma' = |s|^2
+    TOMO_TRY(c.backproject_norm(w.r, w.s, vt, nxt));        // s = A^T r; gamma' = |s|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
     TOMO_HIP(hipGetLastError());
     TOMO_TRY(c.cg_step(x, w.p, w.s, c.img));             // x += alpha p; p = s + beta p

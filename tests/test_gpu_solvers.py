@@ -93,14 +93,22 @@ def test_cgls_warm_start_matches_oracle(tomo):
     op.close()
 
 
-def test_early_cgls_iterates_are_tight(tomo):
+@pytest.mark.parametrize("fft", [(1, 1, 4), (1, 1, 5), (0, 0, 5), (1, 0, 3), (0, 1, 3)],
+                         ids=["fused_norms", "fused_norms_odd_batch", "library_transforms",
+                              "fused_projection_norm", "fused_backprojection_norm"])
+def test_early_cgls_iterates_are_tight(tomo, fft):
     """Before the float32 Krylov process separates in the near-null space (about eight
-    iterations on this operator) the iterates agree tightly with the float64 oracle."""
-    n, nt, npb, B, iters = 64, 90, 91, 4, 5
+    iterations on this operator) the iterates agree tightly with the float64 oracle.  With the
+    hand-written inverse transforms the squared norms |A p|^2 and |A^T r|^2 come from the
+    transforms' own output passes; with rocFFT from separate dot products; and in the mixed
+    settings one of each."""
+    det, grid, B = fft
+    n, nt, npb, iters = 64, 90, 91, 5
     ref = oracle_op(n, nt, npb)
     xt = phantom_stack(n, B, seed_base=540)
     b = np.stack([ref.project(v) for v in xt])
     op = tomo.Operator(n, nt, npb, max_batch=B, device=0)
+    op.set_tuning(det_fft=det, grid_fft=grid)
     xg = _host(op.solve(_dev(b), iters=iters))
     for s in range(B):
         xr = cgls(ref.project, ref.backproject, r32(b[s]), iters)
