@@ -404,6 +404,36 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
 }
 
 // backproject: pad -> F1D -> S diag(D) -> F2D^H -> crop + deapodise (Eq. (2), second line)
+namespace {
+
+// backproject from the channel-fastest polar data in op->Y onwards: filter, adjoint SpMM, inverse
+// 2D DFT, crop + deapodise
+tomo_status backproject_from_polar(tomo_op* op, float* x, int B, int vt, int filter,
+                                   float extra_scale, FFTPlans* p, hipStream_t st, double* sumsq) {
+  const Geom& g = op->g;
+  const int C = (B + 1) / 2;
+  const float* ds = nullptr;
+  if (filter == TOMO_FILTER_DENSITY)
+    TOMO_TRY(launch_scale_rows(op->Y, op->dens, (int64_t)g.L * g.nt, C, st));
+  else if (filter != TOMO_FILTER_NONE)
+    ds = op->filt_dev[filter];
+  const float scale = extra_scale / (float)g.L;
+  if (spmm_adj_slowest_ok(op, C, vt)) {
+    // the staged adjoint writes its tiles into the FFT-side grid itself
+    TOMO_TRY(launch_spmm_adj(op, op->Y, op->Xs, C, vt, ds, st, true));
+  } else {
+    TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
+    TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
+  }
+  if (op->tune.grid_fft && grid_fft_supported(op))
+    return launch_grid_inverse(op, op->Xs, x, B, scale, sumsq, st);
+  TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
+  TOMO_TRY(launch_crop_image(op, op->Xs, x, B, scale, st));
+  return TOMO_OK;
+}
+
+}  // namespace
+
 tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
                               float extra_scale, hipStream_t st, double* sumsq) {
   if (sumsq && backproject_sumsq_blocks(op) == 0)
@@ -424,24 +454,23 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
     }
     TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
   }
-  const float* ds = nullptr;
-  if (filter == TOMO_FILTER_DENSITY)
-    TOMO_TRY(launch_scale_rows(op->Y, op->dens, (int64_t)g.L * g.nt, C, st));
-  else if (filter != TOMO_FILTER_NONE)
-    ds = op->filt_dev[filter];
-  const float scale = extra_scale / (float)g.L;
-  if (spmm_adj_slowest_ok(op, C, vt)) {
-    // the staged adjoint writes its tiles into the FFT-side grid itself
-    TOMO_TRY(launch_spmm_adj(op, op->Y, op->Xs, C, vt, ds, st, true));
-  } else {
-    TOMO_TRY(launch_spmm_adj(op, op->Y, op->X, C, vt, ds, st));
-    TOMO_TRY(launch_to_channel_slowest(op->X, op->Xs, (int64_t)g.G * g.G, C, st));
-  }
-  if (op->tune.grid_fft && grid_fft_supported(op))
-    return launch_grid_inverse(op, op->Xs, x, B, scale, sumsq, st);
-  TOMO_TRY(fft_exec(p->inv2, p, op->Xs, st));
-  TOMO_TRY(launch_crop_image(op, op->Xs, x, B, scale, st));
-  return TOMO_OK;
+  return backproject_from_polar(op, x, B, vt, filter, extra_scale, p, st, sumsq);
+}
+
+bool backproject_residual_supported(const tomo_op* op) {
+  return op->tune.det_fft == 1 && det_cf_supported(op);
+}
+
+tomo_status apply_backproject_residual(tomo_op* op, float* r, const float* q, const double* alpha,
+                                       float* x, int B, int vt, hipStream_t st, double* sumsq) {
+  if (!backproject_residual_supported(op))
+    return fail(TOMO_EINVAL, "internal: the fused residual step needs the channel-fastest front");
+  if (sumsq && backproject_sumsq_blocks(op) == 0)
+    return fail(TOMO_EINVAL, "internal: output norms need the hand-written grid transform");
+  FFTPlans* p = nullptr;
+  TOMO_TRY(get_plans(op, (B + 1) / 2, &p));
+  TOMO_TRY(launch_det_residual_forward(op, r, q, alpha, op->Y, B, st));
+  return backproject_from_polar(op, x, B, vt, TOMO_FILTER_NONE, 1.0f, p, st, sumsq);
 }
 
 tomo_status normal_supported(const tomo_op* op) {

@@ -146,10 +146,14 @@ template <int M>
 constexpr int det_cw() { return M >= 16384 ? 1 : (16384 / M > 8 ? 8 : 16384 / M); }
 
 // y[B][nt][np] -> pad with the axis shift, slices paired -> forward DFT of each row ->
-// Yf[L][nt][C] (polar row k * nt + a, channel fastest).  One block per (angle a, channels
-// c0 .. c0 + CW - 1), XCD-remapped so that the channel groups of one angle are neighbours.
-template <int M, int CW, bool BL>
-__global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* __restrict__ y,
+// Yf[L][nt][C] (polar row k * nt + a, channel fastest).  One block per (angle a, channels c0 ..
+// c0 + CW - 1), XCD-remapped so that the channel groups of one angle are neighbours.
+// RES (a conjugate-gradient residual step fused in): y is r, updated in place to
+// r - alpha[s] q (the arithmetic of the separate update kernel) before it is transformed.
+template <int M, int CW, bool BL, bool RES>
+__global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* y, float* rnew,
+                                                            const float* __restrict__ qv,
+                                                            const double* __restrict__ alpha,
                                                             float2* __restrict__ Yf, DftTables t,
                                                             int B, int nt, int np, int cdet) {
   constexpr int PAD = row_skew<M>();
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* __restr
   const int nc = min(CW, C - c0);
   const int64_t plane = (int64_t)nt * np;
   constexpr int NE = (CW * M + kFB - 1) / kFB;   // loads per thread, issued as one batch
-  float2 v[NE];
+  float2 v[NE], w[NE];
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int i = threadIdx.x + u * kFB;
@@ -170,11 +174,41 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* __restr
     int b = m + cdet;                                 // radial index m holds bin (m + c) mod L
     b -= (b >= L) ? L : 0;
     v[u] = make_float2(0.f, 0.f);
+    w[u] = make_float2(0.f, 0.f);
     if (i < CW * M && q < nc && m < L && b < np) {
       const int c = c0 + q;
       const int64_t off = (int64_t)a * np + b;
       v[u].x = y[(int64_t)(2 * c) * plane + off];
-      if (2 * c + 1 < B) v[u].y = y[(int64_t)(2 * c + 1) * plane + off];
+      if (RES) w[u].x = qv[(int64_t)(2 * c) * plane + off];
+      if (2 * c + 1 < B) {
+        v[u].y = y[(int64_t)(2 * c + 1) * plane + off];
+        if (RES) w[u].y = qv[(int64_t)(2 * c + 1) * plane + off];
+      }
+    }
+  }
+  if constexpr (RES) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      const int q = i / M, m = i % M;
+      int b = m + cdet;
+      b -= (b >= L) ? L : 0;
+      if (i < CW * M && q < nc && m < L && b < np) {
+        const int c = c0 + q;
+        const int64_t off = (int64_t)a * np + b;
+        const float f0 = (float)(-1.0 * alpha[2 * c]);
+        float r0 = 1.0f * v[u].x;
+        r0 += f0 * w[u].x;
+        v[u].x = r0;
+        rnew[(int64_t)(2 * c) * plane + off] = r0;
+        if (2 * c + 1 < B) {
+          const float f1 = (float)(-1.0 * alpha[2 * c + 1]);
+          float r1 = 1.0f * v[u].y;
+          r1 += f1 * w[u].y;
+          v[u].y = r1;
+          rnew[(int64_t)(2 * c + 1) * plane + off] = r1;
+        }
+      }
     }
   }
 #pragma unroll
@@ -204,8 +238,8 @@ tomo_status det_launch(bool inverse, bool fastest, const tomo_op* op, const floa
     hipLaunchKernelGGL((k_det_inverse_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Ysin, yout, op->dft1,
                        B, g.nt, g.np, g.cdet, scale, sumsq);
   else if (fastest)
-    hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL>), cfgrid, dim3(kFB), 0, st, yin, Ysout,
-                       op->dft1, B, g.nt, g.np, g.cdet);
+    hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL, false>), cfgrid, dim3(kFB), 0, st, yin,
+                       nullptr, nullptr, nullptr, Ysout, op->dft1, B, g.nt, g.np, g.cdet);
   else
     hipLaunchKernelGGL((k_det_pad_forward<M, AG, BL>), grid, dim3(kFB), 0, st, yin, Ysout, op->dft1,
                        B, g.nt, g.np, g.cdet);
@@ -229,11 +263,40 @@ tomo_status det_dispatch(bool inverse, bool fastest, const tomo_op* op, const fl
 #undef TOMO_DET
 }
 
+template <int M, bool BL>
+tomo_status det_residual_launch(const tomo_op* op, float* r, const float* q, const double* alpha,
+                                float2* Yf, int B, hipStream_t st) {
+  constexpr int CW = det_cw<M>();
+  const int C = (B + 1) / 2;
+  const dim3 grid((unsigned)(op->g.nt * ((C + CW - 1) / CW)));
+  hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL, true>), grid, dim3(kFB), 0, st, r, r, q, alpha,
+                     Yf, op->dft1, B, op->g.nt, op->g.np, op->g.cdet);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
+
 }  // namespace
 
 bool det_fft_supported(const tomo_op* op) { return op->dft1.tw != nullptr; }
 
 bool det_cf_supported(const tomo_op* op) { return det_fft_supported(op) && op->dft1.M <= 4096; }
+
+tomo_status launch_det_residual_forward(const tomo_op* op, float* r, const float* q,
+                                        const double* alpha, float2* Yf, int B, hipStream_t st) {
+  if (!det_cf_supported(op))
+    return fail(TOMO_EINVAL, "internal: fused residual front needs transform length <= 4096");
+  const bool bl = op->dft1.M != op->g.L;
+#define TOMO_DETR(M_)                                                                            \
+  case M_:                                                                                      \
+    return bl ? det_residual_launch<M_, true>(op, r, q, alpha, Yf, B, st)                       \
+              : det_residual_launch<M_, false>(op, r, q, alpha, Yf, B, st);
+  switch (op->dft1.M) {
+    TOMO_DETR(16) TOMO_DETR(32) TOMO_DETR(64) TOMO_DETR(128) TOMO_DETR(256) TOMO_DETR(512)
+    TOMO_DETR(1024) TOMO_DETR(2048) TOMO_DETR(4096)
+    default: return fail(TOMO_EUNSUPPORTED, "fused detector DFT: no kernel for length %d", op->dft1.M);
+  }
+#undef TOMO_DETR
+}
 
 int64_t det_inverse_blocks_per_channel(const tomo_op* op) {
   if (!det_fft_supported(op)) return 0;

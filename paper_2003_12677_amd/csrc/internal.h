@@ -381,6 +381,13 @@ int64_t project_sumsq_blocks(const tomo_op* op);
 int64_t backproject_sumsq_blocks(const tomo_op* op);
 tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
                               float extra_scale, hipStream_t st, double* sumsq = nullptr);
+// r -= alpha[s] q (in place, per slice; the arithmetic of the separate update) fused into the
+// adjoint front, then x = A_vt^T r (no filter).  Needs the channel-fastest front
+// (backproject_residual_supported).
+bool backproject_residual_supported(const tomo_op* op);
+tomo_status apply_backproject_residual(tomo_op* op, float* r, const float* q, const double* alpha,
+                                       float* x, int B, int vt, hipStream_t st,
+                                       double* sumsq = nullptr);
 
 // solver
 tomo_status run_solve(tomo_op* op, const float* b, float* x, int B, const tomo_solve_opts* o,
@@ -408,6 +415,10 @@ tomo_status launch_det_inverse_crop(const tomo_op* op, const float2* Ys, float* 
                                     float scale, double* sumsq, hipStream_t st);
 tomo_status launch_det_pad_forward(const tomo_op* op, const float* y, float2* Y, int B,
                                    bool channel_fastest, hipStream_t st);
+// the channel-fastest forward front with r -= alpha[s] q applied to its input first (r updated
+// in place)
+tomo_status launch_det_residual_forward(const tomo_op* op, float* r, const float* q,
+                                        const double* alpha, float2* Yf, int B, hipStream_t st);
 // Cartesian 2D DFT fused with embed (forward) and crop (inverse), any G with a DFT table:
 // forward x -> Xs (channel-slowest), inverse Xs (overwritten) -> x.
 bool grid_fft_supported(const tomo_op* op);

@@ -432,6 +432,23 @@ struct Ctx {
     TOMO_HIP(hipGetLastError());
     return TOMO_OK;
   }
+  // r -= alpha q, then x = A_vt^T r and slot = |x|^2, the update fused into the adjoint front
+  // when it can be
+  tomo_status residual_backproject_norm(float* r, const float* q, float* x, int vt, int slot) const {
+    if (!backproject_residual_supported(op)) {
+      TOMO_TRY(lin(r, r, q, nullptr, sc(kAlpha), 1.0, -1.0, sino));
+      return backproject_norm(r, x, vt, slot);
+    }
+    const int64_t nb = backproject_sumsq_blocks(op);
+    if (nb == 0 || nb > op->sb.norm_blocks) {
+      TOMO_TRY(apply_backproject_residual(op, r, q, sc(kAlpha), x, B, vt, st));
+      return dot(x, x, img, slot);
+    }
+    TOMO_TRY(apply_backproject_residual(op, r, q, sc(kAlpha), x, B, vt, st, op->sb.norm_partial));
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.norm_partial, (int)nb, sc(slot));
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
   // x = A_vt^T y and slot = |x|^2, likewise
   tomo_status backproject_norm(const float* y, float* x, int vt, int slot) const {
     const int64_t nb = backproject_sumsq_blocks(op);
@@ -495,8 +512,8 @@ tomo_status cgls(const Ctx& c, const float* b, float* x, int vt, int iters, bool
     TOMO_TRY(c.project_norm(w.p, w.q, vt, kDelta));         // q = A p; delta = |q|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.lin(w.r, w.r, w.q, nullptr, c.sc(kAlpha), 1.0, -1.0, c.sino));// r -= alpha q
-    TOMO_TRY(c.backproject_norm(w.r, w.s, vt, nxt));        // s = A^T r; gamma' = |s|^2
+    // r -= alpha q; s = A^T r; gamma' = |s|^2
+    TOMO_TRY(c.residual_backproject_norm(w.r, w.q, w.s, vt, nxt));
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
     TOMO_HIP(hipGetLastError());
     TOMO_TRY(c.cg_step(x, w.p, w.s, c.img));             // x += alpha p; p = s + beta p

@@ -93,15 +93,17 @@ def test_cgls_warm_start_matches_oracle(tomo):
     op.close()
 
 
-@pytest.mark.parametrize("fft", [(1, 1, 4), (1, 1, 5), (0, 0, 5), (1, 0, 3), (0, 1, 3)],
+@pytest.mark.parametrize("fft", [(1, 1, 4), (1, 1, 5), (0, 0, 5), (1, 0, 3), (0, 1, 3), (2, 1, 3)],
                          ids=["fused_norms", "fused_norms_odd_batch", "library_transforms",
-                              "fused_projection_norm", "fused_backprojection_norm"])
+                              "fused_projection_norm", "fused_backprojection_norm",
+                              "separate_residual_update"])
 def test_early_cgls_iterates_are_tight(tomo, fft):
     """Before the float32 Krylov process separates in the near-null space (about eight
     iterations on this operator) the iterates agree tightly with the float64 oracle.  With the
     hand-written inverse transforms the squared norms |A p|^2 and |A^T r|^2 come from the
     transforms' own output passes; with rocFFT from separate dot products; and in the mixed
-    settings one of each."""
+    settings one of each.  The residual update r -= alpha q rides in the channel-fastest adjoint
+    front (det_fft 1) or runs as its own pass (det_fft 0 or 2)."""
     det, grid, B = fft
     n, nt, npb, iters = 64, 90, 91, 5
     ref = oracle_op(n, nt, npb)
