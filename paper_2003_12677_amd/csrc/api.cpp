@@ -373,20 +373,14 @@ int64_t backproject_sumsq_blocks(const tomo_op* op) {
 }
 
 // project: embed + deapodise -> F2D -> S^dagger -> F1D^-1 -> crop (Eq. (2), first line)
-tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st,
-                          double* sumsq) {
-  if (sumsq && project_sumsq_blocks(op) == 0)
-    return fail(TOMO_EINVAL, "internal: output norms need the hand-written detector transform");
+namespace {
+
+// project from the forward grid transform's output in op->Xs onwards: forward SpMM, inverse
+// detector DFT, crop
+tomo_status project_from_grid(tomo_op* op, float* y, int B, int vt, FFTPlans* p, hipStream_t st,
+                              double* sumsq) {
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
-  FFTPlans* p = nullptr;
-  TOMO_TRY(get_plans(op, C, &p));
-  if (op->tune.grid_fft && grid_fft_supported(op)) {
-    TOMO_TRY(launch_grid_forward(op, x, op->Xs, B, st));
-  } else {
-    TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
-    TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
-  }
   if (spmm_fwd_slowest_ok(op, C, vt)) {
     // the staged forward reads its patches from the FFT-side grid and writes the FFT-side polar
     // rows itself
@@ -401,6 +395,39 @@ tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, 
   TOMO_TRY(fft_exec(p->inv1, p, op->Ys, st));
   TOMO_TRY(launch_crop_sino(op, op->Ys, y, B, 1.0f / (float)g.L, st));
   return TOMO_OK;
+}
+
+}  // namespace
+
+tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st,
+                          double* sumsq) {
+  if (sumsq && project_sumsq_blocks(op) == 0)
+    return fail(TOMO_EINVAL, "internal: output norms need the hand-written detector transform");
+  FFTPlans* p = nullptr;
+  TOMO_TRY(get_plans(op, (B + 1) / 2, &p));
+  if (op->tune.grid_fft && grid_fft_supported(op)) {
+    TOMO_TRY(launch_grid_forward(op, x, op->Xs, B, st));
+  } else {
+    TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
+    TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
+  }
+  return project_from_grid(op, y, B, vt, p, st, sumsq);
+}
+
+bool project_cg_supported(const tomo_op* op) {
+  return op->tune.grid_fft && grid_cg_step_supported(op);
+}
+
+tomo_status apply_project_cg(tomo_op* op, float* pdir, const CgStep& cg, float* y, int B, int vt,
+                             hipStream_t st, double* sumsq) {
+  if (!project_cg_supported(op))
+    return fail(TOMO_EINVAL, "internal: the fused CG step needs the hand-written grid transform");
+  if (sumsq && project_sumsq_blocks(op) == 0)
+    return fail(TOMO_EINVAL, "internal: output norms need the hand-written detector transform");
+  FFTPlans* p = nullptr;
+  TOMO_TRY(get_plans(op, (B + 1) / 2, &p));
+  TOMO_TRY(launch_grid_forward(op, pdir, op->Xs, B, st, &cg));
+  return project_from_grid(op, y, B, vt, p, st, sumsq);
 }
 
 // backproject: pad -> F1D -> S diag(D) -> F2D^H -> crop + deapodise (Eq. (2), second line)

@@ -41,8 +41,15 @@ constexpr int cols_per_block() {
 
 // The grid side G is t.N: M for power-of-two grids (BL = false), else the DFTs go through
 // Bluestein's identity at length M.  Indices below t.N are grid indices; LDS rows have stride M.
-template <int M, int AG, bool BL>
-__global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
+// CG (a conjugate-gradient step fused in): x is the search direction p, and before it is
+// embedded each pixel takes the deferred step  xsol += alpha[s] p;  p = snew + beta[s] p  (the
+// arithmetic of the separate step kernel), both written back in place; the new p is transformed.
+template <int M, int AG, bool BL, bool CG>
+__global__ __launch_bounds__(kFB) void k_rows_embed(const float* x, float* pout,
+                                                    float* __restrict__ xsol,
+                                                    const float* __restrict__ snew,
+                                                    const double* __restrict__ alpha,
+                                                    const double* __restrict__ beta,
                                                     float2* __restrict__ Xs,
                                                     const float* __restrict__ kd, DftTables t,
                                                     int B, int n, int on) {
@@ -55,6 +62,7 @@ __global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
   const int64_t plane = (int64_t)n * n;
   const bool odd = 2 * c + 1 < B;
   float re[NE], im[NE], kk[NE];
+  float sr[CG ? NE : 1], si[CG ? NE : 1], xr[CG ? NE : 1], xi[CG ? NE : 1];
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int i = threadIdx.x + u * kFB;
@@ -70,6 +78,45 @@ __global__ __launch_bounds__(kFB) void k_rows_embed(const float* __restrict__ x,
       kk[u] = kd[i1] * kd[i2];
       re[u] = x[(int64_t)(2 * c) * plane + off];
       if (odd) im[u] = x[(int64_t)(2 * c + 1) * plane + off];
+      if constexpr (CG) {
+        sr[u] = snew[(int64_t)(2 * c) * plane + off];
+        xr[u] = xsol[(int64_t)(2 * c) * plane + off];
+        if (odd) {
+          si[u] = snew[(int64_t)(2 * c + 1) * plane + off];
+          xi[u] = xsol[(int64_t)(2 * c + 1) * plane + off];
+        }
+      }
+    }
+  }
+  if constexpr (CG) {
+    const float fa0 = (float)alpha[2 * c], fb0 = (float)beta[2 * c];
+    const float fa1 = odd ? (float)alpha[2 * c + 1] : 0.f, fb1 = odd ? (float)beta[2 * c + 1] : 0.f;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int i = threadIdx.x + u * kFB;
+      const int q = i / M, g2 = i % M;
+      int i1 = g1_0 + q + on, i2 = g2 + on;
+      i1 -= (i1 >= G) ? G : 0;
+      i2 -= (i2 >= G) ? G : 0;
+      if (i < AG * M && g1_0 + q < G && g2 < G && i1 < n && i2 < n) {
+        const int64_t off = (int64_t)i1 * n + i2;
+        float xv = 1.0f * xr[u];
+        xv += fa0 * re[u];
+        xsol[(int64_t)(2 * c) * plane + off] = xv;
+        float nv = 1.0f * sr[u];
+        nv += fb0 * re[u];
+        pout[(int64_t)(2 * c) * plane + off] = nv;
+        re[u] = nv;
+        if (odd) {
+          float xw = 1.0f * xi[u];
+          xw += fa1 * im[u];
+          xsol[(int64_t)(2 * c + 1) * plane + off] = xw;
+          float nw = 1.0f * si[u];
+          nw += fb1 * im[u];
+          pout[(int64_t)(2 * c + 1) * plane + off] = nw;
+          im[u] = nw;
+        }
+      }
     }
   }
 #pragma unroll
@@ -179,9 +226,11 @@ __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict_
 
 enum class Step { RowsEmbed, ColsFwd, ColsInv, RowsInvCrop };
 
+constexpr int kMaxCgStepM = 2048;
+
 template <int M, bool BL>
 tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
-                        int B, float scale, double* sumsq, hipStream_t st) {
+                        int B, float scale, double* sumsq, const CgStep* cg, hipStream_t st) {
   constexpr int AG = rows_per_block(M), W = cols_per_block<M>();
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
@@ -190,8 +239,17 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
   const dim3 grid((unsigned)(C * ((G + AG - 1) / AG))), cgrid((unsigned)(C * ((G + W - 1) / W)));
   switch (s) {
     case Step::RowsEmbed:
-      hipLaunchKernelGGL((k_rows_embed<M, AG, BL>), grid, dim3(kFB), 0, st, xin, Xs, op->kd_dev, t,
-                         B, g.n, g.on);
+      if (cg) {
+        // the fused step's extra loads fit the registers up to M = 2048 (kMaxCgStepM)
+        if constexpr (M <= kMaxCgStepM)
+          hipLaunchKernelGGL((k_rows_embed<M, AG, BL, true>), grid, dim3(kFB), 0, st, xin,
+                             const_cast<float*>(xin), cg->x, cg->s, cg->alpha, cg->beta, Xs,
+                             op->kd_dev, t, B, g.n, g.on);
+        else
+          return fail(TOMO_EINVAL, "internal: fused CG step for transform length %d", M);
+      } else
+        hipLaunchKernelGGL((k_rows_embed<M, AG, BL, false>), grid, dim3(kFB), 0, st, xin, nullptr,
+                           nullptr, nullptr, nullptr, nullptr, Xs, op->kd_dev, t, B, g.n, g.on);
       break;
     case Step::ColsFwd:
       hipLaunchKernelGGL((k_cols<M, W, false, BL>), cgrid, dim3(kFB), 0, st, Xs, t);
@@ -209,12 +267,12 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
 }
 
 tomo_status grid_dispatch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
-                          int B, float scale, double* sumsq, hipStream_t st) {
+                          int B, float scale, double* sumsq, const CgStep* cg, hipStream_t st) {
   const bool bl = op->dft2.M != op->g.G;
 #define TOMO_GRID(M_)                                                                            \
   case M_:                                                                                      \
-    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, sumsq, st)                \
-              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, sumsq, st);
+    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, sumsq, cg, st)            \
+              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, sumsq, cg, st);
   switch (op->dft2.M) {
     TOMO_GRID(16) TOMO_GRID(32) TOMO_GRID(64) TOMO_GRID(128) TOMO_GRID(256) TOMO_GRID(512)
     TOMO_GRID(1024) TOMO_GRID(2048) TOMO_GRID(4096) TOMO_GRID(8192)
@@ -227,6 +285,10 @@ tomo_status grid_dispatch(Step s, const tomo_op* op, const float* xin, float2* X
 
 bool grid_fft_supported(const tomo_op* op) { return op->dft2.tw != nullptr; }
 
+bool grid_cg_step_supported(const tomo_op* op) {
+  return grid_fft_supported(op) && op->dft2.M <= kMaxCgStepM;
+}
+
 int64_t grid_inverse_blocks_per_channel(const tomo_op* op) {
   if (!grid_fft_supported(op)) return 0;
   const int ag = rows_per_block(op->dft2.M);
@@ -234,15 +296,15 @@ int64_t grid_inverse_blocks_per_channel(const tomo_op* op) {
 }
 
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
-                                hipStream_t st) {
-  TOMO_TRY(grid_dispatch(Step::RowsEmbed, op, x, Xs, nullptr, B, 1.f, nullptr, st));
-  return grid_dispatch(Step::ColsFwd, op, nullptr, Xs, nullptr, B, 1.f, nullptr, st);
+                                hipStream_t st, const CgStep* cg) {
+  TOMO_TRY(grid_dispatch(Step::RowsEmbed, op, x, Xs, nullptr, B, 1.f, nullptr, cg, st));
+  return grid_dispatch(Step::ColsFwd, op, nullptr, Xs, nullptr, B, 1.f, nullptr, nullptr, st);
 }
 
 tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
                                 double* sumsq, hipStream_t st) {
-  TOMO_TRY(grid_dispatch(Step::ColsInv, op, nullptr, Xs, nullptr, B, 1.f, nullptr, st));
-  return grid_dispatch(Step::RowsInvCrop, op, nullptr, Xs, x, B, scale, sumsq, st);
+  TOMO_TRY(grid_dispatch(Step::ColsInv, op, nullptr, Xs, nullptr, B, 1.f, nullptr, nullptr, st));
+  return grid_dispatch(Step::RowsInvCrop, op, nullptr, Xs, x, B, scale, sumsq, nullptr, st);
 }
 
 }  // namespace tomo

@@ -373,10 +373,23 @@ bool adj_tile_supported(const tomo_op* op);
 constexpr size_t kMaxTileLds = 65536;   // staged kernels are used when their LDS fits this
 
 // composite operators on caller buffers
+// A deferred conjugate-gradient step applied by the forward transform's first kernel to its input
+// p before embedding it: x += alpha[s] p; p = s + beta[s] p (p, x updated in place).
+struct CgStep {
+  float* x;
+  const float* s;
+  const double* alpha;
+  const double* beta;
+};
 // With sumsq set (project_sumsq_blocks(op) > 0, else an error), the last kernel also leaves the
 // float64 partial sums of each output slice's squared norm in sumsq ([B][blocks]).
 tomo_status apply_project(tomo_op* op, const float* x, float* y, int B, int vt, hipStream_t st,
                           double* sumsq = nullptr);
+// project of p with the deferred CG step fused into the first kernel (project_cg_supported:
+// the hand-written grid transform): x += alpha p; p = s + beta p; y = A_vt p.
+bool project_cg_supported(const tomo_op* op);
+tomo_status apply_project_cg(tomo_op* op, float* p, const CgStep& cg, float* y, int B, int vt,
+                             hipStream_t st, double* sumsq = nullptr);
 int64_t project_sumsq_blocks(const tomo_op* op);
 int64_t backproject_sumsq_blocks(const tomo_op* op);
 tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int vt, int filter,
@@ -422,8 +435,11 @@ tomo_status launch_det_residual_forward(const tomo_op* op, float* r, const float
 // Cartesian 2D DFT fused with embed (forward) and crop (inverse), any G with a DFT table:
 // forward x -> Xs (channel-slowest), inverse Xs (overwritten) -> x.
 bool grid_fft_supported(const tomo_op* op);
+// cg: the deferred CG step fused into the first kernel (grid_cg_step_supported: transform
+// length up to 2048)
+bool grid_cg_step_supported(const tomo_op* op);
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
-                                hipStream_t st);
+                                hipStream_t st, const CgStep* cg = nullptr);
 tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
                                 double* sumsq, hipStream_t st);
 // The output kernels of the inverse transforms can also sum the squares of what they write, per

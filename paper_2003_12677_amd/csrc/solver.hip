@@ -419,6 +419,26 @@ struct Ctx {
   tomo_status dot(const float* a, const float* b, int64_t len, int slot) const {
     return launch_dot(a, b, len, B, op->sb.partial, sc(slot), st);
   }
+  // with the deferred step  xs += alpha p; p = s + beta p  (this iteration's alpha and beta
+  // slots) fused into the projection's first kernel when it can be, else run on its own first:
+  // y = A_vt p and slot = |y|^2
+  tomo_status step_project_norm(float* xs, float* p, const float* s, float* y, int vt,
+                                int slot) const {
+    if (!project_cg_supported(op)) {
+      TOMO_TRY(cg_step(xs, p, s, img));
+      return project_norm(p, y, vt, slot);
+    }
+    const CgStep cg{xs, s, sc(kAlpha), sc(kBeta)};
+    const int64_t nb = project_sumsq_blocks(op);
+    if (nb == 0 || nb > op->sb.norm_blocks) {
+      TOMO_TRY(apply_project_cg(op, p, cg, y, B, vt, st));
+      return dot(y, y, sino, slot);
+    }
+    TOMO_TRY(apply_project_cg(op, p, cg, y, B, vt, st, op->sb.norm_partial));
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.norm_partial, (int)nb, sc(slot));
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
   // y = A_vt x and slot = |y|^2, the squares summed by the projection's last kernel as it writes
   // y when it can (no separate pass over y), else by a dot product
   tomo_status project_norm(const float* x, float* y, int vt, int slot) const {
@@ -509,16 +529,22 @@ tomo_status cgls(const Ctx& c, const float* b, float* x, int vt, int iters, bool
   TOMO_TRY(c.backproject_norm(w.r, w.s, vt, cur));          // s = A^T r; gamma = |s|^2
   TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));     // p = s
   for (int it = 0; it < iters; ++it) {
-    TOMO_TRY(c.project_norm(w.p, w.q, vt, kDelta));         // q = A p; delta = |q|^2
+    if (it == 0) {
+      TOMO_TRY(c.project_norm(w.p, w.q, vt, kDelta));       // q = A p; delta = |q|^2
+    } else {
+      // the previous iteration's x += alpha p; p = s + beta p, then q = A p; delta = |q|^2
+      TOMO_TRY(c.step_project_norm(x, w.p, w.s, w.q, vt, kDelta));
+    }
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
     TOMO_HIP(hipGetLastError());
     // r -= alpha q; s = A^T r; gamma' = |s|^2
     TOMO_TRY(c.residual_backproject_norm(w.r, w.q, w.s, vt, nxt));
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.cg_step(x, w.p, w.s, c.img));             // x += alpha p; p = s + beta p
     std::swap(cur, nxt);
   }
+  // the last iteration's deferred solution update (its new direction is not needed)
+  if (iters > 0) TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));   // x += alpha p
   return TOMO_OK;
 }
 

@@ -103,7 +103,9 @@ def test_early_cgls_iterates_are_tight(tomo, fft):
     hand-written inverse transforms the squared norms |A p|^2 and |A^T r|^2 come from the
     transforms' own output passes; with rocFFT from separate dot products; and in the mixed
     settings one of each.  The residual update r -= alpha q rides in the channel-fastest adjoint
-    front (det_fft 1) or runs as its own pass (det_fft 0 or 2)."""
+    front (det_fft 1) or runs as its own pass (det_fft 0 or 2); the deferred step
+    x += alpha p, p = s + beta p rides in the hand-written forward grid transform (grid_fft 1) or
+    runs as its own pass (grid_fft 0)."""
     det, grid, B = fft
     n, nt, npb, iters = 64, 90, 91, 5
     ref = oracle_op(n, nt, npb)
