@@ -553,21 +553,25 @@ tomo_status ensure_normal(tomo_op* op, int filter) {
 
 // A^T D A x = crop(k*, 1/L) F2D^H W F2D embed(k* x), all on the channel-slowest grid buffers
 tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
-                         hipStream_t st) {
+                         hipStream_t st, const CgStep* cg, double* sumsq, const float* dotw) {
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
+  if (cg && !project_cg_supported(op))
+    return fail(TOMO_EINVAL, "internal: the fused CG step needs the hand-written grid transform");
+  if (sumsq && backproject_sumsq_blocks(op) == 0)
+    return fail(TOMO_EINVAL, "internal: output sums need the hand-written grid transform");
   TOMO_TRY(ensure_normal(op, filter));
   FFTPlans* p = nullptr;
   TOMO_TRY(get_plans(op, C, &p));
   const bool hand = op->tune.grid_fft && grid_fft_supported(op);
   if (hand) {
-    TOMO_TRY(launch_grid_forward(op, x, op->Xs, B, st));
+    TOMO_TRY(launch_grid_forward(op, x, op->Xs, B, st, cg));
   } else {
     TOMO_TRY(launch_embed(op, x, op->Xs, B, st));
     TOMO_TRY(fft_exec(p->fwd2, p, op->Xs, st));
   }
   TOMO_TRY(launch_normal_stencil(op, op->Xs, op->X, C, vt, filter, st));
-  if (hand) return launch_grid_inverse(op, op->X, out, B, 1.0f / (float)g.L, nullptr, st);
+  if (hand) return launch_grid_inverse(op, op->X, out, B, 1.0f / (float)g.L, sumsq, st, dotw);
   TOMO_TRY(fft_exec(p->inv2, p, op->X, st));
   TOMO_TRY(launch_crop_image(op, op->X, out, B, 1.0f / (float)g.L, st));
   return TOMO_OK;

@@ -165,13 +165,15 @@ __global__ __launch_bounds__(kFB) void k_cols(float2* __restrict__ Xs, DftTables
 }
 
 // With sumsq set, the block also sums the squares of the values it writes (float64), per slice:
-// sumsq[s * groups + j] for its group j of grid rows.
+// sumsq[s * groups + j] for its group j of grid rows; with dotw set as well, the products of the
+// values with dotw (same layout as x) instead of their squares.
 template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict__ Xs,
                                                        float* __restrict__ x,
                                                        const float* __restrict__ kd, DftTables t,
                                                        int B, int n, int on, float scale,
-                                                       double* __restrict__ sumsq) {
+                                                       double* __restrict__ sumsq,
+                                                       const float* __restrict__ dotw) {
   __shared__ float2 buf[lds_size<AG * M>()];
   const int G = BL ? t.N : M;
   const int groups = (G + AG - 1) / AG;
@@ -211,8 +213,13 @@ __global__ __launch_bounds__(kFB) void k_rows_inv_crop(const float2* __restrict_
     const float re = v.x * k, im = v.y * k;
     x[(int64_t)(2 * c) * plane + off] = re;
     if (odd) x[(int64_t)(2 * c + 1) * plane + off] = im;
-    s0 += (double)re * (double)re;
-    s1 += (double)im * (double)im;
+    if (dotw) {
+      s0 += (double)re * (double)dotw[(int64_t)(2 * c) * plane + off];
+      if (odd) s1 += (double)im * (double)dotw[(int64_t)(2 * c + 1) * plane + off];
+    } else {
+      s0 += (double)re * (double)re;
+      s1 += (double)im * (double)im;
+    }
   }
   if (sumsq) {
     block_sum2(s0, s1);
@@ -230,7 +237,8 @@ constexpr int kMaxCgStepM = 2048;
 
 template <int M, bool BL>
 tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
-                        int B, float scale, double* sumsq, const CgStep* cg, hipStream_t st) {
+                        int B, float scale, double* sumsq, const float* dotw, const CgStep* cg,
+                        hipStream_t st) {
   constexpr int AG = rows_per_block(M), W = cols_per_block<M>();
   const Geom& g = op->g;
   const int C = (B + 1) / 2;
@@ -259,7 +267,7 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
       break;
     case Step::RowsInvCrop:
       hipLaunchKernelGGL((k_rows_inv_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Xs, xout, op->kd_dev,
-                         t, B, g.n, g.on, scale, sumsq);
+                         t, B, g.n, g.on, scale, sumsq, sumsq ? dotw : nullptr);
       break;
   }
   TOMO_HIP(hipGetLastError());
@@ -267,12 +275,13 @@ tomo_status grid_launch(Step s, const tomo_op* op, const float* xin, float2* Xs,
 }
 
 tomo_status grid_dispatch(Step s, const tomo_op* op, const float* xin, float2* Xs, float* xout,
-                          int B, float scale, double* sumsq, const CgStep* cg, hipStream_t st) {
+                          int B, float scale, double* sumsq, const float* dotw, const CgStep* cg,
+                          hipStream_t st) {
   const bool bl = op->dft2.M != op->g.G;
 #define TOMO_GRID(M_)                                                                            \
   case M_:                                                                                      \
-    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, sumsq, cg, st)            \
-              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, sumsq, cg, st);
+    return bl ? grid_launch<M_, true>(s, op, xin, Xs, xout, B, scale, sumsq, dotw, cg, st)      \
+              : grid_launch<M_, false>(s, op, xin, Xs, xout, B, scale, sumsq, dotw, cg, st);
   switch (op->dft2.M) {
     TOMO_GRID(16) TOMO_GRID(32) TOMO_GRID(64) TOMO_GRID(128) TOMO_GRID(256) TOMO_GRID(512)
     TOMO_GRID(1024) TOMO_GRID(2048) TOMO_GRID(4096) TOMO_GRID(8192)
@@ -297,14 +306,14 @@ int64_t grid_inverse_blocks_per_channel(const tomo_op* op) {
 
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
                                 hipStream_t st, const CgStep* cg) {
-  TOMO_TRY(grid_dispatch(Step::RowsEmbed, op, x, Xs, nullptr, B, 1.f, nullptr, cg, st));
-  return grid_dispatch(Step::ColsFwd, op, nullptr, Xs, nullptr, B, 1.f, nullptr, nullptr, st);
+  TOMO_TRY(grid_dispatch(Step::RowsEmbed, op, x, Xs, nullptr, B, 1.f, nullptr, nullptr, cg, st));
+  return grid_dispatch(Step::ColsFwd, op, nullptr, Xs, nullptr, B, 1.f, nullptr, nullptr, nullptr, st);
 }
 
 tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
-                                double* sumsq, hipStream_t st) {
-  TOMO_TRY(grid_dispatch(Step::ColsInv, op, nullptr, Xs, nullptr, B, 1.f, nullptr, nullptr, st));
-  return grid_dispatch(Step::RowsInvCrop, op, nullptr, Xs, x, B, scale, sumsq, nullptr, st);
+                                double* sumsq, hipStream_t st, const float* dotw) {
+  TOMO_TRY(grid_dispatch(Step::ColsInv, op, nullptr, Xs, nullptr, B, 1.f, nullptr, nullptr, nullptr, st));
+  return grid_dispatch(Step::RowsInvCrop, op, nullptr, Xs, x, B, scale, sumsq, dotw, nullptr, st);
 }
 
 }  // namespace tomo

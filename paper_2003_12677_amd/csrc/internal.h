@@ -441,14 +441,18 @@ bool grid_cg_step_supported(const tomo_op* op);
 tomo_status launch_grid_forward(const tomo_op* op, const float* x, float2* Xs, int B,
                                 hipStream_t st, const CgStep* cg = nullptr);
 tomo_status launch_grid_inverse(const tomo_op* op, float2* Xs, float* x, int B, float scale,
-                                double* sumsq, hipStream_t st);
-// The output kernels of the inverse transforms can also sum the squares of what they write, per
-// slice, as float64 partial sums sumsq[s * blocks + j] (blocks per channel below; 0 when the
-// operator has no hand-written transform of that kind).
+                                double* sumsq, hipStream_t st, const float* dotw = nullptr);
+// The output kernels of the inverse transforms can also sum the squares of what they write (or,
+// for the grid, its products with dotw), per slice, as float64 partial sums sumsq[s * blocks + j]
+// (blocks per channel below; 0 when the operator has no hand-written transform of that kind).
 int64_t det_inverse_blocks_per_channel(const tomo_op* op);
 int64_t grid_inverse_blocks_per_channel(const tomo_op* op);
+// cg: the deferred CG step fused into the first kernel (x is then the direction p, updated in
+// place; project_cg_supported); sumsq: partial sums of out . dotw per slice ([B][blocks],
+// backproject_sumsq_blocks)
 tomo_status apply_normal(tomo_op* op, const float* x, float* out, int B, int vt, int filter,
-                         hipStream_t st);
+                         hipStream_t st, const CgStep* cg = nullptr, double* sumsq = nullptr,
+                         const float* dotw = nullptr);
 tomo_status normal_supported(const tomo_op* op);
 tomo_status launch_normal_stencil(const tomo_op* op, const float2* in, float2* out, int C, int vt,
                                   int filter, hipStream_t st);

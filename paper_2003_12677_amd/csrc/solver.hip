@@ -274,8 +274,12 @@ __global__ __launch_bounds__(256) void k_sb_rhs(const float* __restrict__ ATf,
 }
 
 // q = mu q + lam D^T D p   (q holds A^T A p on entry)
+// With partial set, each block also leaves the float64 sum of p . q (the new q) over its pixels
+// in partial[slice * gridDim.x + block].
 __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, float* __restrict__ q,
-                                                   float mu, float lam, int n) {
+                                                   float mu, float lam, int n,
+                                                   double* __restrict__ partial) {
+  double acc = 0.0;
   TOMO_SB_PIXELS
     const float c = p[i];
     // D p at (i1, i2), (i1-1, i2) [component 1] and (i1, i2-1) [component 2]
@@ -284,7 +288,13 @@ __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, 
     float v = -g1 - g2;
     if (i1 > 0) v += c - p[i - n];
     if (i2 > 0) v += c - p[i - 1];
-    q[i] = mu * q[i] + lam * v;
+    const float o = mu * q[i] + lam * v;
+    q[i] = o;
+    acc += (double)c * (double)o;
+  }
+  if (partial) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -292,9 +302,11 @@ __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, 
 // pixels and at the rows above and below, the left and right neighbours as single loads (the
 // one-pixel form issued five 4-byte loads and a division per pixel and ran at ~2.3 TB/s).
 __global__ __launch_bounds__(256) void k_sb_addlap4(const float* __restrict__ p, float* __restrict__ q,
-                                                    float mu, float lam, int n) {
+                                                    float mu, float lam, int n,
+                                                    double* __restrict__ partial) {
   const int64_t base = (int64_t)blockIdx.y * n * n;
   const int quads = n * n / 4;
+  double acc = 0.0;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < quads; t += gridDim.x * 256) {
     const int pix = 4 * t;
     const int i1 = pix / n, i2 = pix - i1 * n;
@@ -320,8 +332,13 @@ __global__ __launch_bounds__(256) void k_sb_addlap4(const float* __restrict__ p,
       v += cv[k] - uv[k];
       v += cv[k] - lv[k];
       o[k] = mu * qv[k] + lam * v;
+      acc += (double)cv[k] * (double)o[k];
     }
     *reinterpret_cast<float4*>(q + i) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+  if (partial) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -435,6 +452,25 @@ struct Ctx {
       return dot(y, y, sino, slot);
     }
     TOMO_TRY(apply_project_cg(op, p, cg, y, B, vt, st, op->sb.norm_partial));
+    hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.norm_partial, (int)nb, sc(slot));
+    TOMO_HIP(hipGetLastError());
+    return TOMO_OK;
+  }
+  // q = A_vt^T A_vt p through the normal-operator stencil and slot = p . q, the products summed
+  // by the last kernel as it writes q; with xs, the deferred step  xs += alpha p; p = s + beta p
+  // first, fused into the first kernel.  Each part falls back to its own pass where the
+  // hand-written transforms are off.
+  tomo_status normal_dot(float* xs, float* p, const float* s, float* q, int vt, int slot) const {
+    const bool fuse_step = xs && project_cg_supported(op);
+    if (xs && !fuse_step) TOMO_TRY(cg_step(xs, p, s, img));
+    const CgStep cg{xs, s, sc(kAlpha), sc(kBeta)};
+    const int64_t nb = backproject_sumsq_blocks(op);
+    if (nb == 0 || nb > op->sb.norm_blocks) {
+      TOMO_TRY(apply_normal(op, p, q, B, vt, TOMO_FILTER_NONE, st, fuse_step ? &cg : nullptr));
+      return dot(p, q, img, slot);
+    }
+    TOMO_TRY(apply_normal(op, p, q, B, vt, TOMO_FILTER_NONE, st, fuse_step ? &cg : nullptr,
+                          op->sb.norm_partial, p));
     hipLaunchKernelGGL(k_dot_final, dim3(B), dim3(256), 0, st, op->sb.norm_partial, (int)nb, sc(slot));
     TOMO_HIP(hipGetLastError());
     return TOMO_OK;
@@ -563,16 +599,17 @@ tomo_status cgnr(const Ctx& c, const float* b, float* x, int vt, int iters, bool
   int cur = kGamma0, nxt = kGamma1;
   TOMO_TRY(c.dot(w.s, w.s, c.img, cur));                                      // gamma = |r|^2
   for (int it = 0; it < iters; ++it) {
-    TOMO_TRY(apply_normal(c.op, w.p, w.t, c.B, vt, TOMO_FILTER_NONE, c.st));  // q = A^T A p
-    TOMO_TRY(c.dot(w.p, w.t, c.img, kDelta));                                 // delta = p.q
+    // (after the first iteration: x += alpha p; p = r + beta p) q = A^T A p; delta = p.q
+    TOMO_TRY(c.normal_dot(it == 0 ? nullptr : x, w.p, w.s, w.t, vt, kDelta));
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
     TOMO_HIP(hipGetLastError());
     TOMO_TRY(c.axpy_dot(w.s, w.t, c.img, nxt));          // r -= alpha q; gamma' = |r|^2
     hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
     TOMO_HIP(hipGetLastError());
-    TOMO_TRY(c.cg_step(x, w.p, w.s, c.img));             // x += alpha p; p = r + beta p
     std::swap(cur, nxt);
   }
+  // the last iteration's deferred solution update (its new direction is not needed)
+  if (iters > 0) TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));   // x += alpha p
   return TOMO_OK;
 }
 
@@ -594,20 +631,40 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
   clear_error();
   const int n = c.op->g.n;
   const dim3 grid(grid_for((int64_t)n * n), (unsigned)c.B);
-  // q = mu A^T A v + lam D^T D v
-  auto apply_M = [&](const float* v, float* q) -> tomo_status {
+  // q = mu A^T A v + lam D^T D v.  With step (CG iterations after the first), the deferred
+  // update x += alpha v; v = r + beta v comes first (fused into the forward transform's first
+  // kernel when it can be); with slot, slot = v . q, summed by the Laplacian kernel as it writes q.
+  auto apply_M = [&](float* v, float* q, bool step, int slot) -> tomo_status {
+    const bool fuse = step && project_cg_supported(c.op);
+    if (step && !fuse) TOMO_TRY(c.cg_step(x, v, w.s, c.img));
+    const CgStep cg{x, w.s, c.sc(kAlpha), c.sc(kBeta)};
     if (nrm) {
-      TOMO_TRY(apply_normal(c.op, v, q, c.B, vt, TOMO_FILTER_NONE, c.st));
+      TOMO_TRY(apply_normal(c.op, v, q, c.B, vt, TOMO_FILTER_NONE, c.st, fuse ? &cg : nullptr));
     } else {
-      TOMO_TRY(apply_project(c.op, v, w.q, c.B, vt, c.st));
+      if (fuse)
+        TOMO_TRY(apply_project_cg(c.op, v, cg, w.q, c.B, vt, c.st));
+      else
+        TOMO_TRY(apply_project(c.op, v, w.q, c.B, vt, c.st));
       TOMO_TRY(apply_backproject(c.op, w.q, q, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
     }
-    if (n % 4 == 0)
-      hipLaunchKernelGGL(k_sb_addlap4, dim3(grid_for((int64_t)n * n / 4), (unsigned)c.B), dim3(256),
-                         0, c.st, v, q, (float)mu, (float)lam, n);
-    else
-      hipLaunchKernelGGL(k_sb_addlap, grid, dim3(256), 0, c.st, v, q, (float)mu, (float)lam, n);
+    double* part = slot >= 0 ? w.partial : nullptr;
+    unsigned blocks;
+    if (n % 4 == 0) {
+      blocks = grid_for((int64_t)n * n / 4);
+      if (part) blocks = std::min<unsigned>(blocks, kDotBlocks);
+      hipLaunchKernelGGL(k_sb_addlap4, dim3(blocks, (unsigned)c.B), dim3(256), 0, c.st, v, q,
+                         (float)mu, (float)lam, n, part);
+    } else {
+      blocks = grid.x;
+      if (part) blocks = std::min<unsigned>(blocks, kDotBlocks);
+      hipLaunchKernelGGL(k_sb_addlap, dim3(blocks, (unsigned)c.B), dim3(256), 0, c.st, v, q,
+                         (float)mu, (float)lam, n, part);
+    }
     TOMO_HIP(hipGetLastError());
+    if (part) {
+      hipLaunchKernelGGL(k_dot_final, dim3(c.B), dim3(256), 0, c.st, part, (int)blocks, c.sc(slot));
+      TOMO_HIP(hipGetLastError());
+    }
     return TOMO_OK;
   };
   TOMO_TRY(apply_backproject(c.op, b, ATf, c.B, vt, TOMO_FILTER_NONE, 1.0f, c.st));
@@ -618,24 +675,23 @@ tomo_status tv_split_bregman(const Ctx& c, const float* b, float* x, int vt, int
                        (float)mu, (float)lam, n);
     TOMO_HIP(hipGetLastError());
     // CG on M x = rhs from the current x: r = rhs - M x, p = r
-    TOMO_TRY(apply_M(x, w.t));
+    TOMO_TRY(apply_M(x, w.t, false, -1));
     TOMO_TRY(c.lin(w.s, rhs, w.t, nullptr, nullptr, 1.0, -1.0, c.img));
     TOMO_TRY(c.lin(w.p, w.s, nullptr, nullptr, nullptr, 1.0, 0.0, c.img));
     int cur = kGamma0, nxt = kGamma1;
     TOMO_TRY(c.dot(w.s, w.s, c.img, cur));
     for (int it = 0; it < inner; ++it) {
-      TOMO_TRY(apply_M(w.p, w.t));                                             // q = M p
-      TOMO_TRY(c.dot(w.p, w.t, c.img, kDelta));
+      // (after the first iteration: x += alpha p; p = r + beta p) q = M p; delta = p . q
+      TOMO_TRY(apply_M(w.p, w.t, it > 0, kDelta));
       hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(cur), c.sc(kDelta), c.sc(kAlpha), c.B);
       TOMO_HIP(hipGetLastError());
-      TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));
-      TOMO_TRY(c.lin(w.s, w.s, w.t, nullptr, c.sc(kAlpha), 1.0, -1.0, c.img));
-      TOMO_TRY(c.dot(w.s, w.s, c.img, nxt));
+      TOMO_TRY(c.axpy_dot(w.s, w.t, c.img, nxt));            // r -= alpha q; gamma' = |r|^2
       hipLaunchKernelGGL(k_ratio, dim3(1), dim3(256), 0, c.st, c.sc(nxt), c.sc(cur), c.sc(kBeta), c.B);
       TOMO_HIP(hipGetLastError());
-      TOMO_TRY(c.lin(w.p, w.s, w.p, nullptr, c.sc(kBeta), 1.0, 1.0, c.img));
       std::swap(cur, nxt);
     }
+    // the last CG iteration's deferred solution update
+    if (inner > 0) TOMO_TRY(c.lin(x, x, w.p, nullptr, c.sc(kAlpha), 1.0, 1.0, c.img));
     hipLaunchKernelGGL(k_sb_shrink, grid, dim3(256), 0, c.st, x, d1, d2, e1, e2,
                        (float)(1.0 / lam), n);
     TOMO_HIP(hipGetLastError());

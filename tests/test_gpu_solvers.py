@@ -232,12 +232,15 @@ def test_bf16_refinement_matches_oracle(tomo):
     op.close()
 
 
-@pytest.mark.parametrize("geom", [(64, 90, 91, {}), (24, 20, 33, {"grid": 40})],
-                         ids=["normal_stencil", "project_backproject"])
+@pytest.mark.parametrize("geom", [(64, 90, 91, {}), (24, 20, 33, {"grid": 40}), (30, 24, 45, {})],
+                         ids=["normal_stencil", "project_backproject", "odd_side"])
 def test_tv_split_bregman_matches_oracle(tomo, geom):
     """Split-Bregman TV (Sec. 3.1): 4 Bregman steps of 6 CG steps each, against the float64
     oracle with the same parameters; the first geometry applies A^T A through the normal-operator
-    stencil, the second (grid > n_det) through project + backproject.
+    stencil, the second (grid > n_det) through project + backproject, the third has a side that
+    is not a multiple of 4 (the one-pixel Laplacian kernel).  The CG steps take p . q from the
+    Laplacian kernel and their direction / solution update from the forward transform's first
+    kernel.
 
     The bound comes from float32 oracle realisations at the operator parity tolerance (1e-5 per
     application), as for the long refinement solves: the inner CG runs down to residuals where
