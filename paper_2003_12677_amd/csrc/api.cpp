@@ -115,8 +115,12 @@ tomo_status upload_adj(tomo_op* op) {
 
 void free_tiles(tomo_op* op) {
   DevFwdTiles& f = op->ftile;
-  dfree(f.wi_tile); dfree(f.wi_beg); dfree(f.pt_row); dfree(f.pt_base);
-  for (auto& v : f.val) dfree(v);
+  dfree(f.wi_tile); dfree(f.wi_beg);
+  for (int k = 0; k < 2; ++k) {
+    dfree(f.pt_row[k]);
+    dfree(f.pt_base[k]);
+    for (auto& v : f.val[k]) dfree(v);
+  }
   f = DevFwdTiles();
   DevAdjWin& a = op->awin;
   dfree(a.wi_tile); dfree(a.wi_q); dfree(a.wi_boff); dfree(a.q_row);
@@ -132,17 +136,19 @@ void free_tiles(tomo_op* op) {
 tomo_status upload_tiles(tomo_op* op) {
   op->tiles_ready = false;
   free_tiles(op);
-  {
+  for (int k = 0; k < 2; ++k) {   // row order, then the FFT-side form's angle-radius order
     HostFwdTiles h;
-    TOMO_TRY(build_fwd_tiles(op->g, op->sdag, op->centres, op->tune, &h));
+    TOMO_TRY(build_fwd_tiles(op->g, op->sdag, op->centres, op->tune, &h, k == 1));
     DevFwdTiles& d = op->ftile;
-    d.n_wi = (int64_t)h.wi_tile.size();
-    d.TS = h.TS; d.PS = h.PS; d.NT = h.NT; d.KW = h.KW;
-    TOMO_TRY(upload(&d.wi_tile, h.wi_tile.data(), h.wi_tile.size()));
-    TOMO_TRY(upload(&d.wi_beg, h.wi_beg.data(), h.wi_beg.size()));
-    TOMO_TRY(upload(&d.pt_row, h.pt_row.data(), h.pt_row.size()));
-    TOMO_TRY(upload(&d.pt_base, h.pt_base.data(), h.pt_base.size()));
-    TOMO_TRY(upload_values(h.pt_val, op->g.values, d.val));
+    if (k == 0) {
+      d.n_wi = (int64_t)h.wi_tile.size();
+      d.TS = h.TS; d.PS = h.PS; d.NT = h.NT; d.KW = h.KW;
+      TOMO_TRY(upload(&d.wi_tile, h.wi_tile.data(), h.wi_tile.size()));
+      TOMO_TRY(upload(&d.wi_beg, h.wi_beg.data(), h.wi_beg.size()));
+    }
+    TOMO_TRY(upload(&d.pt_row[k], h.pt_row.data(), h.pt_row.size()));
+    TOMO_TRY(upload(&d.pt_base[k], h.pt_base.data(), h.pt_base.size()));
+    TOMO_TRY(upload_values(h.pt_val, op->g.values, d.val[k]));
   }
   {
     HostAdjWin h;

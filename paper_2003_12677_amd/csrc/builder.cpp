@@ -369,7 +369,7 @@ std::vector<int> tile_order(int NT, int strip) {
 }  // namespace
 
 tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
-                            const Tuning& t, HostFwdTiles* o) {
+                            const Tuning& t, HostFwdTiles* o, bool slowest_order) {
   *o = HostFwdTiles();
   const int G = g.G, oG = G / 2, TS = t.tile, h = g.h, kw = g.kw;
   o->TS = TS;
@@ -400,14 +400,19 @@ tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vecto
   for (int i = 0; i < ntiles; ++i) count[i + 1] += count[i];
   std::vector<int32_t> order(N);
   {
-    // within a tile, samples by angle, then radius (rows visited as a * L + kf), so that a work
-    // item's outputs form runs of consecutive radii in the channel-slowest polar layout
     std::vector<int64_t> next(count.begin(), count.end() - 1);
-    for (int a = 0; a < g.nt; ++a)
-      for (int64_t kf = 0; kf < g.L; ++kf) {
-        const int64_t r = kf * g.nt + a;
-        order[next[rank_of_row[r]]++] = (int32_t)r;
-      }
+    if (slowest_order) {
+      // within a tile, samples by angle, then radius, so that a work item's outputs form runs of
+      // consecutive radii in the channel-slowest polar layout
+      for (int a = 0; a < g.nt; ++a)
+        for (int64_t kf = 0; kf < g.L; ++kf) {
+          const int64_t r = kf * g.nt + a;
+          order[next[rank_of_row[r]]++] = (int32_t)r;
+        }
+    } else {
+      // row order: neighbouring samples write neighbouring rows of the channel-fastest layout
+      for (int64_t r = 0; r < N; ++r) order[next[rank_of_row[r]]++] = (int32_t)r;
+    }
   }
   o->pt_row = order;
   o->pt_base.assign((size_t)N, 0);
@@ -635,9 +640,9 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
     replay_rows(h, out);
     worst = std::max(worst, rel(out, xa));
   }
-  {  // staged forward
+  for (const bool slowest : {false, true}) {  // staged forward, both sample orders
     HostFwdTiles f;
-    TOMO_TRY(build_fwd_tiles(g, sdag, centres, t, &f));
+    TOMO_TRY(build_fwd_tiles(g, sdag, centres, t, &f, slowest));
     std::vector<double> out(N, std::nan(""));
     for (size_t w = 0; w < f.wi_tile.size(); ++w) {
       const int tl = f.wi_tile[w];

@@ -158,8 +158,11 @@ struct HostAdjWin {
 tomo_status resolve_geometry(const tomo_geometry* in, Geom* g);
 double kernel_value(double t, int W, double beta);
 void build_sdag(const Geom& g, HostCSR* sdag, std::vector<int32_t>* centres = nullptr);
+// Samples within a tile in polar row order (kf * nt + a: the channel-fastest output's rows
+// adjacent), or, with slowest_order, by angle then radius (runs of consecutive radii in the
+// channel-slowest rows); the work items (wi_tile, wi_beg) are the same in both.
 tomo_status build_fwd_tiles(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
-                            const Tuning& t, HostFwdTiles* out);
+                            const Tuning& t, HostFwdTiles* out, bool slowest_order = false);
 tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<int32_t>& centres,
                           const Tuning& t, HostAdjWin* out);
 void transpose_csr(const HostCSR& a, HostCSR* at);
@@ -208,9 +211,12 @@ struct DevAdj {
 struct DevFwdTiles {
   int64_t n_wi = 0;
   int TS = 0, PS = 0, NT = 0, KW = 0;
-  int32_t *wi_tile = nullptr, *wi_beg = nullptr, *pt_row = nullptr;
-  int32_t* pt_base = nullptr;
-  void* val[3] = {nullptr, nullptr, nullptr};
+  int32_t *wi_tile = nullptr, *wi_beg = nullptr;
+  // [0]: samples in row order (channel-fastest output); [1]: by angle, then radius (the
+  // channel-slowest output of the FFT-side form)
+  int32_t* pt_row[2] = {nullptr, nullptr};
+  int32_t* pt_base[2] = {nullptr, nullptr};
+  void* val[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
 };
 
 struct DevAdjWin {

@@ -115,7 +115,7 @@ constexpr int window_stride() { return (KW * KW + 3) / 4 * 4; }   // LDS floats 
 // One forward work item wi (channels c0 .. c0 + 8*CPL - 1) of a block; smem holds the patch, the
 // values and the sample records.  MAXP: the most samples a work item may hold (a compile-time
 // bound, so that the staging loops issue only the loads a block of that capacity can need).
-template <int CPL, typename V, int KW, int PS, int MAXP>
+template <int CPL, typename V, int KW, int PS, int MAXP, bool SLOW>
 __device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __restrict__ val,
                                               int wi, int c0, float2* smem) {
   constexpr int CH = kLanes * CPL, W2 = KW * KW, WP = window_stride<KW>(), H = KW / 2;
@@ -144,7 +144,7 @@ __device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __r
     bs = a.pt_base[b0 + threadIdx.x];
   }
   constexpr int NB = NPL < kStageBatch ? NPL : kStageBatch;
-  if (a.plane == 0) {
+  if constexpr (!SLOW) {
     for (int base = 0; base < NPL; base += NB) {
       Vec<CPL> x[NB];
 #pragma unroll
@@ -217,7 +217,7 @@ __device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __r
 #pragma unroll
           for (int k = 0; k < 2 * CPL; ++k) acc.v[k] += ws * x.v[k];
         }
-      if (a.yplane == 0) {
+      if constexpr (!SLOW) {
         vstore<CPL>(a.Y + (int64_t)s_row[i] * a.C + c0 + cl, acc);
       } else {
         // channel-slowest polar rows: sample (kf, a) at a*L + kf of every channel plane; the
@@ -233,11 +233,13 @@ __device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __r
   }
 }
 
-template <int CPL, typename V, int KW, int PS, int MAXP>
+// SLOW: the FFT-side layouts (X channel-slowest, Y channel-slowest rows) instead of the
+// channel-fastest ones
+template <int CPL, typename V, int KW, int PS, int MAXP, bool SLOW>
 __global__ __launch_bounds__(kBlock) void k_fwd_tile(FwdTileArgs a, const V* __restrict__ val) {
   extern __shared__ float2 smem[];
-  fwd_tile_body<CPL, V, KW, PS, MAXP>(a, val, (int)xcd_remap(blockIdx.x, gridDim.x),
-                                      blockIdx.y * kLanes * CPL, smem);
+  fwd_tile_body<CPL, V, KW, PS, MAXP, SLOW>(a, val, (int)xcd_remap(blockIdx.x, gridDim.x),
+                                            blockIdx.y * kLanes * CPL, smem);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -624,9 +626,9 @@ __global__ __launch_bounds__(kBlock) void k_stack_fwd(const StackFwdItem* __rest
     const StackFwdItem& it = items[e.x];
     const int wi = e.y / it.n_cc, cc = e.y % it.n_cc;
     if (it.cpl == 2)
-      fwd_tile_body<2, V, KW, PS, MAXP>(it.a, (const V*)it.val, wi, cc * kLanes * 2, smem);
+      fwd_tile_body<2, V, KW, PS, MAXP, false>(it.a, (const V*)it.val, wi, cc * kLanes * 2, smem);
     else
-      fwd_tile_body<1, V, KW, PS, MAXP>(it.a, (const V*)it.val, wi, cc * kLanes, smem);
+      fwd_tile_body<1, V, KW, PS, MAXP, false>(it.a, (const V*)it.val, wi, cc * kLanes, smem);
     __syncthreads();                                   // LDS is reused by the next entry
   }
 }
@@ -680,27 +682,33 @@ tomo_status fwd_tile_impl(const tomo_op* op, int vt, const float2* X, float2* Y,
                           hipStream_t st) {
   const DevFwdTiles& d = op->ftile;
   constexpr int CH = kLanes * CPL;
-  FwdTileArgs a{d.wi_tile, d.wi_beg, d.pt_row, d.pt_base, X, Y,
+  FwdTileArgs a{d.wi_tile, d.wi_beg, d.pt_row[slow], d.pt_base[slow], X, Y,
                 C, op->g.G, op->g.G / 2, d.TS, d.NT, op->tune.tile_points,
                 slow ? (int64_t)op->g.G * op->g.G : 0, slow ? (int64_t)op->g.nt * op->g.L : 0,
                 op->g.nt, op->g.L};
   const size_t lds = fwd_tile_lds_bytes(op, C);
   dim3 grid((unsigned)d.n_wi, (unsigned)((C + CH - 1) / CH));
-  const V* v = (const V*)d.val[vt];
+  const V* v = (const V*)d.val[slow][vt];
   const bool small = op->tune.tile_points <= 64;
+#define TOMO_FWD_TILE_S(KW_, PS_, MAXP_)                                                          \
+  if (slow)                                                                                     \
+    hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_, MAXP_, true>), grid, dim3(kBlock), lds, st, a, v); \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_, MAXP_, false>), grid, dim3(kBlock), lds, st, a, v);
 #define TOMO_FWD_TILE(KW_, TS_)                                                                  \
   if (d.KW == KW_ && d.TS == TS_) {                                                             \
     constexpr int PS_ = TS_ + 2 * (KW_ / 2) + 1;                                                \
-    if (small)                                                                                  \
-      hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_, 64>), grid, dim3(kBlock), lds, st, a, v); \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_fwd_tile<CPL, V, KW_, PS_, kMaxTilePoints>), grid, dim3(kBlock), lds, \
-                         st, a, v);                                                             \
+    if (small) {                                                                                \
+      TOMO_FWD_TILE_S(KW_, PS_, 64)                                                             \
+    } else {                                                                                    \
+      TOMO_FWD_TILE_S(KW_, PS_, kMaxTilePoints)                                                 \
+    }                                                                                           \
     TOMO_HIP(hipGetLastError());                                                                \
     return TOMO_OK;                                                                             \
   }
   TOMO_FWD_TILE(3, 8) TOMO_FWD_TILE(3, 16) TOMO_FWD_TILE(5, 8) TOMO_FWD_TILE(5, 16)
 #undef TOMO_FWD_TILE
+#undef TOMO_FWD_TILE_S
   return fail(TOMO_EUNSUPPORTED, "staged forward kernel has no variant for k_w %d, tile %d", d.KW,
               d.TS);
 }
@@ -988,10 +996,10 @@ tomo_status stack_plan_create(const StackItemSpec* items, int n, int vt, StackPl
     p->adj_big = p->adj_big || d.QMAX > 128;
     p->lds_f = std::max(p->lds_f, fwd_tile_lds_bytes(op, C));
     p->lds_a = std::max(p->lds_a, adj_seg_lds_bytes(op, C));
-    FwdTileArgs fa{f.wi_tile, f.wi_beg, f.pt_row, f.pt_base, (const float2*)items[i].in,
+    FwdTileArgs fa{f.wi_tile, f.wi_beg, f.pt_row[0], f.pt_base[0], (const float2*)items[i].in,
                    (float2*)items[i].out, C, op->g.G, op->g.G / 2, f.TS, f.NT, op->tune.tile_points, 0, 0,
                    op->g.nt, op->g.L};
-    fi.push_back(StackFwdItem{fa, f.val[vt], cpl, n_cc});
+    fi.push_back(StackFwdItem{fa, f.val[0][vt], cpl, n_cc});
     for (int64_t w = 0; w < f.n_wi; ++w)
       for (int cc = 0; cc < n_cc; ++cc) wf.push_back(make_int2(i, (int)(w * n_cc + cc)));
     float2* part = nullptr;
