@@ -258,12 +258,13 @@ struct AdjWinArgs {
 };
 
 // Store the CPL channels ch0 .. of grid cell `cell`: one 8*CPL-byte store into the channel-
-// fastest grid, or one float2 per channel plane of the channel-slowest grid (the 8 cells of a
-// tile row, held by neighbouring lane groups, then form one 64-byte run per plane).
-template <int CPL>
+// fastest grid, or (SLOW) one float2 per channel plane of the channel-slowest grid (the 8 cells
+// of a tile row, held by neighbouring lane groups, then form one 64-byte run per plane).  The
+// layout is a compile-time choice, so that the channel-fastest kernels are scheduled on their own.
+template <int CPL, bool SLOW>
 __device__ __forceinline__ void store_cell(float2* X, int64_t cell, int C, int ch0, int64_t plane,
                                            const Vec<CPL>& v) {
-  if (plane == 0) {
+  if constexpr (!SLOW) {
     vstore<CPL>(X + cell * C + ch0, v);
   } else {
 #pragma unroll
@@ -451,7 +452,7 @@ __device__ __forceinline__ void adj_cell_f64(double (&tot)[2 * CPL], const float
 // One block per staged tile, placed by an XCD-aware remap so that neighbouring tiles share an
 // L2.  The block loads its list offsets, then its sample rows, values and bucket offsets, then
 // the rows of Y those samples name.
-template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP, bool SLOW>
 __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __restrict__ val) {
   using S = AdjShape<KW, TS>;
   constexpr int CH = kLanes * CPL;
@@ -476,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __res
     Vec<CPL> acc;
     vzero(acc);
     adj_cell<CPL, KW, TS>(acc, sy, sv, sb, m1, m2, cl);
-    store_cell<CPL>(a.X, (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G), a.C, c0 + cl, a.plane, acc);
+    store_cell<CPL, SLOW>(a.X, (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G), a.C, c0 + cl, a.plane, acc);
   }
 }
 
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_win(AdjWinArgs a, const V* __res
 // its tile is split over several segments; sums run over chunks in order (run-to-run identical).
 // (Loading the next chunk while summing the current one needs a second register set; at 106
 // VGPRs that halved the blocks per CU and was slower.)
-template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP, bool SLOW>
 __device__ __forceinline__ void adj_seg_body(const AdjSegArgs& s, const V* __restrict__ val, int sg,
                                              int c0, float2* smem) {
   using S = AdjShape<KW, TS>;
@@ -544,7 +545,7 @@ __device__ __forceinline__ void adj_seg_body(const AdjSegArgs& s, const V* __res
         } else {
           const int j1 = jb1 + c / TS, j2 = jb2 + c % TS;
           if (j1 <= a.G - 1 - a.oG && j2 <= a.G - 1 - a.oG)   // else past the grid's end
-            store_cell<CPL>(a.X, (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G), a.C, c0 + cl, a.plane,
+            store_cell<CPL, SLOW>(a.X, (int64_t)wrap(j1, a.G) * a.G + wrap(j2, a.G), a.C, c0 + cl, a.plane,
                             out);
         }
       }
@@ -557,13 +558,13 @@ __device__ __forceinline__ void adj_seg_body(const AdjSegArgs& s, const V* __res
   }
 }
 
-template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP>
+template <int CPL, typename V, int KW, int TS, bool SCALE, int MAXP, bool SLOW>
 __global__ __launch_bounds__(kBlock) void k_adj_seg(AdjSegArgs s, const V* __restrict__ val) {
   extern __shared__ float2 smem[];
   const int b = blockIdx.x;
   const int sg = (b < s.n_first) ? s.seg0 + b
                                  : s.seg1 + (int)xcd_remap(b - s.n_first, gridDim.x - s.n_first);
-  adj_seg_body<CPL, V, KW, TS, SCALE, MAXP>(s, val, sg, blockIdx.y * kLanes * CPL, smem);
+  adj_seg_body<CPL, V, KW, TS, SCALE, MAXP, SLOW>(s, val, sg, blockIdx.y * kLanes * CPL, smem);
 }
 
 // Split dense tiles: block i sums partial tiles red_slot[i] .. red_slot[i+1]-1 in order into tile
@@ -643,9 +644,9 @@ __global__ __launch_bounds__(kBlock) void k_stack_adj(const StackAdjItem* __rest
     const StackAdjItem& it = items[e.x];
     const int sg = e.y / it.n_cc, cc = e.y % it.n_cc;
     if (it.cpl == 2)
-      adj_seg_body<2, V, KW, TS, false, MAXP>(it.s, (const V*)it.val, sg, cc * kLanes * 2, smem);
+      adj_seg_body<2, V, KW, TS, false, MAXP, false>(it.s, (const V*)it.val, sg, cc * kLanes * 2, smem);
     else
-      adj_seg_body<1, V, KW, TS, false, MAXP>(it.s, (const V*)it.val, sg, cc * kLanes, smem);
+      adj_seg_body<1, V, KW, TS, false, MAXP, false>(it.s, (const V*)it.val, sg, cc * kLanes, smem);
     __syncthreads();
   }
 }
@@ -726,10 +727,14 @@ tomo_status adj_tile_impl(const tomo_op* op, int vt, const float2* Y, float2* X,
   const V* v = (const V*)d.q_val[vt];
   const bool small = d.QMAX <= 128;
 #define TOMO_ADJ_WIN_P(KW_, TS_, P_)                                                             \
-  if (dscale)                                                                                   \
-    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, true, P_>), grid, dim3(kBlock), lds, st, a, v); \
+  if (dscale && slow)                                                                           \
+    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, true, P_, true>), grid, dim3(kBlock), lds, st, a, v); \
+  else if (dscale)                                                                              \
+    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, true, P_, false>), grid, dim3(kBlock), lds, st, a, v); \
+  else if (slow)                                                                                \
+    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, false, P_, true>), grid, dim3(kBlock), lds, st, a, v); \
   else                                                                                          \
-    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, false, P_>), grid, dim3(kBlock), lds, st, a, v);
+    hipLaunchKernelGGL((k_adj_win<CPL, V, KW_, TS_, false, P_, false>), grid, dim3(kBlock), lds, st, a, v);
 #define TOMO_ADJ_WIN(KW_, TS_)                                                                   \
   if (d.KW == KW_ && d.TS == TS_) {                                                             \
     if (small) {                                                                                \
@@ -766,10 +771,14 @@ tomo_status adj_seg_impl(const tomo_op* op, int vt, const float2* Y, float2* X, 
   const V* v = (const V*)d.q_val[vt];
   const bool small = d.QMAX <= 128;
 #define TOMO_ADJ_SEG_P(KW_, TS_, P_)                                                             \
-  if (dscale)                                                                                   \
-    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, true, P_>), grid, dim3(kBlock), lds, st, a, v); \
+  if (dscale && slow)                                                                           \
+    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, true, P_, true>), grid, dim3(kBlock), lds, st, a, v); \
+  else if (dscale)                                                                              \
+    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, true, P_, false>), grid, dim3(kBlock), lds, st, a, v); \
+  else if (slow)                                                                                \
+    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, false, P_, true>), grid, dim3(kBlock), lds, st, a, v); \
   else                                                                                          \
-    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, false, P_>), grid, dim3(kBlock), lds, st, a, v);
+    hipLaunchKernelGGL((k_adj_seg<CPL, V, KW_, TS_, false, P_, false>), grid, dim3(kBlock), lds, st, a, v);
 #define TOMO_ADJ_SEG(KW_, TS_)                                                                   \
   if (d.KW == KW_ && d.TS == TS_) {                                                             \
     if (small) {                                                                                \
