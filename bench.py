@@ -475,16 +475,14 @@ def uneven_leg(torch, tomo):
     res.update(steps=len(steps), eager_ms=ms_e, graph_ms=ms_g,
                eager_slices_per_s=200 / (ms_e * 1e-3), graph_slices_per_s=200 / (ms_g * 1e-3))
     # the same SpMM pairs as one persistent forward and one persistent adjoint launch over every
-    # operator's staged work (the stack needs the dense tiles staged: adj_dense_mode >= 1)
+    # operator's staged work
     ops = []
     for st in steps:
         if st["op"] not in ops:
             ops.append(st["op"])
-    # one kernel per operator set needs one tile side for all (8, the default) and the dense tiles
-    # staged (adj_dense_mode >= 1)
+    # one kernel per operator set needs one tile side for all (8, the default)
     for op in ops:
-        tun = op.get_tuning()
-        op.set_tuning(tile=8, adj_dense_mode=max(1, tun["adj_dense_mode"]))
+        op.set_tuning(tile=8)
     stack = tomo.Stack([dict(op=st["op"], batch=st["batch"], inp=st["inp"], out=st["out"], aux=st["aux"])
                         for st in steps], values="f16")
     stack.launch()

@@ -121,7 +121,7 @@ typedef struct {
 /* Kernel layout parameters of the two SpMMs: the search space of an autotuner.
  * Staged kernels are used when their LDS footprint fits 64 KiB (and for k_w 3 or 5), else the
  * row kernels.
- * Defaults (in field order): 2, 4, 64, 4096, 256, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32, 1, 8, 1. */
+ * Defaults (in field order): 2, 4, 64, 4096, 256, 1024, 7, 7, 8, 64, 128, 1, 8192, 1024, 2, 1, 1, 1, 32, 0, 8, 1. */
 typedef struct {
   int32_t fwd_channels_per_lane;  /* complex channels per lane in the forward SpMM: 1, 2 or 4
                                      (reduced automatically when it does not divide C)        */
@@ -173,14 +173,18 @@ typedef struct {
                                      in the XCD's L2 (0 = row-major over the whole grid); results
                                      do not depend on it; 0..4096                              */
   int32_t adj_dense_mode;         /* staged adjoint, tiles whose region holds more than
-                                     adj_tile_points samples (near the Fourier origin): 0 = the
-                                     row kernels on their cells (on two more streams); 1 = staged
-                                     too, in chunks of <= adj_tile_points samples, one block per
-                                     segment of <= adj_seg_chunks chunks accumulating in
-                                     registers (a tile with several segments is summed from
-                                     partial tiles in a fixed order), on a second stream beside
-                                     the other tiles; 2 = the same segments and the other tiles
-                                     in one launch, the dense segments first                  */
+                                     adj_tile_points samples (near the Fourier origin), in the
+                                     channel-fastest entry points: 0 = the row kernels on their
+                                     cells (on two more streams); 1 = staged too, in chunks of
+                                     <= adj_tile_points samples, one block per segment of
+                                     <= adj_seg_chunks chunks accumulating in registers (a tile
+                                     with several segments is summed from partial tiles in a
+                                     fixed order), on a second stream beside the other tiles;
+                                     2 = the same segments and the other tiles in one launch, the
+                                     dense segments first.  Backproject (which writes the FFT
+                                     side's channel-slowest grid) and stacks always use the
+                                     segments (1 for 0), and so do channel counts the row
+                                     kernels cannot take (odd, above 64)                      */
   int32_t adj_seg_chunks;         /* chunks per segment of a dense tile (1..256)             */
   int32_t adj_run;                /* adj_dense_mode 2: the other staged tiles go to blocks in runs
                                      of this many tiles (in the visiting order), each block
@@ -406,13 +410,13 @@ void tomo_graph_destroy(tomo_graph* g);
  * so a launch may be captured in a HIP graph.  Results equal the items' own tomo_slice_fwd /
  * tomo_slice_adj with the staged kernels, up to float32 summation order.
  * Requirements: operators on one device, one kernel width and tile side, the staged layouts
- * (k_w 3 or 5, tile 8 or 16) with adj_dense_mode 1 or 2, value type `values` built for every
+ * (k_w 3 or 5, tile 8 or 16), value type `values` built for every
  * operator.  Buffers as tomo_slice_fwd / tomo_slice_adj (in: [G*G][C], out: [L*nt][C],
  * aux: [G*G][C] complex64, C = ceil(batch/2), 16-byte aligned); the stack holds the pointers, so
  * they and the operators must stay alive (and not be re-tuned) while it is used.  Launches of one
  * stack, and calls on its operators, must not overlap.  tomo_stack_create allocates the work
  * lists and each item's partial tiles (synchronous).
- * Errors: TOMO_EINVAL (bad item, mixed devices / kernel widths / tiles, adj_dense_mode 0),
+ * Errors: TOMO_EINVAL (bad item, mixed devices / kernel widths / tiles),
  * TOMO_ESTATE, TOMO_EUNSUPPORTED (no staged layout), TOMO_ENOMEM, TOMO_EHIP. */
 typedef struct {
   tomo_op* op;

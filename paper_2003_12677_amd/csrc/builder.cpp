@@ -525,10 +525,9 @@ tomo_status build_adj_win(const Geom& g, const HostCSR& sdag, const std::vector<
     tile_samples(t1, t2, &rows, &bo);
     const int64_t nq = (int64_t)rows.size();
     if (nq > o->QMAX) {
-      if (t.adj_dense_mode != 0) {
-        dense_tiles.push_back(tl);
-        continue;
-      }
+      // a dense tile: chunked segments (the FFT-side form, and adj_dense_mode 1 / 2), and its
+      // cells marked for the row kernels (adj_dense_mode 0)
+      dense_tiles.push_back(tl);
       for (int a = 0; a < TS; ++a)
         for (int b = 0; b < TS; ++b) {
           const int j1 = -oG + t1 * TS + a, j2 = -oG + t2 * TS + b;
@@ -726,9 +725,10 @@ tomo_status check_layouts(const Geom& g, const HostCSR& sdag, const HostCSR& s,
         for (int c = 0; c < T2; ++c) acc[(size_t)c] += slots[(size_t)sl][(size_t)c];
       store_tile(a.red_tile[i], acc);
     }
+    worst = std::max(worst, rel(out, xa));   // every cell from the segments
     HostAdj hd;
     build_adj_layout(s, t, &hd, &a.dense_cell);
-    replay_rows(hd, out);
+    replay_rows(hd, out);                     // the dense cells from the row kernels instead
     worst = std::max(worst, rel(out, xa));
   }
   *max_rel = worst;   // NaN if some output row was never written

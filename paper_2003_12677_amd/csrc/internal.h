@@ -84,7 +84,7 @@ struct Tuning {
   // per segment of <= adj_seg_chunks chunks (split tiles summed from partial tiles in a fixed
   // order), on a second stream beside the staged tiles; 2 = the same segments and the staged
   // tiles in one launch, dense segments first
-  int adj_dense_mode = 1;
+  int adj_dense_mode = 0;
   int adj_seg_chunks = 8;
   // in the one-launch form (adj_dense_mode 2): staged tiles per block, visited in order with the
   // next tile's loads in flight while the current one is summed
@@ -142,7 +142,9 @@ struct HostAdjWin {
   std::vector<int32_t> q_row;              // polar row of each tile sample
   std::vector<double> q_val;               // [Q][W2] window-ordered values
   std::vector<char> dense_cell;            // [M] library cell index -> 1 if in a dense tile
-  // Dense tiles staged in chunks (adj_dense_mode != 0).  Chunks extend the work-item arrays:
+  // Dense tiles staged in chunks (always built: the FFT-side form and adj_dense_mode 1 / 2 use
+  // them, the channel-fastest form with adj_dense_mode 0 the row kernels).  Chunks extend the
+  // work-item arrays:
   // chunk c >= n_wi covers samples [wi_q[c], wi_q[c+1]) with bucket offsets wi_boff[c] (relative
   // to wi_q[c]).  Segment s covers chunks [seg_chunk[s], seg_chunk[s+1]) of tile seg_tile[s];
   // segments 0 .. n_wi-1 are the staged tiles (one chunk each), the rest the dense tiles.  A

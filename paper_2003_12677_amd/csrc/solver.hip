@@ -298,47 +298,76 @@ __global__ __launch_bounds__(256) void k_sb_addlap(const float* __restrict__ p, 
   }
 }
 
-// The same for n % 4 == 0, four pixels of one row per thread: 16-byte loads of p and q at the
+// One quad (4 pixels of a row) of k_sb_addlap4.  Every neighbour load is issued unconditionally,
+// with its offset clamped at the slice's edges so that it reads the centre pixel there (whose
+// difference is then zero, as the one-pixel form's zero differences past the edges).
+struct Quad {
+  float4 c, qq, up, dn;
+  float lf, rt;
+};
+
+__device__ __forceinline__ void quad_load(const float* __restrict__ p, const float* __restrict__ q,
+                                          int64_t base, int t, int n, Quad& d) {
+  const int pix = 4 * t;
+  const int i1 = pix / n, i2 = pix - i1 * n;
+  const int64_t i = base + pix;
+  d.c = *reinterpret_cast<const float4*>(p + i);
+  d.qq = *reinterpret_cast<const float4*>(q + i);
+  d.dn = *reinterpret_cast<const float4*>(p + i + ((i1 < n - 1) ? n : 0));
+  d.up = *reinterpret_cast<const float4*>(p + i - ((i1 > 0) ? n : 0));
+  d.lf = p[i - ((i2 > 0) ? 1 : 0)];
+  d.rt = p[i + ((i2 + 4 < n) ? 4 : 3)];
+}
+
+__device__ __forceinline__ void quad_store(float* __restrict__ q, int64_t base, int t,
+                                           const Quad& d, float mu, float lam, double& acc) {
+  // -(D1 p)(i) + (D1 p)(i - row) = (up - c) + (dn - c) with zero differences past the edges;
+  // the same along the row with the left / right neighbours
+  const float cv[4] = {d.c.x, d.c.y, d.c.z, d.c.w};
+  const float uv[4] = {d.up.x, d.up.y, d.up.z, d.up.w};
+  const float dv[4] = {d.dn.x, d.dn.y, d.dn.z, d.dn.w};
+  const float lv[4] = {d.lf, d.c.x, d.c.y, d.c.z};
+  const float rv[4] = {d.c.y, d.c.z, d.c.w, d.rt};
+  const float qv[4] = {d.qq.x, d.qq.y, d.qq.z, d.qq.w};
+  float o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float v = -(dv[k] - cv[k]) - (rv[k] - cv[k]);   // the one-pixel form's order of operations
+    v += cv[k] - uv[k];
+    v += cv[k] - lv[k];
+    o[k] = mu * qv[k] + lam * v;
+    acc += (double)cv[k] * (double)o[k];
+  }
+  *reinterpret_cast<float4*>(q + base + 4 * t) = make_float4(o[0], o[1], o[2], o[3]);
+}
+
+// The same for n % 4 == 0, four pixels of one row per quad: 16-byte loads of p and q at the
 // pixels and at the rows above and below, the left and right neighbours as single loads (the
-// one-pixel form issued five 4-byte loads and a division per pixel and ran at ~2.3 TB/s).
+// one-pixel form issued five 4-byte loads and a division per pixel and ran at ~2.3 TB/s).  A
+// thread issues the loads of four quads before computing any of them.
 __global__ __launch_bounds__(256) void k_sb_addlap4(const float* __restrict__ p, float* __restrict__ q,
                                                     float mu, float lam, int n,
                                                     double* __restrict__ partial) {
   const int64_t base = (int64_t)blockIdx.y * n * n;
   const int quads = n * n / 4;
+  const int stride = gridDim.x * 256;
   double acc = 0.0;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < quads; t += gridDim.x * 256) {
-    const int pix = 4 * t;
-    const int i1 = pix / n, i2 = pix - i1 * n;
-    const int64_t i = base + pix;
-    const float4 c = *reinterpret_cast<const float4*>(p + i);
-    const float4 qq = *reinterpret_cast<const float4*>(q + i);
-    const float4 dn = (i1 < n - 1) ? *reinterpret_cast<const float4*>(p + i + n) : c;
-    const float4 up = (i1 > 0) ? *reinterpret_cast<const float4*>(p + i - n) : c;
-    const float lf = (i2 > 0) ? p[i - 1] : c.x;
-    const float rt = (i2 + 4 < n) ? p[i + 4] : c.w;
-    // -(D1 p)(i) + (D1 p)(i - row) = (up - c) + (dn - c) with zero differences past the edges;
-    // the same along the row with the left / right neighbours
-    const float cv[4] = {c.x, c.y, c.z, c.w};
-    const float uv[4] = {up.x, up.y, up.z, up.w};
-    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
-    const float lv[4] = {lf, c.x, c.y, c.z};
-    const float rv[4] = {c.y, c.z, c.w, rt};
-    const float qv[4] = {qq.x, qq.y, qq.z, qq.w};
-    float o[4];
+  int t = blockIdx.x * 256 + threadIdx.x;
+  for (; t + 3 * stride < quads; t += 4 * stride) {
+    Quad d[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      float v = -(dv[k] - cv[k]) - (rv[k] - cv[k]);   // the one-pixel form's order of operations
-      v += cv[k] - uv[k];
-      v += cv[k] - lv[k];
-      o[k] = mu * qv[k] + lam * v;
-      acc += (double)cv[k] * (double)o[k];
-    }
-    *reinterpret_cast<float4*>(q + i) = make_float4(o[0], o[1], o[2], o[3]);
+    for (int u = 0; u < 4; ++u) quad_load(p, q, base, t + u * stride, n, d[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) quad_store(q, base, t + u * stride, d[u], mu, lam, acc);
+  }
+  for (; t < quads; t += stride) {
+    Quad d;
+    quad_load(p, q, base, t, n, d);
+    quad_store(q, base, t, d, mu, lam, acc);
   }
   if (partial) {
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = b;
   }
 }
 

@@ -551,8 +551,7 @@ tomo_status adj_cpl(const tomo_op* op, const DevAdj& d, int vt, const float2* Y,
     case 4: return adj_impl<4, V>(op, d, vt, Y, X, C, dscale, st);
     default:
       return fail(TOMO_EUNSUPPORTED, "the row kernels take at most 64 lane groups: odd channel "
-                  "counts above 64 (%d) need the staged adjoint with staged dense tiles "
-                  "(adj_tiled, adj_dense_mode 1 or 2)", C);
+                  "counts above 64 (%d) need the staged adjoint (adj_tiled)", C);
   }
 }
 
@@ -567,8 +566,7 @@ bool spmm_fwd_slowest_ok(const tomo_op* op, int C, int vt) {
 
 bool spmm_adj_slowest_ok(const tomo_op* op, int C, int vt) {
   return vt >= 0 && vt <= 2 && op->adj_ready && ((op->tune.adj_tiled >> vt) & 1) &&
-         op->tiles_ready && adj_tile_supported(op) && adj_seg_lds_bytes(op, C) <= kMaxTileLds &&
-         op->tune.adj_dense_mode != 0;
+         op->tiles_ready && adj_tile_supported(op) && adj_seg_lds_bytes(op, C) <= kMaxTileLds;
 }
 
 tomo_status launch_spmm_fwd(const tomo_op* op, const float2* X, float2* Y, int C, int vt,
@@ -598,7 +596,11 @@ tomo_status launch_spmm_adj(const tomo_op* op, const float2* Y, float2* X, int C
       default: return adj_cpl<_Float16>(op, d, vt, Y, X, C, dscale, s);
     }
   };
-  if (spmm_adj_slowest_ok(op, C, vt)) {
+  // the dense tiles' segments: for the FFT-side output (the row kernels write only the channel-
+  // fastest grid), for channel counts the row kernels cannot take, and when adj_dense_mode
+  // selects them
+  if (spmm_adj_slowest_ok(op, C, vt) &&
+      (slow || op->tune.adj_dense_mode != 0 || pick_cpl(op->tune.adj_cpl, C) == 0)) {
     if (op->tune.adj_dense_mode == 2)
       return launch_adj_seg(op, Y, X, C, vt, dscale, true, true, slow, st);
     // the dense tiles' segments on a second stream beside the staged tiles (disjoint cells)

@@ -38,9 +38,6 @@ tomo_status tomo_stack_create(const tomo_stack_item* items, int32_t n, int32_t v
       return fail(TOMO_EINVAL, "item %d needs a 16-byte aligned aux buffer", i);
     if (!it.op->tiles_ready || !fwd_tile_supported(it.op) || !adj_tile_supported(it.op))
       return fail(TOMO_EUNSUPPORTED, "item %d: the staged layouts are not available", i);
-    if (it.op->tune.adj_dense_mode == 0)
-      return fail(TOMO_EINVAL, "item %d: the operator's adjoint keeps its dense tiles on the row "
-                  "kernels (tuning adj_dense_mode 0); stacks need them staged (1 or 2)", i);
     spec.push_back(StackItemSpec{it.op, it.batch, it.in, it.out, it.aux});
   }
   DeviceGuard guard(device);

@@ -226,7 +226,8 @@ def test_operators_with_each_adjoint_form(tomo, shape, dense, vt):
 
 def test_odd_channel_count_above_64(tomo):
     """133 slices (67 complex channels, odd, above the row kernels' 64 lane groups) run through the
-    staged kernels, which split channels over blocks; the row kernels refuse such a batch."""
+    staged kernels, which split channels over blocks (the dense tiles in segments, whatever
+    adj_dense_mode selects); with the staged adjoint off, the row kernels refuse such a batch."""
     n, nt, npb, B = 16, 12, 23, 133
     op = tomo.Operator(n, nt, npb, max_batch=B, device=0)
     ref = oracle_op(n, nt, npb)
@@ -237,7 +238,18 @@ def test_odd_channel_count_above_64(tomo):
     for s in (0, 1, 64, 131, 132):
         assert rel_l2(yg[s], ref.project(x[s].astype(np.float32).astype(np.float64))) < TOL, s
         assert rel_l2(xg[s], ref.backproject(y[s].astype(np.float32).astype(np.float64))) < TOL, s
+    # the channel-fastest adjoint: with adj_dense_mode 0 it falls back to the segments of mode 1
+    Yc = torch.randn(op.polar_shape(B), device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    outs = {}
+    for mode in (0, 1, 2):
+        op.set_tuning(adj_dense_mode=mode)
+        outs[mode] = op.slice_adj(Yc, B).clone()
+    assert torch.equal(outs[0], outs[1])
+    assert (outs[2] - outs[1]).abs().max().item() <= 1e-5 * outs[1].abs().max().item()
     op.set_tuning(adj_dense_mode=0)
+    xg0 = _host(op.backproject(_dev(y)))
+    assert rel_l2(xg0[132], ref.backproject(y[132].astype(np.float32).astype(np.float64))) < TOL
+    op.set_tuning(adj_tiled=0)
     with pytest.raises(tomo.TomoError, match="EUNSUPPORTED"):
         op.backproject(_dev(y))
     op.close()
