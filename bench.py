@@ -436,6 +436,7 @@ def uneven_leg(torch, tomo):
         if count == 0:
             continue
         nt, npb = round(0.75 * n), round(n * math.sqrt(2))
+        print(f"uneven: building and tuning the {n}^2 operator", file=sys.stderr, flush=True)
         op = tomo.Operator(n, nt, npb, max_batch=BATCH, values=("f16",), device=0)
         tune = op.autotune(BATCH, values="f16")
         gen = torch.Generator(device=dev)
@@ -459,6 +460,8 @@ def uneven_leg(torch, tomo):
                                            "adj_sell_xcd_rows", "adj_medium_xcd_rows",
                                            "adj_dense_mode", "adj_seg_chunks", "adj_run")},
                                  "tuned_ms_b32": [tune["fwd_ms"], tune["adj_ms"]]})
+
+    print("uneven: timing eager launches, the graph and the stack", file=sys.stderr, flush=True)
 
     def run_eager():
         for op, b, Xc, Yp, Xa in eager:
