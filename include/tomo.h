@@ -95,7 +95,10 @@ typedef struct {
   double beta;           /* Kaiser-Bessel shape; NaN -> Beatty et al. (2005) rule with
                             oversampling G / n                                             */
   double center;         /* rotation-axis bin c; NaN -> floor(n_det / 2) (Sec. 3, c = n_p/2).
-                            Non-integer c returns TOMO_EUNSUPPORTED.                      */
+                            c = c0 + f: the integer part c0 shifts the bins, a fractional
+                            part f multiplies polar frequency k by exp(-2 pi i k f / L)
+                            before the inverse detector DFT (and its conjugate after the
+                            forward one), k signed in [-L/2, L/2)                          */
   const double* angles;  /* host array [n_angles] of radians, or NULL -> a * pi / n_angles */
 } tomo_geometry;
 
@@ -228,8 +231,7 @@ typedef struct {
  * operator (no HIP call is made; only tomo_op_info and tomo_export_* work on it).
  * The device that is current on entry is current again on return.
  * On success *out owns all device memory; free it with tomo_destroy_operator.
- * Errors: TOMO_EINVAL (geometry), TOMO_EUNSUPPORTED (non-integer center),
- * TOMO_ENOMEM, TOMO_EHIP; *out is left NULL. */
+ * Errors: TOMO_EINVAL (geometry), TOMO_ENOMEM, TOMO_EHIP; *out is left NULL. */
 tomo_status tomo_build_operator(const tomo_geometry* g, int device, tomo_op** out);
 
 /* Forward projection y = A x (Eq. (2), first line) for `batch` slices.

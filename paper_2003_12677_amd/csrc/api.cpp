@@ -212,6 +212,7 @@ void free_device(tomo_op* op) {
   for (auto& v : op->fwd.val) dfree(v);
   free_adj(op);
   dfree(op->kd_dev);
+  dfree(op->phase_dev);
   for (auto* t : {&op->dft1, &op->dft2}) {
     dfree(t->tw);
     dfree(t->chirp);
@@ -320,6 +321,16 @@ tomo_status upload_all(tomo_op* op) {
   TOMO_TRY(upload_tiles(op));
   std::vector<float> kdf(op->kd.begin(), op->kd.end());
   TOMO_TRY(upload(&op->kd_dev, kdf.data(), kdf.size()));
+  if (g.cfrac != 0.0) {
+    // exp(-2 pi i k f / L) in float64, k the signed frequency of FFT-ordered index kf
+    std::vector<float2> ph((size_t)g.L);
+    for (int kf = 0; kf < g.L; ++kf) {
+      const int k = kf < g.L - g.L / 2 ? kf : kf - g.L;
+      const double a = -2.0 * M_PI * (double)k * g.cfrac / (double)g.L;
+      ph[(size_t)kf] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    TOMO_TRY(upload(&op->phase_dev, ph.data(), ph.size()));
+  }
   for (int f = TOMO_FILTER_RAMLAK; f <= TOMO_FILTER_HAMMING; ++f) {
     std::vector<double> d;
     filter_diagonal(g, f, &d);
@@ -398,6 +409,8 @@ tomo_status project_from_grid(tomo_op* op, float* y, int B, int vt, FFTPlans* p,
   }
   if (op->tune.det_fft && det_fft_supported(op))
     return launch_det_inverse_crop(op, op->Ys, y, B, 1.0f / (float)g.L, sumsq, st);
+  if (op->phase_dev)
+    TOMO_TRY(launch_phase_rows(op->Ys, op->phase_dev, g.L, (int64_t)C * g.nt, false, st));
   TOMO_TRY(fft_exec(p->inv1, p, op->Ys, st));
   TOMO_TRY(launch_crop_sino(op, op->Ys, y, B, 1.0f / (float)g.L, st));
   return TOMO_OK;
@@ -484,6 +497,8 @@ tomo_status apply_backproject(tomo_op* op, const float* y, float* x, int B, int 
     } else {
       TOMO_TRY(launch_pad_sino(op, y, op->Ys, B, st));
       TOMO_TRY(fft_exec(p->fwd1, p, op->Ys, st));
+      if (op->phase_dev)
+        TOMO_TRY(launch_phase_rows(op->Ys, op->phase_dev, g.L, (int64_t)C * g.nt, true, st));
     }
     TOMO_TRY(launch_polar_to_fastest(op->Ys, op->Y, g.L, g.nt, C, st));
   }

@@ -103,9 +103,12 @@ tomo_status resolve_geometry(const tomo_geometry* in, Geom* g) {
   if (!(r.beta > 0) || !std::isfinite(r.beta)) return fail(TOMO_EINVAL, "beta must be positive");
   r.center = std::isnan(in->center) ? (double)(r.np / 2) : in->center;
   if (!std::isfinite(r.center)) return fail(TOMO_EINVAL, "center must be finite");
-  if (r.center != std::floor(r.center))
-    return fail(TOMO_EUNSUPPORTED, "non-integer rotation-axis bin %g is not supported", r.center);
-  r.cdet = (int)mod_pos((int64_t)r.center, r.L);
+  // c = c0 + f: the integer part shifts the detector bins, the fractional part is a phase ramp
+  // on the polar rows (Sec. 3)
+  const double c0 = std::floor(r.center);
+  if (std::fabs(c0) > 1e9) return fail(TOMO_EINVAL, "center %g out of range", r.center);
+  r.cdet = (int)mod_pos((int64_t)c0, r.L);
+  r.cfrac = r.center - c0;
   r.jmax = (r.G + 1) / 2 - 1;
   r.on = r.n / 2;
   r.theta.resize(r.nt);

@@ -45,7 +45,8 @@ template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restrict__ Ys,
                                                           float* __restrict__ y, DftTables t,
                                                           int B, int nt, int np, int cdet, float scale,
-                                                          double* __restrict__ sumsq) {
+                                                          double* __restrict__ sumsq,
+                                                          const float2* __restrict__ phase) {
   __shared__ float2 buf[lds_size<AG * M>()];
   const int L = BL ? t.N : M;
   const int agroups = (nt + AG - 1) / AG;
@@ -65,6 +66,8 @@ __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restri
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int i = threadIdx.x + u * kFB;
+      // a fractional axis bin: the polar row's phase ramp before the inverse DFT
+      if (phase && i < AG * M && i % M < L) v[u] = cmul(v[u], phase[i % M]);
       if (i < AG * M) buf[lds(i)] = v[u];
     }
   }
@@ -100,7 +103,8 @@ __global__ __launch_bounds__(kFB) void k_det_inverse_crop(const float2* __restri
 template <int M, int AG, bool BL>
 __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict__ y,
                                                          float2* __restrict__ Ys, DftTables t,
-                                                         int B, int nt, int np, int cdet) {
+                                                         int B, int nt, int np, int cdet,
+                                                         const float2* __restrict__ phase) {
   __shared__ float2 buf[lds_size<AG * M>()];
   const int L = BL ? t.N : M;
   const int agroups = (nt + AG - 1) / AG;
@@ -132,7 +136,11 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward(const float* __restrict
   __syncthreads();
   dft_lds<M, AG, false, BL>(buf, t);
   float2* dst = Ys + ((int64_t)c * nt + a0) * L;
-  for (int i = threadIdx.x; i < na * L; i += kFB) dst[i] = buf[lds((i / L) * M + i % L)];
+  for (int i = threadIdx.x; i < na * L; i += kFB) {
+    float2 w = buf[lds((i / L) * M + i % L)];
+    if (phase) w = cmul(w, conj2(phase[i % L]));   // a fractional axis bin's phase ramp
+    dst[i] = w;
+  }
 }
 
 // Rows (angles) per block of the channel-slowest kernels: about 32 KB of LDS, so that four blocks
@@ -155,7 +163,8 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* y, floa
                                                             const float* __restrict__ qv,
                                                             const double* __restrict__ alpha,
                                                             float2* __restrict__ Yf, DftTables t,
-                                                            int B, int nt, int np, int cdet) {
+                                                            int B, int nt, int np, int cdet,
+                                                            const float2* __restrict__ phase) {
   constexpr int PAD = row_skew<M>();
   __shared__ float2 buf[lds_rows_size<CW, M, PAD>()];
   const int L = BL ? t.N : M;
@@ -220,7 +229,9 @@ __global__ __launch_bounds__(kFB) void k_det_pad_forward_cf(const float* y, floa
   dft_lds<M, CW, false, BL, PAD>(buf, t);
   for (int i = threadIdx.x; i < L * nc; i += kFB) {
     const int k = i / nc, q = i % nc;
-    Yf[((int64_t)k * nt + a) * C + c0 + q] = buf[ldsr<M, PAD>(q, k)];
+    float2 w = buf[ldsr<M, PAD>(q, k)];
+    if (phase) w = cmul(w, conj2(phase[k]));       // a fractional axis bin's phase ramp
+    Yf[((int64_t)k * nt + a) * C + c0 + q] = w;
   }
 }
 
@@ -236,13 +247,14 @@ tomo_status det_launch(bool inverse, bool fastest, const tomo_op* op, const floa
   const dim3 cfgrid((unsigned)(g.nt * ((C + CW - 1) / CW)));
   if (inverse)
     hipLaunchKernelGGL((k_det_inverse_crop<M, AG, BL>), grid, dim3(kFB), 0, st, Ysin, yout, op->dft1,
-                       B, g.nt, g.np, g.cdet, scale, sumsq);
+                       B, g.nt, g.np, g.cdet, scale, sumsq, op->phase_dev);
   else if (fastest)
     hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL, false>), cfgrid, dim3(kFB), 0, st, yin,
-                       nullptr, nullptr, nullptr, Ysout, op->dft1, B, g.nt, g.np, g.cdet);
+                       nullptr, nullptr, nullptr, Ysout, op->dft1, B, g.nt, g.np, g.cdet,
+                       op->phase_dev);
   else
     hipLaunchKernelGGL((k_det_pad_forward<M, AG, BL>), grid, dim3(kFB), 0, st, yin, Ysout, op->dft1,
-                       B, g.nt, g.np, g.cdet);
+                       B, g.nt, g.np, g.cdet, op->phase_dev);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }
@@ -270,7 +282,7 @@ tomo_status det_residual_launch(const tomo_op* op, float* r, const float* q, con
   const int C = (B + 1) / 2;
   const dim3 grid((unsigned)(op->g.nt * ((C + CW - 1) / CW)));
   hipLaunchKernelGGL((k_det_pad_forward_cf<M, CW, BL, true>), grid, dim3(kFB), 0, st, r, r, q, alpha,
-                     Yf, op->dft1, B, op->g.nt, op->g.np, op->g.cdet);
+                     Yf, op->dft1, B, op->g.nt, op->g.np, op->g.cdet, op->phase_dev);
   TOMO_HIP(hipGetLastError());
   return TOMO_OK;
 }

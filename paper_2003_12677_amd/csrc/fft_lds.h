@@ -68,6 +68,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
   }
 }
 
+__device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

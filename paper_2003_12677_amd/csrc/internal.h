@@ -41,7 +41,8 @@ struct Geom {
   int n = 0, nt = 0, np = 0, G = 0, L = 0, kw = 3, h = 1, max_batch = 0;
   int jmax = 0;            // kept band |j| <= jmax = ceil(G/2) - 1
   int on = 0;              // image origin pixel n/2
-  int cdet = 0;            // integer rotation-axis bin
+  int cdet = 0;            // integer part of the rotation-axis bin, mod L
+  double cfrac = 0;        // its fractional part, in [0, 1): a phase ramp on the polar rows
   double beta = 0, center = 0;
   uint32_t values = TOMO_VALUES_F32;
   std::vector<double> theta;
@@ -273,6 +274,11 @@ struct tomo_op {
   tomo::DevEll fwd;
   tomo::DevAdj adj;
   float* kd_dev = nullptr;        // [n]
+  // polar-row phase of a fractional rotation-axis bin c0 + f: phase[kf] = exp(-2 pi i k f / L)
+  // for the signed frequency k of FFT-ordered radial index kf (project multiplies by it before
+  // the inverse detector DFT, backproject by its conjugate after the forward one); null when
+  // f == 0
+  float2* phase_dev = nullptr;    // [L]
   // tables of the hand-written DFTs: detector length L and grid side G (twiddles of the length M
   // held in LDS; chirp and convolution kernels when M is the Bluestein length of L or G)
   tomo::fftk::DftTables dft1, dft2;
@@ -339,6 +345,9 @@ tomo_status launch_to_channel_slowest(const float2* src, float2* dst, int64_t P,
 // polar: Yf[kf][a][C] <-> Ys[C][a][kf]
 tomo_status launch_polar_to_slowest(const float2* Yf, float2* Ys, int L, int nt, int C, hipStream_t st);
 tomo_status launch_polar_to_fastest(const float2* Ys, float2* Yf, int L, int nt, int C, hipStream_t st);
+// Ys[r][kf] *= phase[kf] (conj: its conjugate) for rows r < rows of length L
+tomo_status launch_phase_rows(float2* Ys, const float2* phase, int L, int64_t rows, bool conj,
+                              hipStream_t st);
 // `slow` (only when spmm_fwd_slowest_ok / spmm_adj_slowest_ok): the Cartesian grid is the
 // channel-slowest [C][G][G] FFT-side buffer, read or written by the staged kernels directly, and
 // the forward writes the channel-slowest polar rows [C][nt][L]

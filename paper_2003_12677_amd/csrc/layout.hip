@@ -168,9 +168,32 @@ __global__ __launch_bounds__(256) void k_polar_to_fastest(const float2* __restri
   }
 }
 
+// Ys[r][kf] *= phase[kf] (or its conjugate), rows of length L: a fractional rotation-axis bin's
+// phase ramp on the library-FFT path
+__global__ __launch_bounds__(256) void k_phase_rows(float2* __restrict__ Ys,
+                                                    const float2* __restrict__ phase, int L,
+                                                    int64_t total, bool conj) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    float2 p = phase[i % L];
+    if (conj) p.y = -p.y;
+    const float2 v = Ys[i];
+    Ys[i] = make_float2(v.x * p.x - v.y * p.y, v.x * p.y + v.y * p.x);
+  }
+}
+
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
+
+tomo_status launch_phase_rows(float2* Ys, const float2* phase, int L, int64_t rows, bool conj,
+                              hipStream_t st) {
+  const int64_t total = rows * L;
+  hipLaunchKernelGGL(k_phase_rows, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65535)),
+                     dim3(256), 0, st, Ys, phase, L, total, conj);
+  TOMO_HIP(hipGetLastError());
+  return TOMO_OK;
+}
 
 tomo_status launch_scale_rows(float2* Y, const float* w, int64_t P, int C, hipStream_t st) {
   const int64_t total = P * C;

@@ -19,6 +19,9 @@ from tests.gpu_util import krylov_tolerance, noisy_fp32, oracle_op, r32, rel_l2
 pytestmark = pytest.mark.gpu
 
 GEOMS = [(64, 90, 91, 3), (37, 30, 53, 3), (16, 12, 16, 3), (32, 24, 45, 5)]
+# a fractional rotation axis: its phase ramp is unitary on the polar rows, so A^T D A keeps the
+# stencil form (the oracle applies the ramp in project and backproject)
+CENTERED = [(64, 90, 91, 3, 44.6), (37, 30, 53, 3, 25.25)]
 
 
 def _dev(a):
@@ -47,6 +50,20 @@ def test_normal_matches_oracle(tomo, geom, B, tiled):
         eh = rel_l2(got_h[s], normal(ref, x[s], D))
         print(f"{geom} B={B} slice {s}: A^T A {e:.2e}, A^T D A {eh:.2e}")
         assert e <= 1e-5 and eh <= 1e-5
+    op.close()
+
+
+@pytest.mark.parametrize("geom", CENTERED, ids=lambda g: "x".join(map(str, g)))
+def test_normal_fractional_axis_matches_oracle(tomo, geom):
+    n, nt, npb, kw, c = geom
+    op = tomo.Operator(n, nt, npb, kw=kw, max_batch=3, center=c, device=0)
+    ref = oracle_op(n, nt, npb, kw=kw, center=c)
+    x = r32(np.random.default_rng(17).uniform(0, 1, (3, n, n)))
+    got = _host(op.normal(_dev(x)))
+    for s in range(3):
+        e = rel_l2(got[s], normal(ref, x[s]))
+        print(f"{geom} slice {s}: A^T A with a fractional axis {e:.2e}")
+        assert e <= 1e-5
     op.close()
 
 

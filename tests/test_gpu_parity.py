@@ -22,6 +22,7 @@ SHAPES = [
     (16, 12, 16, {}),
     (12, 10, 16, {"grid": 20}),
     (16, 9, 23, {"center": 10.0}),
+    (16, 9, 23, {"center": 11.3}),         # fractional axis (the oracle's phase-ramp reading)
     (64, 90, 91, {}),
     (9, 7, 13, {"kw": 5}),
 ]
@@ -118,6 +119,7 @@ POW2_SHAPES = [
     (16, 12, 16, {}),
     (32, 24, 64, {}),
     (24, 20, 32, {"center": 10.0}),
+    (24, 20, 32, {"center": 10.3}),        # fractional axis: a phase ramp on the polar rows
     (12, 10, 16, {"grid": 32}),            # zero-padded detector: crop / pad of L to n_p
     (40, 30, 64, {"kw": 5}),
     (100, 60, 256, {}),
@@ -130,6 +132,7 @@ POW2_SHAPES = [
 NONPOW2_SHAPES = [
     (64, 90, 91, {}),
     (17, 11, 23, {"center": 9.0}),
+    (17, 11, 23, {"center": 8.4}),         # fractional axis through Bluestein transforms
     (24, 20, 33, {"grid": 40}),
     (30, 17, 45, {"kw": 5}),
     (200, 16, 283, {}),                    # prime length
