@@ -1,6 +1,7 @@
 // Normal operator A^T A (or A^T D A) in the reduced form that Sec. 4 proposes as the Toeplitz
-// approach: with as many detector bins as polar samples per angle and an integer rotation axis,
-// the 1D inverse transform followed by its adjoint is 1/L times the identity, so
+// approach: with as many detector bins as polar samples per angle, the crop (a circular shift by
+// the axis bin's integer part) is a bijection and a fractional part's phase ramp is unitary, so
+// the 1D inverse transform followed by its adjoint is 1/L times the identity, and
 //     A^T D A x = (1/L) k* . F2D^H W F2D (k* . x),   W = S diag(D) S^dagger.
 // W connects Cartesian frequencies that share a polar sample: a fixed (2R+1)^2 stencil with
 // per-point weights (R = kw - 1), stored as values only (no column indices).
