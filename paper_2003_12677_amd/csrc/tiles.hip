@@ -200,8 +200,13 @@ __device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __r
     s_base[threadIdx.x] = bs;
   }
   __syncthreads();
-  const int g = threadIdx.x / kLanes;
-  const int cl = (threadIdx.x % kLanes) * CPL;
+  // lane groups: 8 neighbouring lanes share a sample and split its channels (the channel-
+  // fastest output row is one 8*CH-byte run); for the channel-slowest output, 32 neighbouring
+  // lanes take 32 consecutive samples of one channel group instead, so that a store covers
+  // runs of consecutive radii of each channel plane (measured: project 1.160 -> 1.141 ms at
+  // 2048^2 x 32)
+  const int g = SLOW ? (int)threadIdx.x % kGroups : (int)threadIdx.x / kLanes;
+  const int cl = (SLOW ? (int)threadIdx.x / kGroups : (int)threadIdx.x % kLanes) * CPL;
   if (cl < nch) {
     for (int i = g; i < ns; i += kGroups) {
       const float2* p = patch + s_base[i] * CH + cl;
@@ -221,8 +226,8 @@ __device__ __forceinline__ void fwd_tile_body(const FwdTileArgs& a, const V* __r
         vstore<CPL>(a.Y + (int64_t)s_row[i] * a.C + c0 + cl, acc);
       } else {
         // channel-slowest polar rows: sample (kf, a) at a*L + kf of every channel plane; the
-        // samples of a tile are ordered by angle, then radius, so neighbouring lane groups write
-        // runs of consecutive radii
+        // samples of a tile are ordered by angle, then radius, so neighbouring lanes write runs
+        // of consecutive radii
         const int r = s_row[i], kf = r / a.nt;
         const int64_t at = (int64_t)(r - kf * a.nt) * a.L + kf;
 #pragma unroll
