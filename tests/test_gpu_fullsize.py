@@ -15,13 +15,14 @@ configuration (one batch of 32 slices = 16 complex channels).
 * The composed operators on four sampled slices (two complex channels): relative L2 and the
   largest element error against the largest reference element, both within 1e-5.
 * CGLS (Sec. 3.1) in the benchmark's batch: its first iterates against the oracle's float64
-  CGLS on the same float32 sinograms, in every slice position of the batch."""
+  CGLS on the same float32 sinograms, in every slice position of the batch; likewise the first
+  steps of the mixed-precision refinement (float32 residuals, bf16-value inner CGLS)."""
 
 import numpy as np
 import pytest
 import torch
 
-from oracle import cgls, round_values
+from oracle import Operator as OracleOperator, cgls, refine, round_values
 from synth import phantom_stack
 from tests.gpu_util import cart_map, oracle_op, polar_row_map, r32, rel_l2, summation_bound_check
 
@@ -146,3 +147,44 @@ def test_fullsize_cgls_first_iterates(big, ref):
         print(f"sinogram {k}: CGLS-{iters} rel L2 against the oracle, worst over 16 slice positions "
               f"{max(errs):.2e}")
         assert max(errs) < 2e-5
+
+
+def test_fullsize_bf16_refinement_first_steps(big, ref):
+    """The mixed-precision solve at the benchmark's size, two outer steps of three inner CGLS
+    iterations: outer residuals with float32 values, inner solves with bf16 values, against the
+    oracle's float64 refinement with the same rounded values (bf16 values convert to float32
+    exactly, so each GPU application differs from the oracle's only by float32 summation).
+
+    * The first outer step is CGLS-3 with bf16 values: within 2e-5, as the CGLS iterates above.
+    * The second step starts from the first one's image x1 and is far more sensitive to an error
+      of x1 along the constant image (the DC coefficient, where the float32 sums of thousands of
+      same-sign terms near the Fourier origin leave most of the kernels' error) than along a
+      generic direction: the residual b - A x1 is a tenth of b, and a DC error of x1 moves its
+      low frequencies a hundredfold more.  The oracle measures that amplification A itself, from
+      a constant perturbation of its own x1 (measured ~130, against ~1 for a random one).  The
+      bound is 2 A e1 + 2e-5, with e1 the first step's measured error; measured 8-10e-5."""
+    R, I = 2, 3
+    hi32 = OracleOperator(ref.geom, S=round_values(ref.S, "f32"))
+    lo = OracleOperator(ref.geom, S=round_values(ref.S, "bf16"))
+    x = phantom_stack(N, 2, seed_base=3200, supersample=1)
+    b2 = [r32(ref.project(v.astype(np.float64))) for v in x]
+    bd = torch.from_numpy(np.ascontiguousarray(np.stack([b2[s % 2] for s in range(B)]), dtype=np.float32)).cuda()
+    xg1 = big.solve(bd, iters=I, refine_outer=1, values="bf16")
+    xg2 = big.solve(bd, iters=I, refine_outer=R, values="bf16")
+    torch.cuda.synchronize()
+    xg1 = xg1.cpu().numpy().astype(np.float64)
+    xg2 = xg2.cpu().numpy().astype(np.float64)
+    for k in range(2):
+        x1 = refine(hi32.project, lo.project, lo.backproject, b2[k], 1, I)
+        x2 = refine(hi32.project, lo.project, lo.backproject, b2[k], R, I)
+        e1 = max(rel_l2(xg1[s], x1) for s in range(k, B, 2))
+        eps = 1e-6
+        xp = x1 + np.full_like(x1, eps * np.linalg.norm(x1) / x1.shape[0])
+        x2p = xp + cgls(lo.project, lo.backproject, b2[k] - hi32.project(xp), I)
+        amp = rel_l2(x2p, x2) / eps
+        e2 = max(rel_l2(xg2[s], x2) for s in range(k, B, 2))
+        bound = 2.0 * amp * e1 + 2e-5
+        print(f"sinogram {k}: refinement first step {e1:.2e}; {R}x{I} (bf16 inner) {e2:.2e}, bound "
+              f"{bound:.2e} (oracle's DC amplification {amp:.0f})")
+        assert e1 < 2e-5
+        assert e2 < bound
