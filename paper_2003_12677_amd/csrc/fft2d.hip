@@ -32,11 +32,13 @@ constexpr int rows_per_block(int M) {
   return M >= 8192 ? 1 : (M >= 2048 ? 2 : (4096 / M > 16 ? 16 : 4096 / M));
 }
 
-// columns per column block: 4 adjacent columns (32-byte runs of a row) while they fit 64 KB
-// (measured at G = 2048: 2 columns with twice the blocks per CU took 510 us, 4 columns 410 us)
+// columns per column block: adjacent columns, each row read and written as one run.  At
+// M = 2048, 8 columns (64-byte runs, 135 KB of LDS, one block per CU) beat 4 columns (32-byte
+// runs, two blocks per CU): project 1.150 -> 1.128 ms, normal operator 1.517 -> 1.489 ms at
+// 2048^2 x 32; 2 columns had taken 510 us per pass against 410 us for 4.  Elsewhere 64 KB.
 template <int M>
 constexpr int cols_per_block() {
-  return M >= 8192 ? 1 : (M >= 4096 ? 2 : (M >= 2048 ? 4 : (8192 / M > 16 ? 16 : 8192 / M)));
+  return M >= 8192 ? 1 : (M >= 4096 ? 2 : (M >= 2048 ? 8 : (8192 / M > 16 ? 16 : 8192 / M)));
 }
 
 // The grid side G is t.N: M for power-of-two grids (BL = false), else the DFTs go through
