@@ -13,7 +13,8 @@ configuration (one batch of 32 slices = 16 complex channels).
   values below 1e-12) are far inside it.  A wrong
   tile, strip, bin or chunk boundary anywhere in the grid errs by O(|v| |x|) and fails it.
 * The composed operators on four sampled slices (two complex channels): relative L2 and the
-  largest element error against the largest reference element, both within 1e-5.
+  largest element error against the largest reference element, both within 1e-5; with bf16
+  values against the oracle's operators with the same rounded values, likewise.
 * CGLS (Sec. 3.1) in the benchmark's batch: its first iterates against the oracle's float64
   CGLS on the same float32 sinograms, in every slice position of the batch; likewise the first
   steps of the mixed-precision refinement (float32 residuals, bf16-value inner CGLS)."""
@@ -122,6 +123,31 @@ def test_fullsize_operators_sampled_slices(big, ref):
         err_bf16 = rel_l2(yb[s].cpu().numpy(), P)
         print(f"slice {s}: bf16-value projection error vs FP64 oracle {err_bf16:.3e}")
         assert err_bf16 < 4e-3
+
+
+def test_fullsize_bf16_operators_against_rounded_oracle(big, ref):
+    """project / backproject with bf16 values (the staged forward's channel-slowest output, the
+    staged adjoint and its dense-tile segments writing the FFT-side grid) against the oracle's
+    operators built from the same bf16-rounded matrix values: 16-bit values convert to float32
+    exactly, so the only differences are float32 arithmetic, held to the float32 operators'
+    1e-5 (relative L2 and largest element error against the largest reference element) on
+    slices at both ends of the batch."""
+    lo = OracleOperator(ref.geom, S=round_values(ref.S, "bf16"))
+    x = phantom_stack(N, B, seed_base=3300, supersample=1).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    y = big.project(xt, values="bf16")
+    xb = big.backproject(y, values="bf16")
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy().astype(np.float64)
+    xbh = xb.cpu().numpy().astype(np.float64)
+    for s in (0, 1, B - 1):
+        P = lo.project(x[s].astype(np.float64))
+        BP = lo.backproject(yh[s])
+        for got, want, what in ((yh[s], P, "project"), (xbh[s], BP, "backproject")):
+            l2 = rel_l2(got, want)
+            mx = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+            print(f"slice {s}: bf16 {what} rel L2 {l2:.2e} max {mx:.2e}")
+            assert l2 < 1e-5 and mx < 1e-5
 
 
 def test_fullsize_cgls_first_iterates(big, ref):
